@@ -1,0 +1,345 @@
+"""Pins of the FP64 CPU oracle against facts fixed outside the oracle itself:
+values the paper prints, library special cases (scipy z-score + cdist, the
+Pearson identity through numpy.corrcoef), a pure-Python rendering of the
+definition on tiny inputs, closed forms, invariants and metamorphic
+relations.  Each test names the slip it would catch."""
+
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+from scipy.spatial.distance import cdist
+from scipy.stats import zscore
+
+from oracle import cimpl
+from oracle import mp_oracle as O
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- paper sizes
+
+def test_paper_printed_sizes():
+    """Profile size n-m+1 and ez = ceil(frac*m) as printed by the paper
+    (an off-by-one in l or a round-half-even zone fails here)."""
+    with open(os.path.join(GOLDEN, "paper_sizes.json")) as f:
+        cases = json.load(f)["cases"]
+    for c in cases:
+        if c["n"] is not None:
+            assert O.profile_length(c["n"], c["m"]) == c["profile_size"], c["cite"]
+        assert O.exclusion_zone(c["m"], Fraction(c["frac"])) == c["ez"], c["cite"]
+
+
+# ------------------------------------------------------- definition, tiny cases
+
+def _pure_python_selfjoin(T, m, ez):
+    """The definition written with Python floats and loops only."""
+    n = len(T)
+    l = n - m + 1
+
+    def z(i):
+        w = [float(x) for x in T[i:i + m]]
+        mu = sum(w) / m
+        sd = math.sqrt(sum((x - mu) ** 2 for x in w) / m)
+        return [(x - mu) / sd for x in w]
+
+    Z = [z(i) for i in range(l)]
+    P, I = [], []
+    for i in range(l):
+        best, arg = math.inf, -1
+        for j in range(l):
+            if abs(i - j) <= ez:
+                continue
+            d = math.sqrt(sum((a - b) ** 2 for a, b in zip(Z[i], Z[j])))
+            if d < best:
+                best, arg = d, j
+        P.append(best)
+        I.append(arg)
+    return np.array(P), np.array(I)
+
+
+@pytest.mark.parametrize("seed,n,m,ez", [(0, 24, 3, 1), (1, 40, 8, 2), (2, 33, 2, 0), (3, 50, 8, 4)])
+def test_oracle_equals_pure_python(seed, n, m, ez):
+    T = np.random.default_rng(seed).standard_normal(n).cumsum()
+    P, I = O.selfjoin(T, m, ez)
+    P2, I2 = _pure_python_selfjoin(T, m, ez)
+    np.testing.assert_allclose(P, P2, rtol=0, atol=1e-12)
+    np.testing.assert_array_equal(I, I2)
+
+
+@pytest.mark.parametrize("seed,n,m", [(0, 64, 2), (1, 64, 3), (2, 60, 8), (3, 45, 8)])
+def test_distance_matrix_matches_scipy_and_corrcoef(seed, n, m):
+    """D from the oracle == cdist of scipy z-scores (ddof=0) == sqrt(2m(1-rho))
+    from numpy.corrcoef (a wrong std convention or dropped term fails)."""
+    T = np.random.default_rng(seed).standard_normal(n).cumsum()
+    W = np.lib.stride_tricks.sliding_window_view(T, m)
+    D = O.distance_matrix(T, m)
+    Zs = zscore(W, axis=1, ddof=0)
+    np.testing.assert_allclose(D, cdist(Zs, Zs), rtol=0, atol=1e-12)
+    rho = np.corrcoef(W)
+    Dp = np.sqrt(np.maximum(2 * m * (1 - rho), 0.0))
+    np.testing.assert_allclose(D, Dp, rtol=0, atol=1e-6)
+
+
+def test_selfjoin_is_rowmin_of_distance_matrix_with_zone():
+    T = np.random.default_rng(7).standard_normal(80).cumsum()
+    m, ez = 8, 2
+    D = O.distance_matrix(T, m)
+    l = D.shape[0]
+    ii, jj = np.meshgrid(np.arange(l), np.arange(l), indexing="ij")
+    D[np.abs(ii - jj) <= ez] = np.inf
+    P, I = O.selfjoin(T, m, ez)
+    np.testing.assert_allclose(P, D.min(axis=1), atol=1e-12)
+    np.testing.assert_array_equal(I, D.argmin(axis=1))
+
+
+def test_exclusion_zone_boundary_is_inclusive():
+    """|i-j| <= ez is excluded, |i-j| = ez+1 is admissible: an exact repeat
+    at distance p is found when ez = p-1 and skipped when ez = p."""
+    rng = np.random.default_rng(11)
+    m, p = 12, 5
+    base = rng.standard_normal(p)
+    T = np.concatenate([np.tile(base, 8), rng.standard_normal(60).cumsum() + 40])
+    P, I = O.selfjoin(T, m, p - 1)
+    assert P[0] < 1e-7 and I[0] == p
+    P, I = O.selfjoin(T, m, p)
+    assert P[0] < 1e-7 and I[0] == 2 * p
+
+
+# ------------------------------------------------------------------ closed forms
+
+def test_bounds_attained_population_std():
+    """d(w, -w) = 2 sqrt(m) exactly and d(w, a*w+b) = 0: only the
+    population-std z-normalisation gives both."""
+    rng = np.random.default_rng(3)
+    m = 16
+    w = rng.standard_normal(m)
+    T = np.concatenate([w, rng.standard_normal(10), -w, rng.standard_normal(10), 3 * w + 7])
+    j1, j2 = m + 10, 2 * m + 20
+    assert abs(O.pair_distance(T, 0, T, j1, m) - 2 * math.sqrt(m)) < 1e-12
+    assert O.pair_distance(T, 0, T, j2, m) < 1e-12
+
+
+def test_planted_copy_points_both_ways():
+    rng = np.random.default_rng(5)
+    m = 32
+    T = rng.standard_normal(600).cumsum()
+    T[400:400 + m] = 0.5 * T[100:100 + m] - 9.0
+    P, I = O.selfjoin(T, m, m // 4)
+    assert P[100] < 1e-7 and P[400] < 1e-7
+    assert I[100] == 400 and I[400] == 100
+
+
+def test_sine_integer_period_profile_is_zero():
+    p, m = 37, 20
+    t = np.arange(400)
+    T = np.sin(2 * np.pi * t / p)
+    P, I = O.selfjoin(T, m, m // 4)
+    assert np.max(P) < 1e-6
+    assert np.all(np.abs(np.abs(np.arange(len(P)) - I) % p) == 0)
+
+
+# --------------------------------------------------------------- invariants
+
+@pytest.mark.parametrize("seed", range(4))
+def test_selfjoin_invariants(seed):
+    rng = np.random.default_rng(seed)
+    n, m = 300, int(rng.integers(4, 40))
+    ez = m // 4
+    T = rng.standard_normal(n).cumsum()
+    P, I = O.selfjoin(T, m, ez)
+    l = n - m + 1
+    assert P.shape == (l,)
+    assert np.all(P >= 0) and np.all(P <= 2 * math.sqrt(m) + 1e-12)
+    assert np.all(np.abs(np.arange(l) - I) > ez)
+    assert np.all((I >= 0) & (I < l))
+    for i in range(0, l, 7):
+        assert abs(P[i] - O.pair_distance(T, i, T, I[i], m)) < 1e-12
+    assert np.all(P[I] <= P + 1e-12)
+
+
+def test_affine_invariance_and_reversal():
+    rng = np.random.default_rng(9)
+    m, ez = 16, 4
+    T = rng.standard_normal(250).cumsum()
+    P, I = O.selfjoin(T, m, ez)
+    P2, I2 = O.selfjoin(-0.37 * T + 1e6, m, ez)
+    np.testing.assert_allclose(P, P2, atol=1e-6)
+    Pr, _ = O.selfjoin(T[::-1].copy(), m, ez)
+    np.testing.assert_allclose(Pr[::-1], P, atol=1e-10)
+
+
+def test_abjoin_properties():
+    rng = np.random.default_rng(4)
+    m = 10
+    A = rng.standard_normal(120).cumsum()
+    B = rng.standard_normal(90).cumsum()
+    Pab, Iab, Pba, Iba = O.abjoin(A, B, m)
+    assert abs(Pab.min() - Pba.min()) < 1e-12
+    for i in range(0, Pab.size, 5):
+        assert abs(Pab[i] - O.pair_distance(A, i, B, Iab[i], m)) < 1e-12
+    for j in range(0, Pba.size, 5):
+        assert abs(Pba[j] - O.pair_distance(A, Iba[j], B, j, m)) < 1e-12
+    # joined with itself: every window finds itself at distance 0
+    Pss, Iss, _, _ = O.abjoin(A, A, m)
+    assert np.max(Pss) < 1e-7
+    np.testing.assert_array_equal(Iss, np.arange(Pss.size))
+
+
+# ------------------------------------------------------- degenerate windows
+
+def test_constant_windows():
+    """Reading: a constant window z-normalises to zero, so d(const, x) =
+    sqrt(m) and d(const, const) = 0."""
+    rng = np.random.default_rng(2)
+    m = 8
+    T = rng.standard_normal(200).cumsum()
+    T[50:50 + m] = 3.0
+    T[150:150 + m] = -1.0
+    assert O.pair_distance(T, 50, T, 150, m) == 0.0
+    assert abs(O.pair_distance(T, 50, T, 10, m) - math.sqrt(m)) < 1e-12
+    P, I = O.selfjoin(T, m, 2)
+    assert P[50] == 0.0 and I[50] == 150
+    assert P[150] == 0.0 and I[150] == 50
+    Pc, Ic = cimpl.selfjoin(T, m, 2)
+    np.testing.assert_allclose(Pc, P, atol=1e-12)
+    np.testing.assert_array_equal(Ic, I)
+
+
+def test_non_finite_windows_are_invalid():
+    rng = np.random.default_rng(6)
+    m, ez = 8, 2
+    T = rng.standard_normal(150).cumsum()
+    T[70] = np.nan
+    T[100] = np.inf
+    P, I = O.selfjoin(T, m, ez)
+    bad = np.zeros(P.size, bool)
+    for q in (70, 100):
+        bad[max(0, q - m + 1):q + 1] = True
+    assert np.all(np.isinf(P[bad])) and np.all(I[bad] == -1)
+    assert np.all(np.isfinite(P[~bad]))
+    assert not np.any(bad[I[~bad]])
+    Pc, Ic = cimpl.selfjoin(T, m, ez)
+    np.testing.assert_allclose(Pc, P, atol=1e-12)
+    np.testing.assert_array_equal(Ic, I)
+
+
+def test_no_admissible_neighbour():
+    T = np.random.default_rng(1).standard_normal(20)
+    P, I = O.selfjoin(T, 8, 20)
+    assert np.all(np.isinf(P)) and np.all(I == -1)
+
+
+# ------------------------------------------------------------ C vs numpy
+
+@pytest.mark.parametrize("seed,n,m,ez", [(0, 700, 32, 8), (1, 513, 17, 5), (2, 300, 2, 0)])
+def test_c_oracle_matches_numpy_oracle(seed, n, m, ez):
+    T = np.random.default_rng(seed).standard_normal(n).cumsum()
+    P, I = O.selfjoin(T, m, ez)
+    Pc, Ic = cimpl.selfjoin(T, m, ez)
+    np.testing.assert_allclose(Pc, P, rtol=0, atol=1e-12)
+    np.testing.assert_array_equal(Ic, I)
+    rows = np.array([0, 5, n - m, (n - m) // 2])
+    Pr, Ir = O.selfjoin_rows(T, m, ez, rows, chunk=97)
+    np.testing.assert_allclose(Pr, P[rows], atol=1e-12)
+    np.testing.assert_array_equal(Ir, I[rows])
+
+
+def test_c_abjoin_matches_numpy():
+    rng = np.random.default_rng(12)
+    A = rng.standard_normal(300).cumsum()
+    B = rng.standard_normal(260).cumsum()
+    m = 16
+    Pab, Iab, Pba, Iba = O.abjoin(A, B, m)
+    P1, I1 = cimpl.abjoin_rows(A, B, m, np.arange(Pab.size))
+    P2, I2 = cimpl.abjoin_rows(B, A, m, np.arange(Pba.size))
+    np.testing.assert_allclose(P1, Pab, atol=1e-12)
+    np.testing.assert_array_equal(I1, Iab)
+    np.testing.assert_allclose(P2, Pba, atol=1e-12)
+    np.testing.assert_array_equal(I2, Iba)
+
+
+# ------------------------------------------------------------- gradient
+
+def test_reference_gradient_matches_finite_differences():
+    rng = np.random.default_rng(21)
+    n, m, ez = 120, 12, 3
+    T = rng.standard_normal(n).cumsum()
+    P, I = O.selfjoin(T, m, ez)
+    g = O.reference_gradient(T, m, I, np.ones_like(P))
+    h = 1e-6
+    for t in rng.choice(n, 25, replace=False):
+        Tp, Tm = T.copy(), T.copy()
+        Tp[t] += h
+        Tm[t] -= h
+        fd = (O.profile_sum_loss(Tp, m, I) - O.profile_sum_loss(Tm, m, I)) / (2 * h)
+        assert abs(fd - g[t]) <= 1e-5 * max(1.0, abs(fd)), (t, fd, g[t])
+
+
+def test_reference_gradient_invariants():
+    """L is invariant to T -> aT + b, so sum(g) = 0 and T.g = 0."""
+    rng = np.random.default_rng(22)
+    n, m = 200, 16
+    T = rng.standard_normal(n).cumsum()
+    P, I = O.selfjoin(T, m, 4)
+    gP = rng.uniform(0.5, 1.5, P.size)
+    g = O.reference_gradient(T, m, I, gP)
+    scale = np.abs(g).sum()
+    assert abs(g.sum()) < 1e-12 * scale
+    assert abs((T * g).sum()) < 1e-10 * scale * np.abs(T).max()
+
+
+def test_gradient_fd_through_the_argmin():
+    """Central differences of sum(P) with the argmin recomputed agree with
+    the fixed-index gradient wherever the index does not flip."""
+    rng = np.random.default_rng(23)
+    n, m, ez = 90, 10, 2
+    T = rng.standard_normal(n).cumsum()
+    P, I = O.selfjoin(T, m, ez)
+    g = O.reference_gradient(T, m, I, np.ones_like(P))
+    h, checked = 1e-5, 0
+    for t in rng.permutation(n):
+        Tp, Tm = T.copy(), T.copy()
+        Tp[t] += h
+        Tm[t] -= h
+        Pp, Ip = O.selfjoin(Tp, m, ez)
+        Pm, Im = O.selfjoin(Tm, m, ez)
+        if not (np.array_equal(Ip, I) and np.array_equal(Im, I)):
+            continue
+        fd = (Pp.sum() - Pm.sum()) / (2 * h)
+        assert abs(fd - g[t]) <= 1e-4 * max(1.0, abs(fd))
+        checked += 1
+        if checked == 12:
+            break
+    assert checked >= 6
+
+
+# ------------------------------------------------------------- motifs
+
+def test_top_motifs_recover_planted_pairs():
+    """Planted noisy pairs are the top motifs (a member may shift by a few
+    samples: a window sliding one step keeps most of the copy)."""
+    from workloads import planted_walk
+    for seed in (123, 77):
+        pw = planted_walk(6000, 64, seed=seed, n_motifs=3, n_discords=2, dtype=np.float64)
+        P, I = cimpl.selfjoin(pw.T, pw.m, pw.m // 4)
+        found = [tuple(sorted(p)) for p in O.top_motifs(P, I, pw.m, 3)]
+        for a, b in pw.motif_pairs:
+            assert any(abs(a - x) <= pw.m // 8 and abs(b - y) <= pw.m // 8 for x, y in found)
+
+
+def test_top_discord_on_corrupted_sine():
+    """A sine with one cycle replaced by noise: the top discord overlaps the
+    corruption, and the motif pairs lie a whole number of periods apart."""
+    p, m = 50, 40
+    t = np.arange(3000)
+    T = np.sin(2 * np.pi * t / p)
+    T[1500:1550] = np.random.default_rng(0).standard_normal(50)
+    P, I = O.selfjoin(T, m, m // 4)
+    d = O.top_discords(P, m, 1)[0]
+    assert 1500 - m < d < 1550
+    for i, j in O.top_motifs(P, I, m, 3):
+        assert abs(i - j) % p == 0
