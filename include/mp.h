@@ -1,0 +1,187 @@
+/*
+ * mp.h -- C ABI of the MI355X matrix-profile similarity-join library
+ * (libmpx.so, HIP kernels for gfx950).
+ *
+ * The operation (tsmp paper, arXiv 1904.12626):
+ *   Section 2  -- the matrix profile P of a sliding-window join is, for every
+ *                 length-m window, the Euclidean distance to its nearest
+ *                 neighbour; the profile index I holds that neighbour's
+ *                 position (the row minimum of the distance matrix,
+ *                 excluding trivial matches).
+ *   Section 3.3.4 -- windows are z-normalised (SiMPle is the one mode that
+ *                 is not).
+ *   Section 3.2 -- one series gives a self-join, two give an AB-join; the
+ *                 exclusion zone suppresses trivial matches in self-joins.
+ *   Section 3.3.2 -- the dot products of one row are reused for the next
+ *                 (STOMP), so every cell costs O(1); Section 3.3.3 (SCRIMP)
+ *                 processes the distance matrix in an order independent of
+ *                 rows; Section 3.2 states that these orders give equal
+ *                 results.
+ *
+ * Conventions shared by every entry point
+ *   - Windows: T_i = T[i .. i+m-1], i = 0 .. l-1 with l = n - m + 1.
+ *   - z-normalisation uses the population standard deviation; a window whose
+ *     m values are all equal normalises to the zero vector (so its distance to
+ *     any other valid window is sqrt(m), and 0 to another constant window).
+ *   - A window holding a NaN or +-Inf is invalid: its P is +inf, its I is -1,
+ *     and it is never chosen as a neighbour.  A row with no admissible
+ *     neighbour also gets (+inf, -1).  These are results, not errors.
+ *   - P holds distances (not squared distances); I is 0-based and local to
+ *     its series; ties go to the smallest index up to the key resolution of
+ *     the chosen precision.
+ *   - Self-join: pairs with |i - j| <= ez are excluded.  AB-join: no zone.
+ *
+ * Memory and streams
+ *   - Every array argument (T, P, I, gP, gT, workspace, offsets passed to
+ *     mp_batch) is DEVICE memory owned by the caller, except where a comment
+ *     says "host".  The library never allocates device memory, never frees,
+ *     and never synchronises: all work is enqueued on `stream` (a
+ *     hipStream_t; NULL = the legacy default stream) and the call returns at
+ *     once.  Results are valid once the stream reaches that point.
+ *   - The workspace must be at least the size the matching *_workspace
+ *     query returns and 256-byte aligned; its contents on entry do not matter
+ *     and on exit are scratch.  Two calls that share a workspace must be
+ *     ordered on one stream.
+ *   - Every call except mp_batch_plan_upload enqueues kernels only (no
+ *     memset, no copies), so it may be captured into a HIP graph.
+ *
+ * Errors
+ *   - Argument checks run on the host before anything is enqueued; a
+ *     failing check returns MP_EINVAL / MP_EWORKSPACE / MP_EUNSUPPORTED and
+ *     enqueues nothing.  A failed kernel launch returns MP_ELAUNCH.  No
+ *     function throws across the ABI.
+ */
+#ifndef MPX_MP_H
+#define MPX_MP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MP_ABI_VERSION 1
+
+typedef enum {
+  MP_OK = 0,
+  MP_EINVAL = -1,        /* bad size, pointer, alignment or option      */
+  MP_EWORKSPACE = -2,    /* workspace null, misaligned or too small     */
+  MP_ELAUNCH = -3,       /* a kernel launch failed                      */
+  MP_EUNSUPPORTED = -4   /* valid request this build does not support   */
+} mp_status;
+
+typedef enum {
+  MP_F64 = 0,            /* T (and gP, gT) are double; P is double      */
+  MP_F32 = 1             /* T (and gP, gT) are float;  P is float       */
+} mp_dtype;
+
+/* precision of the diagonal sweep */
+#define MP_PREC_F64 0    /* FP64 sweep (the reference GPU path)          */
+#define MP_PREC_F32 1    /* FP32 sweep, FP64 stats/seeds, reseeded       */
+
+/* flags */
+#define MP_FLAG_FP64_FINALIZE 1u  /* recompute P[i] = dist(i, I[i]) in FP64 */
+
+typedef struct {
+  int32_t precision;     /* MP_PREC_F64 or MP_PREC_F32                        */
+  int32_t reseed_rows;   /* rows per tile = reseed interval; 0 = automatic   */
+  int32_t tile_slots;    /* diagonals per lane (8 or 16; F64 supports 8);
+                            0 = automatic                                   */
+  int32_t flags;         /* MP_FLAG_*                                        */
+} mp_options;
+
+/* ---------------------------------------------------------------- self-join
+ * Section 2 / 3.2: P[i] = min over |i-j| > ez of d(i, j), I[i] = argmin.
+ *   T      device, n values of `dtype`
+ *   m      window, 2 <= m <= n;  ez >= 0
+ *   P      device, l = n-m+1 values of `dtype`;  I  device, l int64
+ *   opt    host pointer, may be NULL (= all defaults: FP32 sweep, automatic
+ *          tiling, FP64 finalize on)
+ */
+size_t mp_selfjoin_workspace(int64_t n, int32_t m, mp_dtype dtype, const mp_options *opt);
+mp_status mp_selfjoin(const void *T, int64_t n, int32_t m, int32_t ez, mp_dtype dtype,
+                      const mp_options *opt, void *P, int64_t *I, void *ws, size_t ws_bytes,
+                      void *stream);
+
+/* ----------------------------------------------------------------- AB-join
+ * Section 3.2: two series.  P_ab[i] = min_j d(A_i, B_j) (index into B),
+ * P_ba[j] = min_i d(A_i, B_j) (index into A).  No exclusion zone.
+ *   A, B   device, nA / nB values;  P_ab, I_ab length nA-m+1;  P_ba, I_ba
+ *   length nB-m+1.
+ */
+size_t mp_abjoin_workspace(int64_t nA, int64_t nB, int32_t m, mp_dtype dtype, const mp_options *opt);
+mp_status mp_abjoin(const void *A, int64_t nA, const void *B, int64_t nB, int32_t m,
+                    mp_dtype dtype, const mp_options *opt, void *P_ab, int64_t *I_ab,
+                    void *P_ba, int64_t *I_ba, void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------ batched joins
+ * Many self-joins of uneven lengths and windows in one launch sequence.
+ * Series s occupies T_cat[t_off[s] .. t_off[s+1]-1]; its profile occupies
+ * P_cat/I_cat[p_off[s] .. p_off[s] + l_s - 1] with p_off[s] = sum of l over
+ * the series before it.  The plan is a host object built once from host
+ * copies of the offsets, windows and zones; mp_batch_plan_upload writes its
+ * device tables into the workspace (hipMemcpyAsync; call it before any
+ * stream capture and keep the plan alive until that copy has completed);
+ * mp_batch then only enqueues kernels and may be captured and replayed.
+ */
+typedef struct mp_batch_plan mp_batch_plan;
+mp_status mp_batch_plan_create(int32_t nseries, const int64_t *t_off_host /* [nseries+1] */,
+                               const int32_t *m_host /* [nseries] */,
+                               const int32_t *ez_host /* [nseries] */, mp_dtype dtype,
+                               const mp_options *opt, mp_batch_plan **out);
+size_t mp_batch_plan_workspace(const mp_batch_plan *plan);
+int64_t mp_batch_plan_profile_length(const mp_batch_plan *plan);  /* sum of l_s */
+int64_t mp_batch_plan_cells(const mp_batch_plan *plan);           /* admissible pairs */
+mp_status mp_batch_plan_upload(const mp_batch_plan *plan, void *ws, size_t ws_bytes, void *stream);
+mp_status mp_batch(const mp_batch_plan *plan, const void *T_cat, void *P_cat, int64_t *I_cat,
+                   void *ws, size_t ws_bytes, void *stream);
+void mp_batch_plan_destroy(mp_batch_plan *plan);
+
+/* ---------------------------------------------------------------- backward
+ * Gradient of a loss L(P) with respect to T through the z-normalised
+ * distance of each row's argmin pair, holding I fixed (not in the paper; the
+ * derivative of d(i, j) = ||z_i - z_j|| through z = (x - mean)/sigma):
+ *   dd/dT[i:i+m] = (rho z_i - z_j) / (sigma_i d),
+ *   dd/dT[j:j+m] = (rho z_j - z_i) / (sigma_j d),   rho = z_i.z_j / m.
+ * Rows with I < 0, d == 0 or a constant window contribute nothing.
+ * Uses the batch plan's layout: T_cat / I_cat / gP_cat as for mp_batch,
+ * gT_cat (n values per series, `dtype`) is overwritten.  The workspace is
+ * the plan's workspace.
+ */
+mp_status mp_backward(const mp_batch_plan *plan, const void *T_cat, const int64_t *I_cat,
+                      const void *gP_cat, void *gT_cat, void *ws, size_t ws_bytes,
+                      void *stream);
+
+/* ----------------------------------------------------------- FP64 recheck
+ * Section 2: the lowest points of P are the best motif pair, the highest
+ * point is the discord.  Extracts k_motifs motif pairs (repeatedly the
+ * smallest finite P[i] with its pair (i, I[i]), then every index within m of
+ * either member is masked) and k_discords discords (repeatedly the largest
+ * finite P, masking within m), and recomputes their distances in FP64 from
+ * T.  One workgroup; meant for small k (<= 64 each).
+ *   T        device, n values of `dtype`; P, I device, l values (a profile
+ *            this library produced for T with window m)
+ *   out_idx  device int64[2*k_motifs + k_discords]: motif pairs (i, j) first,
+ *            then discord positions; -1 where fewer exist
+ *   out_dist device double[k_motifs + k_discords]: FP64 distance of each
+ *            motif pair, then of each discord to its neighbour I; +inf where
+ *            fewer exist
+ *   ws       device scratch of mp_recheck_workspace(n, m) bytes
+ */
+size_t mp_recheck_workspace(int64_t n, int32_t m);
+mp_status mp_recheck(const void *T, int64_t n, int32_t m, mp_dtype dtype, const void *P,
+                     const int64_t *I, int32_t k_motifs, int32_t k_discords, int64_t *out_idx,
+                     double *out_dist, void *ws, size_t ws_bytes, void *stream);
+
+/* --------------------------------------------------------------- helpers */
+const char *mp_strerror(mp_status status);
+int mp_abi_version(void);
+/* Cells (admissible pairs) of a self-join / AB-join, for throughput metrics. */
+int64_t mp_selfjoin_cells(int64_t n, int32_t m, int32_t ez);
+int64_t mp_abjoin_cells(int64_t nA, int64_t nB, int32_t m);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MPX_MP_H */

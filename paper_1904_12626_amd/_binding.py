@@ -1,0 +1,291 @@
+"""ctypes binding of libmpx.so (include/mp.h).
+
+Argument marshalling only: every step of the join runs in the library's HIP
+kernels.  torch supplies device memory (outputs and workspace) and the
+current stream.  The binding refuses to run when the library is missing.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from fractions import Fraction
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmpx.so")
+
+MP_OK, MP_EINVAL, MP_EWORKSPACE, MP_ELAUNCH, MP_EUNSUPPORTED = 0, -1, -2, -3, -4
+MP_F64, MP_F32 = 0, 1
+MP_PREC_F64, MP_PREC_F32 = 0, 1
+MP_FLAG_FP64_FINALIZE = 1
+
+# every symbol include/mp.h declares
+EXPORTS = (
+    "mp_selfjoin_workspace", "mp_selfjoin", "mp_abjoin_workspace", "mp_abjoin",
+    "mp_batch_plan_create", "mp_batch_plan_workspace", "mp_batch_plan_profile_length",
+    "mp_batch_plan_cells", "mp_batch_plan_upload", "mp_batch", "mp_batch_plan_destroy",
+    "mp_backward", "mp_recheck_workspace", "mp_recheck", "mp_strerror", "mp_abi_version",
+    "mp_selfjoin_cells", "mp_abjoin_cells",
+)
+
+
+class MPError(RuntimeError):
+    def __init__(self, where: str, status: int, msg: str):
+        super().__init__(f"{where}: {msg} (status {status})")
+        self.status = status
+
+
+class mp_options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("reseed_rows", ctypes.c_int32),
+                ("tile_slots", ctypes.c_int32), ("flags", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libmpx.so; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'` "
+            "(hipcc, gfx950); there is no fallback implementation")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_size_t
+    op = ctypes.POINTER(mp_options)
+    sig = {
+        "mp_selfjoin_workspace": (sz, [i64, i32, i32, op]),
+        "mp_selfjoin": (ctypes.c_int, [vp, i64, i32, i32, i32, op, vp, vp, vp, sz, vp]),
+        "mp_abjoin_workspace": (sz, [i64, i64, i32, i32, op]),
+        "mp_abjoin": (ctypes.c_int, [vp, i64, vp, i64, i32, i32, op, vp, vp, vp, vp, vp, sz, vp]),
+        "mp_batch_plan_create": (ctypes.c_int, [i32, vp, vp, vp, i32, op, ctypes.POINTER(vp)]),
+        "mp_batch_plan_workspace": (sz, [vp]),
+        "mp_batch_plan_profile_length": (i64, [vp]),
+        "mp_batch_plan_cells": (i64, [vp]),
+        "mp_batch_plan_upload": (ctypes.c_int, [vp, vp, sz, vp]),
+        "mp_batch": (ctypes.c_int, [vp, vp, vp, vp, vp, sz, vp]),
+        "mp_batch_plan_destroy": (None, [vp]),
+        "mp_backward": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, sz, vp]),
+        "mp_recheck_workspace": (sz, [i64, i32]),
+        "mp_recheck": (ctypes.c_int, [vp, i64, i32, i32, vp, vp, i32, i32, vp, vp, vp, sz, vp]),
+        "mp_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+        "mp_abi_version": (ctypes.c_int, []),
+        "mp_selfjoin_cells": (i64, [i64, i32, i32]),
+        "mp_abjoin_cells": (i64, [i64, i64, i32]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(where: str, status: int):
+    if status != MP_OK:
+        raise MPError(where, status, lib().mp_strerror(status).decode())
+
+
+def exclusion_zone(m: int, frac=Fraction(1, 2)) -> int:
+    """ez = ceil(frac * m) (the tsmp exclusion_zone argument is a fraction of
+    the window; default 1/2)."""
+    f = Fraction(frac).limit_denominator(1 << 20) if isinstance(frac, float) else Fraction(frac)
+    v = f * int(m)
+    return int(math.ceil(v))
+
+
+def make_options(precision: str = "f32", reseed_rows: int = 0, tile_slots: int = 0,
+                 fp64_finalize: bool = True) -> mp_options:
+    if precision not in ("f32", "f64"):
+        raise ValueError("precision must be 'f32' or 'f64'")
+    return mp_options(MP_PREC_F32 if precision == "f32" else MP_PREC_F64, int(reseed_rows),
+                      int(tile_slots), MP_FLAG_FP64_FINALIZE if fp64_finalize else 0)
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.float64:
+        return MP_F64
+    if t.dtype == torch.float32:
+        return MP_F32
+    raise TypeError(f"series must be float32 or float64, got {t.dtype}")
+
+
+def _series(t: torch.Tensor, name: str) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dim() != 1:
+        raise ValueError(f"{name} must be 1-D")
+    return t.contiguous()
+
+
+def _stream(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t: torch.Tensor):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def selfjoin(T: torch.Tensor, m: int, ez: int | None = None, *, exclusion_zone_frac=Fraction(1, 2),
+             precision: str = "f32", reseed_rows: int = 0, tile_slots: int = 0,
+             fp64_finalize: bool = True, stream=None, workspace: torch.Tensor | None = None):
+    """Self-join matrix profile of a 1-D series: returns (P, I) on T's device.
+
+    ez defaults to ceil(exclusion_zone_frac * m).  P has T's dtype, I is int64;
+    invalid rows are (+inf, -1).  Enqueued on `stream` (default: current)."""
+    T = _series(T, "T")
+    L = lib()
+    n = T.numel()
+    if ez is None:
+        ez = exclusion_zone(m, exclusion_zone_frac)
+    dt = _dtype_code(T)
+    opt = make_options(precision, reseed_rows, tile_slots, fp64_finalize)
+    ws_bytes = L.mp_selfjoin_workspace(n, m, dt, ctypes.byref(opt))
+    if ws_bytes == 0:
+        _check("mp_selfjoin", MP_EINVAL if (m < 2 or n < m) else MP_EUNSUPPORTED)
+    l = n - m + 1
+    P = torch.empty(l, dtype=T.dtype, device=T.device)
+    I = torch.empty(l, dtype=torch.int64, device=T.device)
+    ws = workspace if workspace is not None else torch.empty(ws_bytes, dtype=torch.uint8, device=T.device)
+    _check("mp_selfjoin", L.mp_selfjoin(_ptr(T), n, m, int(ez), dt, ctypes.byref(opt), _ptr(P), _ptr(I),
+                                        _ptr(ws), ws.numel(), _stream(stream)))
+    return P, I
+
+
+def abjoin(A: torch.Tensor, B: torch.Tensor, m: int, *, precision: str = "f32", reseed_rows: int = 0,
+           tile_slots: int = 0, fp64_finalize: bool = True, stream=None):
+    """AB-join: returns (P_ab, I_ab, P_ba, I_ba); I_ab indexes B, I_ba indexes A."""
+    A = _series(A, "A")
+    B = _series(B, "B")
+    if A.dtype != B.dtype or A.device != B.device:
+        raise ValueError("A and B must share dtype and device")
+    L = lib()
+    dt = _dtype_code(A)
+    opt = make_options(precision, reseed_rows, tile_slots, fp64_finalize)
+    nA, nB = A.numel(), B.numel()
+    ws_bytes = L.mp_abjoin_workspace(nA, nB, m, dt, ctypes.byref(opt))
+    if ws_bytes == 0:
+        _check("mp_abjoin", MP_EINVAL)
+    lA, lB = nA - m + 1, nB - m + 1
+    Pab = torch.empty(lA, dtype=A.dtype, device=A.device)
+    Iab = torch.empty(lA, dtype=torch.int64, device=A.device)
+    Pba = torch.empty(lB, dtype=A.dtype, device=A.device)
+    Iba = torch.empty(lB, dtype=torch.int64, device=A.device)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=A.device)
+    _check("mp_abjoin", L.mp_abjoin(_ptr(A), nA, _ptr(B), nB, m, dt, ctypes.byref(opt), _ptr(Pab), _ptr(Iab),
+                                    _ptr(Pba), _ptr(Iba), _ptr(ws), ws.numel(), _stream(stream)))
+    return Pab, Iab, Pba, Iba
+
+
+class BatchPlan:
+    """Host plan of many self-joins of uneven lengths and windows
+    (mp_batch_plan_*).  `run` enqueues only kernels and may be captured into
+    a CUDA/HIP graph once `upload` has completed."""
+
+    def __init__(self, lengths, windows, zones, dtype=torch.float32, device="cuda", *,
+                 precision: str = "f32", reseed_rows: int = 0, tile_slots: int = 0,
+                 fp64_finalize: bool = True):
+        L = lib()
+        self.lengths = [int(x) for x in lengths]
+        self.windows = [int(x) for x in windows]
+        self.zones = [int(x) for x in zones]
+        ns = len(self.lengths)
+        if not (ns == len(self.windows) == len(self.zones)) or ns == 0:
+            raise ValueError("lengths, windows and zones must be non-empty and of equal length")
+        self.dtype = dtype
+        self.device = torch.device(device)
+        dt = MP_F64 if dtype == torch.float64 else MP_F32
+        off = (ctypes.c_int64 * (ns + 1))()
+        acc = 0
+        for i, n in enumerate(self.lengths):
+            off[i] = acc
+            acc += n
+        off[ns] = acc
+        self.total_n = acc
+        mm = (ctypes.c_int32 * ns)(*self.windows)
+        ee = (ctypes.c_int32 * ns)(*self.zones)
+        self._opt = make_options(precision, reseed_rows, tile_slots, fp64_finalize)
+        h = ctypes.c_void_p()
+        _check("mp_batch_plan_create", L.mp_batch_plan_create(ns, off, mm, ee, dt, ctypes.byref(self._opt),
+                                                              ctypes.byref(h)))
+        self._h = h
+        self.t_off = [off[i] for i in range(ns + 1)]
+        self.profile_length = int(L.mp_batch_plan_profile_length(h))
+        self.cells = int(L.mp_batch_plan_cells(h))
+        self.ws_bytes = int(L.mp_batch_plan_workspace(h))
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        self.p_off = []
+        acc = 0
+        for n, m in zip(self.lengths, self.windows):
+            self.p_off.append(acc)
+            acc += n - m + 1
+        self.p_off.append(acc)
+        self.upload()
+
+    def upload(self, stream=None):
+        _check("mp_batch_plan_upload", lib().mp_batch_plan_upload(self._h, _ptr(self.workspace), self.ws_bytes,
+                                                                   _stream(stream)))
+        (stream or torch.cuda.current_stream()).synchronize()
+
+    def run(self, T_cat: torch.Tensor, P_cat=None, I_cat=None, stream=None):
+        T_cat = _series(T_cat, "T_cat")
+        if T_cat.numel() != self.total_n or T_cat.dtype != self.dtype:
+            raise ValueError("T_cat does not match the plan")
+        if P_cat is None:
+            P_cat = torch.empty(self.profile_length, dtype=self.dtype, device=T_cat.device)
+        if I_cat is None:
+            I_cat = torch.empty(self.profile_length, dtype=torch.int64, device=T_cat.device)
+        _check("mp_batch", lib().mp_batch(self._h, _ptr(T_cat), _ptr(P_cat), _ptr(I_cat), _ptr(self.workspace),
+                                          self.ws_bytes, _stream(stream)))
+        return P_cat, I_cat
+
+    def backward(self, T_cat, I_cat, gP_cat, gT_cat=None, stream=None):
+        T_cat = _series(T_cat, "T_cat")
+        gP_cat = gP_cat.contiguous().to(self.dtype)
+        if gT_cat is None:
+            gT_cat = torch.empty_like(T_cat)
+        _check("mp_backward", lib().mp_backward(self._h, _ptr(T_cat), _ptr(I_cat.contiguous()), _ptr(gP_cat),
+                                                _ptr(gT_cat), _ptr(self.workspace), self.ws_bytes,
+                                                _stream(stream)))
+        return gT_cat
+
+    def split(self, X_cat):
+        return [X_cat[self.p_off[i]:self.p_off[i + 1]] for i in range(len(self.lengths))]
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.mp_batch_plan_destroy(h)
+            self._h = None
+
+
+def recheck(T: torch.Tensor, m: int, P: torch.Tensor, I: torch.Tensor, k_motifs: int, k_discords: int,
+            stream=None):
+    """FP64 recheck of the best motif pairs and discords of a profile.
+    Returns (idx int64[2*k_motifs + k_discords], dist float64[k_motifs + k_discords])."""
+    T = _series(T, "T")
+    L = lib()
+    dt = _dtype_code(T)
+    n = T.numel()
+    out_idx = torch.empty(2 * k_motifs + k_discords, dtype=torch.int64, device=T.device)
+    out_dist = torch.empty(k_motifs + k_discords, dtype=torch.float64, device=T.device)
+    ws_bytes = L.mp_recheck_workspace(n, m)
+    ws = torch.empty(max(ws_bytes, 256), dtype=torch.uint8, device=T.device)
+    _check("mp_recheck", L.mp_recheck(_ptr(T), n, m, dt, _ptr(P.contiguous()), _ptr(I.contiguous()),
+                                      k_motifs, k_discords, _ptr(out_idx), _ptr(out_dist), _ptr(ws),
+                                      ws.numel(), _stream(stream)))
+    return out_idx, out_dist
+
+
+def selfjoin_cells(n: int, m: int, ez: int) -> int:
+    return int(lib().mp_selfjoin_cells(n, m, ez))
+
+
+def abjoin_cells(nA: int, nB: int, m: int) -> int:
+    return int(lib().mp_abjoin_cells(nA, nB, m))

@@ -1,0 +1,45 @@
+"""Differentiable matrix profile: torch.autograd.Function over the batched
+self-join (forward) and the library's backward kernel (dL/dT through each
+row's argmin pair, index held fixed)."""
+
+from __future__ import annotations
+
+import torch
+
+from ._binding import BatchPlan
+
+
+class MatrixProfileFn(torch.autograd.Function):
+    """P, I = MatrixProfileFn.apply(T, plan) for T of shape [B, n] (equal
+    lengths) or the concatenated 1-D layout of `plan`.  P is differentiable;
+    I is marked non-differentiable."""
+
+    @staticmethod
+    def forward(ctx, T, plan: BatchPlan):
+        Tc = T.reshape(-1).contiguous()
+        P, I = plan.run(Tc)
+        ctx.plan = plan
+        ctx.shape = T.shape
+        ctx.save_for_backward(Tc, I)
+        ctx.mark_non_differentiable(I)
+        if T.dim() == 2:
+            B = T.shape[0]
+            return P.view(B, -1), I.view(B, -1)
+        return P, I
+
+    @staticmethod
+    def backward(ctx, gP, gI):
+        Tc, I = ctx.saved_tensors
+        gP = torch.nan_to_num(gP.reshape(-1), nan=0.0, posinf=0.0, neginf=0.0)
+        gT = ctx.plan.backward(Tc, I, gP)
+        return gT.view(ctx.shape), None
+
+
+def matrix_profile(T: torch.Tensor, m: int, ez: int, plan: BatchPlan | None = None, **plan_kw):
+    """Differentiable profile of a [B, n] batch of equal-length series."""
+    if T.dim() != 2:
+        raise ValueError("T must be [B, n]")
+    B, n = T.shape
+    if plan is None:
+        plan = BatchPlan([n] * B, [m] * B, [ez] * B, dtype=T.dtype, device=T.device, **plan_kw)
+    return MatrixProfileFn.apply(T, plan)

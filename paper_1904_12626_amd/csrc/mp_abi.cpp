@@ -1,0 +1,488 @@
+// Host side of the C ABI declared in include/mp.h: argument checks, the
+// workspace layout, tiling choices and the launch sequence
+//   plan (tile table) -> stats -> sweep -> special tables -> finalize -> rescan.
+// Nothing here allocates device memory or synchronises.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/mp.h"
+#include "mp_internal.h"
+
+using mpx::SeriesDesc;
+using mpx::SweepDesc;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+struct Options {
+  bool f64 = false;      // FP64 sweep
+  int slots = 8;         // diagonals per lane
+  int reseed = 0;        // 0 = automatic
+  bool fp64_finalize = true;
+};
+
+mp_status parse_options(const mp_options *opt, Options &o) {
+  o = Options();
+  if (!opt) return MP_OK;
+  if (opt->precision != MP_PREC_F64 && opt->precision != MP_PREC_F32) return MP_EINVAL;
+  o.f64 = opt->precision == MP_PREC_F64;
+  if (opt->tile_slots != 0 && opt->tile_slots != 8 && opt->tile_slots != 16) return MP_EINVAL;
+  if (o.f64 && opt->tile_slots == 16) return MP_EUNSUPPORTED;
+  o.slots = opt->tile_slots ? opt->tile_slots : 8;
+  if (opt->reseed_rows < 0) return MP_EINVAL;
+  if (opt->reseed_rows != 0 && (opt->reseed_rows % 64 != 0 || opt->reseed_rows > (1 << 20)))
+    return MP_EINVAL;
+  o.reseed = opt->reseed_rows;
+  if (opt->flags & ~MP_FLAG_FP64_FINALIZE) return MP_EINVAL;
+  o.fp64_finalize = (opt->flags & MP_FLAG_FP64_FINALIZE) != 0;
+  return MP_OK;
+}
+
+int bits_for(int64_t l) {
+  int b = 1;
+  while (((int64_t)1 << b) < l) ++b;
+  return b;
+}
+
+// Host mirror of a job: series and sweeps, sizes, and the tile count.
+struct Job {
+  std::vector<SeriesDesc> series;
+  std::vector<SweepDesc> sweeps;
+  int64_t total_l = 0, total_rc = 0, total_x = 0, total_n = 0, nseg = 0, tiles = 0, cells = 0;
+  int W = 512, R = 4096;
+  Options opt;
+  bool t_f64 = false;
+};
+
+void add_series(Job &j, int64_t t_off, int64_t n, int32_t m, int32_t ez, int partner, int out) {
+  SeriesDesc s{};
+  s.t_off = t_off;
+  s.n = n;
+  s.l = n - m + 1;
+  s.w_off = j.total_l;
+  s.rc_off = j.total_rc;
+  s.x_off = j.total_x;
+  s.m = m;
+  s.ez = ez;
+  s.partner = partner;
+  s.out = out;
+  j.total_l += s.l;
+  j.total_rc += s.l + mpx::kRcPad;
+  j.total_x += s.l + 1;
+  j.total_n += n;
+  j.series.push_back(s);
+}
+
+void add_sweep(Job &j, int rs, int cs, int rk, int ck, int64_t k_lo, int64_t k_hi) {
+  SweepDesc d{};
+  d.rs = rs;
+  d.cs = cs;
+  d.rk = rk;
+  d.ck = ck;
+  d.k_lo = k_lo;
+  d.k_hi = k_hi;
+  d.idx_bits = bits_for(std::max(j.series[rk].l, j.series[ck].l));
+  d.nseg = 0;
+  j.sweeps.push_back(d);
+}
+
+int64_t count_tiles(const Job &j, int W, int R) {
+  int64_t t = 0;
+  for (const SweepDesc &d : j.sweeps) {
+    const SeriesDesc &rs = j.series[d.rs], &cs = j.series[d.cs];
+    if (d.k_lo > d.k_hi) continue;
+    for (int64_t k0 = d.k_lo; k0 <= d.k_hi; k0 += W) {
+      const int64_t L = std::min(rs.l, cs.l - k0);
+      t += (L + R - 1) / R;
+    }
+  }
+  return t;
+}
+
+// Cells of one sweep: sum over diagonals k of min(l_r, l_c - k).
+int64_t sweep_cells(int64_t lr, int64_t lc, int64_t k_lo, int64_t k_hi) {
+  if (k_lo > k_hi) return 0;
+  int64_t c = 0;
+  // split at k where l_c - k == l_r
+  const int64_t kb = lc - lr;  // for k <= kb the diagonal has l_r cells
+  const int64_t a_hi = std::min(k_hi, kb);
+  if (a_hi >= k_lo) c += (a_hi - k_lo + 1) * lr;
+  const int64_t b_lo = std::max(k_lo, kb + 1);
+  if (b_lo <= k_hi) {
+    // sum_{k=b_lo}^{k_hi} (lc - k)
+    const int64_t n = k_hi - b_lo + 1;
+    c += n * lc - (b_lo + k_hi) * n / 2;
+  }
+  return c;
+}
+
+// Tiling: W = 64 * slots diagonals per strip, R rows per tile (also the
+// reseed interval).  Automatic R starts at 4096 and halves (down to 64)
+// while the job has fewer than ~8 tiles per SIMD.
+void finish_job(Job &j) {
+  j.W = 64 * j.opt.slots;
+  int R = j.opt.reseed ? j.opt.reseed : 4096;
+  if (!j.opt.reseed) {
+    while (R > 64 && count_tiles(j, j.W, R) < 8 * 1024) R /= 2;
+  }
+  j.R = R;
+  int64_t seg = 0;
+  j.cells = 0;
+  for (SweepDesc &d : j.sweeps) {
+    d.seg_base = seg;
+    d.nseg = (d.k_lo > d.k_hi) ? 0 : (d.k_hi - d.k_lo + j.W) / j.W;
+    seg += d.nseg;
+    j.cells += sweep_cells(j.series[d.rs].l, j.series[d.cs].l, d.k_lo, d.k_hi);
+  }
+  j.nseg = seg;
+  j.tiles = count_tiles(j, j.W, j.R);
+}
+
+struct Layout {
+  size_t mu, sig, keys, flags, nc, nv, rc, special, counters, segp, segs, rescan, grad, sdesc,
+      wdesc, total;
+};
+
+Layout layout_of(const Job &j, bool with_batch_tables) {
+  Layout L{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align_up(o + bytes);
+    return at;
+  };
+  const size_t tl = (size_t)j.total_l;
+  L.mu = take(8 * tl);
+  L.sig = take(8 * tl);
+  L.keys = take(8 * tl);
+  L.flags = take(tl);
+  L.nc = take(4 * (size_t)j.total_x);
+  L.nv = take(4 * (size_t)j.total_x);
+  L.rc = take((j.opt.f64 ? 32 : 16) * (size_t)j.total_rc);
+  L.special = take(4 * j.series.size());
+  L.counters = take(8 * 4);
+  L.segp = take(8 * ((size_t)j.nseg + 1));
+  L.segs = take(4 * std::max<size_t>(1, (size_t)j.nseg));
+  L.rescan = take(8 * tl);
+  if (with_batch_tables) {
+    L.grad = take(8 * (size_t)j.total_n);
+    L.sdesc = take(sizeof(SeriesDesc) * j.series.size());
+    L.wdesc = take(sizeof(SweepDesc) * j.sweeps.size());
+  }
+  L.total = o;
+  return L;
+}
+
+mpx::Work work_of(const Layout &L, void *ws) {
+  char *b = (char *)ws;
+  mpx::Work w{};
+  w.mu = (double *)(b + L.mu);
+  w.sig = (double *)(b + L.sig);
+  w.keys = (uint64_t *)(b + L.keys);
+  w.flags = (uint8_t *)(b + L.flags);
+  w.next_const = (int32_t *)(b + L.nc);
+  w.next_valid = (int32_t *)(b + L.nv);
+  w.rc = (void *)(b + L.rc);
+  w.special = (int32_t *)(b + L.special);
+  w.counters = (unsigned long long *)(b + L.counters);
+  w.seg_prefix = (int64_t *)(b + L.segp);
+  w.seg_sweep = (int32_t *)(b + L.segs);
+  w.rescan = (int64_t *)(b + L.rescan);
+  w.grad = L.grad ? (double *)(b + L.grad) : nullptr;
+  return w;
+}
+
+mpx::Plan plan_of(const Job &j, const Layout &L, void *ws, bool external) {
+  mpx::Plan p{};
+  p.nseries = (int32_t)j.series.size();
+  p.nsweeps = (int32_t)j.sweeps.size();
+  if (external) {
+    p.s_ext = (const SeriesDesc *)((char *)ws + L.sdesc);
+    p.w_ext = (const SweepDesc *)((char *)ws + L.wdesc);
+  } else {
+    for (size_t i = 0; i < j.series.size() && i < 2; ++i) p.s_inl[i] = j.series[i];
+    for (size_t i = 0; i < j.sweeps.size() && i < 2; ++i) p.w_inl[i] = j.sweeps[i];
+  }
+  return p;
+}
+
+bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
+size_t esize(mp_dtype dt) { return dt == MP_F64 ? 8 : 4; }
+
+mp_status check_ws(void *ws, size_t ws_bytes, size_t need) {
+  if (!ws || !aligned(ws, kAlign) || ws_bytes < need) return MP_EWORKSPACE;
+  return MP_OK;
+}
+
+// The full launch sequence of a job whose descriptors are reachable through
+// `plan`.
+mp_status run_job(const Job &j, const mpx::Plan &plan, const mpx::Work &w, const void *T,
+                  const mpx::Outputs &o, bool out_f64, hipStream_t st) {
+  const Options &op = j.opt;
+  if (mpx::launch_plan(plan, w, j.W, j.R, j.nseg, st) != hipSuccess) return MP_ELAUNCH;
+  if (mpx::launch_stats(plan, w, T, j.t_f64, op.f64, j.total_rc, st) != hipSuccess) return MP_ELAUNCH;
+  if (j.tiles > 0) {
+    const int grid = (int)std::min<int64_t>(j.tiles, mpx::sweep_grid(op.f64, op.slots));
+    if (mpx::launch_sweep(plan, w, T, j.t_f64, op.f64, op.slots, j.R, j.tiles, j.nseg, grid, st) !=
+        hipSuccess)
+      return MP_ELAUNCH;
+  }
+  if (mpx::launch_special(plan, w, st) != hipSuccess) return MP_ELAUNCH;
+  if (mpx::launch_finalize(plan, w, T, j.t_f64, o, out_f64, op.fp64_finalize, j.total_l, st) !=
+      hipSuccess)
+    return MP_ELAUNCH;
+  if (mpx::launch_rescan(plan, w, T, j.t_f64, o, out_f64, op.fp64_finalize, st) != hipSuccess)
+    return MP_ELAUNCH;
+  return MP_OK;
+}
+
+mp_status build_selfjoin(int64_t n, int32_t m, int32_t ez, mp_dtype dt, const mp_options *opt,
+                         Job &j) {
+  if (dt != MP_F64 && dt != MP_F32) return MP_EINVAL;
+  if (m < 2 || n < m || ez < 0) return MP_EINVAL;
+  if (n - m + 1 >= ((int64_t)1 << 31)) return MP_EINVAL;
+  mp_status s = parse_options(opt, j.opt);
+  if (s != MP_OK) return s;
+  j.t_f64 = dt == MP_F64;
+  add_series(j, 0, n, m, ez, 0, 0);
+  const int64_t l = n - m + 1;
+  add_sweep(j, 0, 0, 0, 0, (int64_t)ez + 1, l - 1);
+  finish_job(j);
+  return MP_OK;
+}
+
+mp_status build_abjoin(int64_t nA, int64_t nB, int64_t b_off, int32_t m, mp_dtype dt,
+                       const mp_options *opt, Job &j) {
+  if (dt != MP_F64 && dt != MP_F32) return MP_EINVAL;
+  if (m < 2 || nA < m || nB < m) return MP_EINVAL;
+  if (nA - m + 1 >= ((int64_t)1 << 31) || nB - m + 1 >= ((int64_t)1 << 31)) return MP_EINVAL;
+  mp_status s = parse_options(opt, j.opt);
+  if (s != MP_OK) return s;
+  j.t_f64 = dt == MP_F64;
+  add_series(j, 0, nA, m, -1, 1, 0);
+  add_series(j, b_off, nB, m, -1, 0, 1);
+  const int64_t lA = nA - m + 1, lB = nB - m + 1;
+  add_sweep(j, 0, 1, 0, 1, 0, lB - 1);  // rows A, columns B, j >= i
+  add_sweep(j, 1, 0, 1, 0, 1, lA - 1);  // rows B, columns A, i > j
+  finish_job(j);
+  return MP_OK;
+}
+
+}  // namespace
+
+struct mp_batch_plan {
+  Job job;
+  Layout lay;
+  std::vector<int64_t> p_off;
+};
+
+extern "C" {
+
+int mp_abi_version(void) { return MP_ABI_VERSION; }
+
+const char *mp_strerror(mp_status s) {
+  switch (s) {
+    case MP_OK: return "ok";
+    case MP_EINVAL: return "invalid argument";
+    case MP_EWORKSPACE: return "workspace missing, misaligned or too small";
+    case MP_ELAUNCH: return "kernel launch failed";
+    case MP_EUNSUPPORTED: return "unsupported option combination";
+  }
+  return "unknown status";
+}
+
+int64_t mp_selfjoin_cells(int64_t n, int32_t m, int32_t ez) {
+  if (m < 2 || n < m || ez < 0) return 0;
+  const int64_t l = n - m + 1;
+  return sweep_cells(l, l, (int64_t)ez + 1, l - 1);
+}
+
+int64_t mp_abjoin_cells(int64_t nA, int64_t nB, int32_t m) {
+  if (m < 2 || nA < m || nB < m) return 0;
+  return (nA - m + 1) * (nB - m + 1);
+}
+
+size_t mp_selfjoin_workspace(int64_t n, int32_t m, mp_dtype dtype, const mp_options *opt) {
+  Job j;
+  if (build_selfjoin(n, m, 0, dtype, opt, j) != MP_OK) return 0;
+  return layout_of(j, false).total;
+}
+
+mp_status mp_selfjoin(const void *T, int64_t n, int32_t m, int32_t ez, mp_dtype dtype,
+                      const mp_options *opt, void *P, int64_t *I, void *ws, size_t ws_bytes,
+                      void *stream) {
+  Job j;
+  mp_status s = build_selfjoin(n, m, ez, dtype, opt, j);
+  if (s != MP_OK) return s;
+  if (!T || !P || !I || !aligned(T, esize(dtype)) || !aligned(P, esize(dtype)) || !aligned(I, 8))
+    return MP_EINVAL;
+  const Layout L = layout_of(j, false);
+  if ((s = check_ws(ws, ws_bytes, L.total)) != MP_OK) return s;
+  const mpx::Work w = work_of(L, ws);
+  const mpx::Plan p = plan_of(j, L, ws, false);
+  mpx::Outputs o{};
+  o.P[0] = P;
+  o.I[0] = I;
+  return run_job(j, p, w, T, o, dtype == MP_F64, (hipStream_t)stream);
+}
+
+size_t mp_abjoin_workspace(int64_t nA, int64_t nB, int32_t m, mp_dtype dtype, const mp_options *opt) {
+  Job j;
+  if (build_abjoin(nA, nB, 0, m, dtype, opt, j) != MP_OK) return 0;
+  return layout_of(j, false).total;
+}
+
+mp_status mp_abjoin(const void *A, int64_t nA, const void *B, int64_t nB, int32_t m, mp_dtype dtype,
+                    const mp_options *opt, void *P_ab, int64_t *I_ab, void *P_ba, int64_t *I_ba,
+                    void *ws, size_t ws_bytes, void *stream) {
+  if (!A || !B || !P_ab || !I_ab || !P_ba || !I_ba) return MP_EINVAL;
+  const size_t es = esize(dtype);
+  if (!aligned(A, es) || !aligned(B, es) || !aligned(P_ab, es) || !aligned(P_ba, es) ||
+      !aligned(I_ab, 8) || !aligned(I_ba, 8))
+    return MP_EINVAL;
+  // B is addressed relative to A (one flat device address space)
+  const int64_t diff = (int64_t)((intptr_t)B - (intptr_t)A);
+  if (diff % (int64_t)es != 0) return MP_EINVAL;
+  Job j;
+  mp_status s = build_abjoin(nA, nB, diff / (int64_t)es, m, dtype, opt, j);
+  if (s != MP_OK) return s;
+  const Layout L = layout_of(j, false);
+  if ((s = check_ws(ws, ws_bytes, L.total)) != MP_OK) return s;
+  const mpx::Work w = work_of(L, ws);
+  const mpx::Plan p = plan_of(j, L, ws, false);
+  mpx::Outputs o{};
+  o.P[0] = P_ab;
+  o.I[0] = I_ab;
+  o.P[1] = P_ba;
+  o.I[1] = I_ba;
+  return run_job(j, p, w, A, o, dtype == MP_F64, (hipStream_t)stream);
+}
+
+mp_status mp_batch_plan_create(int32_t nseries, const int64_t *t_off, const int32_t *m,
+                               const int32_t *ez, mp_dtype dtype, const mp_options *opt,
+                               mp_batch_plan **out) {
+  if (!out) return MP_EINVAL;
+  *out = nullptr;
+  if (nseries < 1 || !t_off || !m || !ez) return MP_EINVAL;
+  if (dtype != MP_F64 && dtype != MP_F32) return MP_EINVAL;
+  mp_batch_plan *pl = new (std::nothrow) mp_batch_plan();
+  if (!pl) return MP_EINVAL;
+  Job &j = pl->job;
+  mp_status s = parse_options(opt, j.opt);
+  if (s != MP_OK) {
+    delete pl;
+    return s;
+  }
+  j.t_f64 = dtype == MP_F64;
+  if (t_off[0] != 0) {
+    delete pl;
+    return MP_EINVAL;
+  }
+  for (int32_t i = 0; i < nseries; ++i) {
+    const int64_t n = t_off[i + 1] - t_off[i];
+    if (m[i] < 2 || n < m[i] || ez[i] < 0 || n - m[i] + 1 >= ((int64_t)1 << 31)) {
+      delete pl;
+      return MP_EINVAL;
+    }
+    add_series(j, t_off[i], n, m[i], ez[i], i, 0);
+  }
+  if (j.total_l >= ((int64_t)1 << 40)) {
+    delete pl;
+    return MP_EINVAL;
+  }
+  for (int32_t i = 0; i < nseries; ++i)
+    add_sweep(j, i, i, i, i, (int64_t)ez[i] + 1, j.series[i].l - 1);
+  finish_job(j);
+  pl->lay = layout_of(j, true);
+  pl->p_off.resize(nseries + 1);
+  for (int32_t i = 0; i <= nseries; ++i) pl->p_off[i] = i < nseries ? j.series[i].w_off : j.total_l;
+  *out = pl;
+  return MP_OK;
+}
+
+size_t mp_batch_plan_workspace(const mp_batch_plan *pl) { return pl ? pl->lay.total : 0; }
+int64_t mp_batch_plan_profile_length(const mp_batch_plan *pl) { return pl ? pl->job.total_l : 0; }
+int64_t mp_batch_plan_cells(const mp_batch_plan *pl) { return pl ? pl->job.cells : 0; }
+
+mp_status mp_batch_plan_upload(const mp_batch_plan *pl, void *ws, size_t ws_bytes, void *stream) {
+  if (!pl) return MP_EINVAL;
+  mp_status s = check_ws(ws, ws_bytes, pl->lay.total);
+  if (s != MP_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  char *b = (char *)ws;
+  if (hipMemcpyAsync(b + pl->lay.sdesc, pl->job.series.data(),
+                     sizeof(SeriesDesc) * pl->job.series.size(), hipMemcpyHostToDevice, st) != hipSuccess)
+    return MP_ELAUNCH;
+  if (hipMemcpyAsync(b + pl->lay.wdesc, pl->job.sweeps.data(),
+                     sizeof(SweepDesc) * pl->job.sweeps.size(), hipMemcpyHostToDevice, st) != hipSuccess)
+    return MP_ELAUNCH;
+  return MP_OK;
+}
+
+mp_status mp_batch(const mp_batch_plan *pl, const void *T_cat, void *P_cat, int64_t *I_cat, void *ws,
+                   size_t ws_bytes, void *stream) {
+  if (!pl || !T_cat || !P_cat || !I_cat) return MP_EINVAL;
+  const size_t es = pl->job.t_f64 ? 8 : 4;
+  if (!aligned(T_cat, es) || !aligned(P_cat, es) || !aligned(I_cat, 8)) return MP_EINVAL;
+  mp_status s = check_ws(ws, ws_bytes, pl->lay.total);
+  if (s != MP_OK) return s;
+  const mpx::Work w = work_of(pl->lay, ws);
+  const mpx::Plan p = plan_of(pl->job, pl->lay, ws, true);
+  mpx::Outputs o{};
+  o.P[0] = P_cat;
+  o.I[0] = I_cat;
+  return run_job(pl->job, p, w, T_cat, o, pl->job.t_f64, (hipStream_t)stream);
+}
+
+void mp_batch_plan_destroy(mp_batch_plan *pl) { delete pl; }
+
+mp_status mp_backward(const mp_batch_plan *pl, const void *T_cat, const int64_t *I_cat,
+                      const void *gP_cat, void *gT_cat, void *ws, size_t ws_bytes, void *stream) {
+  if (!pl || !T_cat || !I_cat || !gP_cat || !gT_cat) return MP_EINVAL;
+  const size_t es = pl->job.t_f64 ? 8 : 4;
+  if (!aligned(T_cat, es) || !aligned(gP_cat, es) || !aligned(gT_cat, es) || !aligned(I_cat, 8))
+    return MP_EINVAL;
+  mp_status s = check_ws(ws, ws_bytes, pl->lay.total);
+  if (s != MP_OK) return s;
+  const mpx::Work w = work_of(pl->lay, ws);
+  const mpx::Plan p = plan_of(pl->job, pl->lay, ws, true);
+  if (mpx::launch_backward(p, w, T_cat, pl->job.t_f64, I_cat, gP_cat, gT_cat, pl->job.total_l,
+                           pl->job.total_n, (hipStream_t)stream) != hipSuccess)
+    return MP_ELAUNCH;
+  return MP_OK;
+}
+
+size_t mp_recheck_workspace(int64_t n, int32_t m) {
+  if (m < 2 || n < m) return 0;
+  return align_up((size_t)(n - m + 1));
+}
+
+mp_status mp_recheck(const void *T, int64_t n, int32_t m, mp_dtype dtype, const void *P,
+                     const int64_t *I, int32_t k_motifs, int32_t k_discords, int64_t *out_idx,
+                     double *out_dist, void *ws, size_t ws_bytes, void *stream) {
+  if (dtype != MP_F64 && dtype != MP_F32) return MP_EINVAL;
+  if (m < 2 || n < m || k_motifs < 0 || k_discords < 0 || k_motifs > 64 || k_discords > 64)
+    return MP_EINVAL;
+  if (!T || !P || !I || !out_idx || !out_dist) return MP_EINVAL;
+  const size_t es = esize(dtype);
+  if (!aligned(T, es) || !aligned(P, es) || !aligned(I, 8) || !aligned(out_idx, 8) ||
+      !aligned(out_dist, 8))
+    return MP_EINVAL;
+  mp_status s = check_ws(ws, ws_bytes, mp_recheck_workspace(n, m));
+  if (s != MP_OK) return s;
+  if (k_motifs + k_discords == 0) return MP_OK;
+  if (mpx::launch_recheck(T, dtype == MP_F64, n, m, P, dtype == MP_F64, I, k_motifs, k_discords,
+                          out_idx, out_dist, (uint8_t *)ws, (hipStream_t)stream) != hipSuccess)
+    return MP_ELAUNCH;
+  return MP_OK;
+}
+
+}  // extern "C"

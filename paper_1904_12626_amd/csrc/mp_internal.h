@@ -1,0 +1,105 @@
+// Internal declarations shared by the HIP translation units of libmpx.
+// Nothing here is part of the public ABI (include/mp.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace mpx {
+
+constexpr int kWave = 64;
+// Padding (in windows) after every series' row/column data so that the
+// sweep's look-ahead loads past the last window stay inside the buffer.
+constexpr int64_t kRcPad = 64 * 16 + 128;
+// Keys >= this value mean "no admissible neighbour".  Valid keys are
+// 1 - rho in [0, 2] (plus rounding); invalid rows carry 4.
+constexpr double kKeyInvalid = 3.0;
+
+// One series as the kernels see it.  Offsets index the caller's T array and
+// the concatenated per-window workspace arrays.
+struct SeriesDesc {
+  int64_t t_off;   // first element in the T base array
+  int64_t n;       // series length
+  int64_t l;       // windows, n - m + 1
+  int64_t w_off;   // first window in mu/sig/flags/keys/P/I and rescan ids
+  int64_t rc_off;  // first entry in the padded row/column data array
+  int64_t x_off;   // first entry in next_const/next_valid (l + 1 entries)
+  int32_t m;
+  int32_t ez;       // >= 0: self-join zone; -1: AB side (no zone)
+  int32_t partner;  // series whose windows are this series' candidates
+  int32_t out;      // output slot: 0 (single array) or the AB side (0/1)
+};
+
+// One diagonal sweep: rows from series rs, columns from series cs,
+// diagonals k = j - i in [k_lo, k_hi].  Row minima go to the keys of
+// series rk, column minima to the keys of series ck.
+struct SweepDesc {
+  int32_t rs, cs, rk, ck;
+  int64_t k_lo, k_hi;
+  int64_t seg_base;  // first strip (segment) of this sweep in the tile table
+  int64_t nseg;      // strips
+  int32_t idx_bits;  // low bits of a packed key that hold the index
+  int32_t pad_;
+};
+
+// Everything the kernels need to find a series / sweep.  Passed by value;
+// up to two descriptors travel inline, a batch keeps them in the workspace.
+struct Plan {
+  int32_t nseries, nsweeps;
+  SeriesDesc s_inl[2];
+  SweepDesc w_inl[2];
+  const SeriesDesc *s_ext;
+  const SweepDesc *w_ext;
+
+  __device__ __forceinline__ SeriesDesc series(int i) const { return s_ext ? s_ext[i] : s_inl[i]; }
+  __device__ __forceinline__ SweepDesc sweep(int i) const { return w_ext ? w_ext[i] : w_inl[i]; }
+};
+
+// Workspace arrays (device).
+struct Work {
+  double *mu;          // [total_l] window mean (FP64)
+  double *sig;         // [total_l] window population std (FP64)
+  uint64_t *keys;      // [total_l] packed (key, index) minima
+  uint8_t *flags;      // [total_l] bit0 valid, bit1 constant
+  int32_t *next_const; // [total_x] smallest constant window >= x (l if none)
+  int32_t *next_valid; // [total_x] smallest valid window >= x (l if none)
+  void *rc;            // [total_rc] row/column data {a, g, s, u} (F4)
+  int32_t *special;    // [nseries] bit0 has invalid windows, bit1 has constant
+  unsigned long long *counters;  // [4]: 0 tile counter, 1 rescan count
+  int64_t *seg_prefix; // [nseg + 1] first tile of each strip
+  int32_t *seg_sweep;  // [nseg] sweep of each strip
+  int64_t *rescan;     // [total_l] windows needing an exact row scan
+  double *grad;        // [total_n] FP64 gradient accumulator (batch plans)
+};
+
+struct Outputs {
+  void *P[2];
+  int64_t *I[2];
+};
+
+// ------------------------------------------------------------- launchers
+hipError_t launch_plan(const Plan &plan, const Work &w, int W, int R, int64_t nseg, hipStream_t st);
+hipError_t launch_stats(const Plan &plan, const Work &w, const void *T, bool t_f64, bool f64_sweep,
+                        int64_t total_rc, hipStream_t st);
+hipError_t launch_sweep(const Plan &plan, const Work &w, const void *T, bool t_f64, bool f64_sweep,
+                        int slots, int R, int64_t total_tiles, int64_t nseg, int grid,
+                        hipStream_t st);
+hipError_t launch_special(const Plan &plan, const Work &w, hipStream_t st);
+hipError_t launch_finalize(const Plan &plan, const Work &w, const void *T, bool t_f64,
+                           const Outputs &o, bool out_f64, bool fp64_finalize, int64_t total_l,
+                           hipStream_t st);
+hipError_t launch_rescan(const Plan &plan, const Work &w, const void *T, bool t_f64,
+                         const Outputs &o, bool out_f64, bool fp64_finalize, hipStream_t st);
+hipError_t launch_recheck(const void *T, bool t_f64, int64_t n, int32_t m, const void *P,
+                          bool p_f64, const int64_t *I, int32_t km, int32_t kd, int64_t *out_idx,
+                          double *out_dist, uint8_t *mask, hipStream_t st);
+hipError_t launch_backward(const Plan &plan, const Work &w, const void *T, bool t_f64,
+                           const int64_t *I, const void *gP, void *gT, int64_t total_l,
+                           int64_t total_n, hipStream_t st);
+
+// Occupancy-derived persistent grid for the sweep kernel.
+int sweep_grid(bool f64_sweep, int slots);
+
+}  // namespace mpx

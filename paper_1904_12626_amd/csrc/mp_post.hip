@@ -1,0 +1,380 @@
+// After the sweep: decode the packed minima into (P, I), resolve windows the
+// sweep cannot express exactly (constant and invalid windows), optionally
+// recompute P in FP64 from the chosen pair, and the FP64 recheck of the best
+// motif pairs and discords.
+#include <cmath>
+
+#include "mp_internal.h"
+#include "mp_types.h"
+
+namespace mpx {
+
+namespace {
+
+__device__ __forceinline__ int find_series_w(const Plan &plan, int64_t wi) {
+  if (plan.s_ext) {
+    int lo = 0, hi = plan.nseries - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (plan.s_ext[mid].w_off <= wi) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+  }
+  return (plan.nseries > 1 && wi >= plan.s_inl[1].w_off) ? 1 : 0;
+}
+
+template <typename Tin>
+__device__ __forceinline__ double sample(const Tin *p) {
+  const double v = (double)*p;
+  return isfinite(v) ? v : 0.0;
+}
+
+// FP64 z-normalised Euclidean distance between window i of series A and
+// window j of series B, in the direct difference form (constant windows
+// normalise to zero).  Callers pass valid windows only.
+template <typename Tin>
+__device__ double pair_dist64(const Tin *TA, double muA, double sgA, bool cA, const Tin *TB,
+                              double muB, double sgB, bool cB, int m) {
+  const double ia = cA ? 0.0 : 1.0 / sgA, ib = cB ? 0.0 : 1.0 / sgB;
+  double s = 0.0;
+  for (int u = 0; u < m; ++u) {
+    const double za = (sample(TA + u) - muA) * ia;
+    const double zb = (sample(TB + u) - muB) * ib;
+    const double d = za - zb;
+    s = fma(d, d, s);
+  }
+  return sqrt(s);
+}
+
+// Smallest window index of a partner series that is admissible for window w
+// (|w - j| > ez for a self-join, anything for an AB side) and has the
+// property tabulated in `next` (next[x] = smallest index >= x with it, or l).
+__device__ __forceinline__ int64_t first_admissible(const int32_t *next, int64_t l, int64_t w,
+                                                    int ez) {
+  const int64_t f = next[0];
+  if (f >= l) return -1;
+  if (ez < 0) return f;
+  if (f < w - ez) return f;
+  const int64_t x = w + ez + 1;
+  if (x >= l) return -1;
+  const int64_t g = next[x];
+  return g < l ? g : -1;
+}
+
+// Same, when every partner window is valid.
+__device__ __forceinline__ int64_t first_admissible_all(int64_t l, int64_t w, int ez) {
+  if (l <= 0) return -1;
+  if (ez < 0 || 0 < w - ez) return 0;
+  const int64_t x = w + ez + 1;
+  return x < l ? x : -1;
+}
+
+template <typename Tout>
+__device__ __forceinline__ void store_out(const Outputs &o, const SeriesDesc &S, int64_t w,
+                                          double P, int64_t I) {
+  const int slot = S.out;
+  const int64_t pos = (slot == 0 && o.P[1] == nullptr) ? (S.w_off + w) : w;
+  reinterpret_cast<Tout *>(o.P[slot])[pos] = (Tout)P;
+  o.I[slot][pos] = I;
+}
+
+}  // namespace
+
+// --------------------------------------------------------------- finalize
+// key -> P = sqrt(2 m key), I = index; then the degenerate-window rules:
+//  * invalid window: (+inf, -1);
+//  * constant window w: the nearest admissible constant partner at distance 0
+//    if any, otherwise the smallest admissible valid partner at sqrt(m);
+//  * valid window whose partner series has constant windows: the smallest
+//    admissible constant partner at distance sqrt(m) competes (the sweep
+//    scores such pairs too high);
+//  * if the chosen partner is invalid (the sweep scores pairs with an
+//    invalid column window like rho = 0), the window is queued for an exact
+//    rescan.
+template <typename Tin, typename Tout>
+__global__ void __launch_bounds__(256) k_finalize(Plan plan, Work wk, const Tin *__restrict__ Tb,
+                                                  Outputs o, int fp64_finalize, int64_t total_l) {
+  const int64_t wi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (wi >= total_l) return;
+  const int si = find_series_w(plan, wi);
+  const SeriesDesc S = plan.series(si);
+  const SeriesDesc Q = plan.series(S.partner);
+  const int64_t w = wi - S.w_off;
+  const uint8_t fw = wk.flags[wi];
+  if (!(fw & 1)) {
+    store_out<Tout>(o, S, w, INFINITY, -1);
+    return;
+  }
+  int ib = 1;
+  while (((int64_t)1 << ib) < max(S.l, Q.l)) ++ib;
+  const uint64_t key = wk.keys[wi];
+  double val = INFINITY;
+  int64_t idx = -1;
+  if (key != ~0ull) {
+    val = unpack_key(key, ib);
+    idx = unpack_idx(key, ib);
+    if (!(val < kKeyInvalid)) { val = INFINITY; idx = -1; }
+  }
+  const int sp = wk.special[S.partner];
+  const int32_t *nc = wk.next_const + Q.x_off;
+  const int32_t *nv = wk.next_valid + Q.x_off;
+  if (fw & 2) {  // constant window
+    const int64_t jc = (sp & 2) ? first_admissible(nc, Q.l, w, S.ez) : -1;
+    if (jc >= 0) {
+      val = 0.0;
+      idx = jc;
+    } else {
+      const int64_t jv = (sp & 1) ? first_admissible(nv, Q.l, w, S.ez)
+                                  : first_admissible_all(Q.l, w, S.ez);
+      val = jv >= 0 ? 0.5 : INFINITY;
+      idx = jv;
+    }
+    store_out<Tout>(o, S, w, idx >= 0 ? sqrt(2.0 * S.m * val) : INFINITY, idx);
+    return;
+  }
+  if (sp & 2) {
+    const int64_t jc = first_admissible(nc, Q.l, w, S.ez);
+    if (jc >= 0 && (0.5 < val || (0.5 == val && jc < idx))) {
+      val = 0.5;
+      idx = jc;
+    }
+  }
+  if ((sp & 1) && idx >= 0 && !(wk.flags[Q.w_off + idx] & 1)) {
+    const unsigned long long pos = atomicAdd(&wk.counters[1], 1ull);
+    wk.rescan[pos] = wi;
+    store_out<Tout>(o, S, w, INFINITY, -1);
+    return;
+  }
+  double P = INFINITY;
+  if (idx >= 0) {
+    P = sqrt(2.0 * S.m * fmax(val, 0.0));
+    if (fp64_finalize && !(wk.flags[Q.w_off + idx] & 2)) {
+      P = pair_dist64(Tb + S.t_off + w, wk.mu[wi], wk.sig[wi], false, Tb + Q.t_off + idx,
+                      wk.mu[Q.w_off + idx], wk.sig[Q.w_off + idx], false, S.m);
+    }
+  }
+  store_out<Tout>(o, S, w, P, idx);
+}
+
+// ------------------------------------------------------------------ rescan
+// Exact row minimum for the queued windows: one workgroup per queued window
+// (grid-stride over the queue), every admissible valid partner scored in
+// FP64 as 1 - rho (constant partners score 1/2), smallest (key, index) wins.
+template <typename Tin, typename Tout>
+__global__ void __launch_bounds__(256) k_rescan(Plan plan, Work wk, const Tin *__restrict__ Tb,
+                                                Outputs o, int fp64_finalize) {
+  __shared__ double bk[256];
+  __shared__ int64_t bi[256];
+  const unsigned long long count = wk.counters[1];
+  for (unsigned long long q = blockIdx.x; q < count; q += gridDim.x) {
+    const int64_t wi = wk.rescan[q];
+    const int si = find_series_w(plan, wi);
+    const SeriesDesc S = plan.series(si);
+    const SeriesDesc Q = plan.series(S.partner);
+    const int64_t w = wi - S.w_off;
+    const Tin *Tw = Tb + S.t_off + w;
+    const double muw = wk.mu[wi], sgw = wk.sig[wi];
+    double best = INFINITY;
+    int64_t arg = -1;
+    for (int64_t j = threadIdx.x; j < Q.l; j += blockDim.x) {
+      if (S.ez >= 0 && llabs(j - w) <= S.ez) continue;
+      const uint8_t fj = wk.flags[Q.w_off + j];
+      if (!(fj & 1)) continue;
+      double key;
+      if (fj & 2) {
+        key = 0.5;
+      } else {
+        const Tin *Tj = Tb + Q.t_off + j;
+        const double muj = wk.mu[Q.w_off + j];
+        double c = 0.0;
+        for (int u = 0; u < S.m; ++u) c = fma(sample(Tw + u) - muw, sample(Tj + u) - muj, c);
+        key = 1.0 - c / ((double)S.m * sgw * wk.sig[Q.w_off + j]);
+      }
+      if (key < best) { best = key; arg = j; }  // j increases per thread
+    }
+    bk[threadIdx.x] = best;
+    bi[threadIdx.x] = arg;
+    __syncthreads();
+    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+      if ((int)threadIdx.x < h) {
+        const double k2 = bk[threadIdx.x + h];
+        const int64_t i2 = bi[threadIdx.x + h];
+        if (i2 >= 0 && (k2 < bk[threadIdx.x] || (k2 == bk[threadIdx.x] && (bi[threadIdx.x] < 0 || i2 < bi[threadIdx.x])))) {
+          bk[threadIdx.x] = k2;
+          bi[threadIdx.x] = i2;
+        }
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      const int64_t j = bi[0];
+      double P = INFINITY;
+      if (j >= 0) {
+        P = sqrt(2.0 * S.m * fmax(bk[0], 0.0));
+        if (fp64_finalize && !(wk.flags[Q.w_off + j] & 2))
+          P = pair_dist64(Tw, muw, sgw, false, Tb + Q.t_off + j, wk.mu[Q.w_off + j],
+                          wk.sig[Q.w_off + j], false, S.m);
+      }
+      store_out<Tout>(o, S, w, P, j);
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_finalize(const Plan &plan, const Work &w, const void *T, bool t_f64,
+                           const Outputs &o, bool out_f64, bool fp64_finalize, int64_t total_l,
+                           hipStream_t st) {
+  const dim3 blk(256), grd((unsigned)((total_l + 255) / 256));
+  const int f = fp64_finalize ? 1 : 0;
+  if (t_f64) {
+    if (out_f64) hipLaunchKernelGGL((k_finalize<double, double>), grd, blk, 0, st, plan, w, (const double *)T, o, f, total_l);
+    else hipLaunchKernelGGL((k_finalize<double, float>), grd, blk, 0, st, plan, w, (const double *)T, o, f, total_l);
+  } else {
+    if (out_f64) hipLaunchKernelGGL((k_finalize<float, double>), grd, blk, 0, st, plan, w, (const float *)T, o, f, total_l);
+    else hipLaunchKernelGGL((k_finalize<float, float>), grd, blk, 0, st, plan, w, (const float *)T, o, f, total_l);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_rescan(const Plan &plan, const Work &w, const void *T, bool t_f64,
+                         const Outputs &o, bool out_f64, bool fp64_finalize, hipStream_t st) {
+  const dim3 blk(256), grd(512);
+  const int f = fp64_finalize ? 1 : 0;
+  if (t_f64) {
+    if (out_f64) hipLaunchKernelGGL((k_rescan<double, double>), grd, blk, 0, st, plan, w, (const double *)T, o, f);
+    else hipLaunchKernelGGL((k_rescan<double, float>), grd, blk, 0, st, plan, w, (const double *)T, o, f);
+  } else {
+    if (out_f64) hipLaunchKernelGGL((k_rescan<float, double>), grd, blk, 0, st, plan, w, (const float *)T, o, f);
+    else hipLaunchKernelGGL((k_rescan<float, float>), grd, blk, 0, st, plan, w, (const float *)T, o, f);
+  }
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ recheck
+// One workgroup: k_motifs rounds of "smallest finite unmasked P -> pair
+// (i, I[i]), mask within m of both", then k_discords rounds of "largest
+// finite unmasked P, mask within m"; every reported pair is re-measured in
+// FP64.  Ties go to the smallest index.
+template <typename Tin, typename Tp>
+__global__ void __launch_bounds__(1024) k_recheck(const Tin *__restrict__ T, int64_t n, int m,
+                                                  const Tp *__restrict__ P,
+                                                  const int64_t *__restrict__ I, int km, int kd,
+                                                  int64_t *out_idx, double *out_dist,
+                                                  uint8_t *mask) {
+  __shared__ double bv[1024];
+  __shared__ int64_t bi[1024];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int64_t l = n - m + 1;
+  auto stats = [&](int64_t i, double &mu, double &sg, bool &cst) {
+    double s = 0.0, lo = 0.0, hi = 0.0;
+    for (int u = 0; u < m; ++u) {
+      const double v = sample(T + i + u);
+      if (u == 0) { lo = v; hi = v; }
+      lo = fmin(lo, v);
+      hi = fmax(hi, v);
+      s += v;
+    }
+    mu = s / m;
+    double q = 0.0;
+    for (int u = 0; u < m; ++u) {
+      const double dv = sample(T + i + u) - mu;
+      q = fma(dv, dv, q);
+    }
+    sg = sqrt(q / m);
+    cst = (lo == hi);
+  };
+  auto dist = [&](int64_t i, int64_t j) -> double {
+    double mi, si, mj, sj;
+    bool ci, cj;
+    stats(i, mi, si, ci);
+    stats(j, mj, sj, cj);
+    return pair_dist64(T + i, mi, si, ci, T + j, mj, sj, cj, m);
+  };
+  // block argmin (sign = +1) or argmax (sign = -1) of finite unmasked P
+  auto pick = [&](double sign) -> int64_t {
+    double best = INFINITY;
+    int64_t arg = -1;
+    for (int64_t x = tid; x < l; x += nt) {
+      const double p = (double)P[x];
+      if (mask[x] || !isfinite(p)) continue;
+      const double v = sign * p;
+      if (v < best) { best = v; arg = x; }
+    }
+    bv[tid] = best;
+    bi[tid] = arg;
+    __syncthreads();
+    for (int h = nt / 2; h > 0; h >>= 1) {
+      if (tid < h) {
+        const double v2 = bv[tid + h];
+        const int64_t i2 = bi[tid + h];
+        if (i2 >= 0 && (bi[tid] < 0 || v2 < bv[tid] || (v2 == bv[tid] && i2 < bi[tid]))) {
+          bv[tid] = v2;
+          bi[tid] = i2;
+        }
+      }
+      __syncthreads();
+    }
+    const int64_t r = bi[0];
+    __syncthreads();
+    return r;
+  };
+  auto mask_around = [&](int64_t c) {
+    for (int64_t x = max((int64_t)0, c - m) + tid; x <= min(l - 1, c + m); x += nt) mask[x] = 1;
+    __syncthreads();
+  };
+  for (int64_t x = tid; x < l; x += nt) mask[x] = 0;
+  __syncthreads();
+  for (int q = 0; q < km; ++q) {
+    const int64_t i = pick(1.0);
+    const int64_t j = (i >= 0) ? I[i] : -1;
+    if (tid == 0) {
+      out_idx[2 * q] = (j >= 0) ? i : -1;
+      out_idx[2 * q + 1] = j;
+      out_dist[q] = (j >= 0) ? dist(i, j) : INFINITY;
+    }
+    if (j < 0) {
+      for (int r = q + 1; r < km && tid == 0; ++r) {
+        out_idx[2 * r] = -1;
+        out_idx[2 * r + 1] = -1;
+        out_dist[r] = INFINITY;
+      }
+      break;
+    }
+    mask_around(i);
+    mask_around(j);
+  }
+  for (int64_t x = tid; x < l; x += nt) mask[x] = 0;
+  __syncthreads();
+  for (int q = 0; q < kd; ++q) {
+    const int64_t i = pick(-1.0);
+    const int64_t j = (i >= 0) ? I[i] : -1;
+    if (tid == 0) {
+      out_idx[2 * km + q] = i;
+      out_dist[km + q] = (i >= 0 && j >= 0) ? dist(i, j) : INFINITY;
+    }
+    if (i < 0) {
+      for (int r = q + 1; r < kd && tid == 0; ++r) {
+        out_idx[2 * km + r] = -1;
+        out_dist[km + r] = INFINITY;
+      }
+      break;
+    }
+    mask_around(i);
+  }
+}
+
+hipError_t launch_recheck(const void *T, bool t_f64, int64_t n, int32_t m, const void *P,
+                          bool p_f64, const int64_t *I, int32_t km, int32_t kd, int64_t *out_idx,
+                          double *out_dist, uint8_t *mask, hipStream_t st) {
+  const dim3 blk(1024), grd(1);
+  if (t_f64) {
+    if (p_f64) hipLaunchKernelGGL((k_recheck<double, double>), grd, blk, 0, st, (const double *)T, n, m, (const double *)P, I, km, kd, out_idx, out_dist, mask);
+    else hipLaunchKernelGGL((k_recheck<double, float>), grd, blk, 0, st, (const double *)T, n, m, (const float *)P, I, km, kd, out_idx, out_dist, mask);
+  } else {
+    if (p_f64) hipLaunchKernelGGL((k_recheck<float, double>), grd, blk, 0, st, (const float *)T, n, m, (const double *)P, I, km, kd, out_idx, out_dist, mask);
+    else hipLaunchKernelGGL((k_recheck<float, float>), grd, blk, 0, st, (const float *)T, n, m, (const float *)P, I, km, kd, out_idx, out_dist, mask);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace mpx

@@ -1,0 +1,210 @@
+// Preparation kernels: the tile table of the diagonal sweep, per-window
+// statistics (z-normalisation terms) and the suffix tables used to resolve
+// constant and invalid windows.
+#include <cmath>
+
+#include "mp_internal.h"
+#include "mp_types.h"
+
+namespace mpx {
+
+// ------------------------------------------------------------------ plan
+// Strip g of sweep s covers diagonals [k_lo + (g - seg_base) * W, +W); its
+// longest diagonal has min(l_rows, l_cols - k0) cells, cut into tiles of R
+// rows.  One workgroup writes the first tile of every strip (an exclusive
+// prefix sum) and clears the per-call counters.
+__global__ void __launch_bounds__(1024) k_plan(Plan plan, Work w, int W, int R, int64_t nseg) {
+  __shared__ int64_t part[1024];
+  const int tid = threadIdx.x;
+  if (tid < 4) w.counters[tid] = 0;
+  for (int s = tid; s < plan.nseries; s += blockDim.x) w.special[s] = 0;
+
+  const int64_t per = (nseg + blockDim.x - 1) / blockDim.x;
+  const int64_t a = min(nseg, (int64_t)tid * per), b = min(nseg, a + per);
+  int sw = 0;
+  auto tiles_of = [&](int64_t g, int &swi) -> int64_t {
+    while (swi + 1 < plan.nsweeps && plan.sweep(swi + 1).seg_base <= g) ++swi;
+    const SweepDesc d = plan.sweep(swi);
+    const SeriesDesc rs = plan.series(d.rs), cs = plan.series(d.cs);
+    const int64_t k0 = d.k_lo + (g - d.seg_base) * (int64_t)W;
+    const int64_t L = min(rs.l, cs.l - k0);
+    return (L + R - 1) / R;
+  };
+  int64_t sum = 0;
+  for (int64_t g = a; g < b; ++g) sum += tiles_of(g, sw);
+  part[tid] = sum;
+  __syncthreads();
+  if (tid == 0) {
+    int64_t run = 0;
+    for (int q = 0; q < (int)blockDim.x; ++q) {
+      const int64_t v = part[q];
+      part[q] = run;
+      run += v;
+    }
+    w.seg_prefix[nseg] = run;
+  }
+  __syncthreads();
+  int64_t run = part[tid];
+  sw = 0;
+  for (int64_t g = a; g < b; ++g) {
+    const int64_t t = tiles_of(g, sw);
+    w.seg_prefix[g] = run;
+    w.seg_sweep[g] = sw;
+    run += t;
+  }
+}
+
+hipError_t launch_plan(const Plan &plan, const Work &w, int W, int R, int64_t nseg, hipStream_t st) {
+  hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, st, plan, w, W, R, nseg);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- stats
+// Window i of a series, with x = T where finite and 0 elsewhere:
+//   mu_i, sigma_i  two-pass FP64 mean and population std of x[i:i+m]
+//   a_i = x[i+m] - x[i]                       (0 for the last window)
+//   g_i = x[i] - mu_i + a_i (m-1)/(2m)
+//   s_i = 1 / (sqrt(m) sigma_i)   (0 for constant or invalid windows)
+//   u_i = 1 (valid), 1/2 (constant), 4 (invalid)
+// The centred cross product C(i,j) = sum_t (x[i+t]-mu_i)(x[j+t]-mu_j) then
+// obeys C(i+1,j+1) = C(i,j) + a_j g_i + a_i g_j exactly (expand
+// x[i+m] = x[i] + a_i and mu_{i+1} = mu_i + a_i/m), and the sweep's key
+// u_i - C s_i s_j equals 1 - rho(i,j) for valid windows.
+template <typename F, typename Tin>
+__global__ void __launch_bounds__(256) k_stats(Plan plan, Work w, const Tin *__restrict__ Tb,
+                                               int64_t total_rc) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= total_rc) return;
+  // series owning rc entry r
+  int si = 0;
+  if (plan.s_ext) {
+    int lo = 0, hi = plan.nseries - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (plan.s_ext[mid].rc_off <= r) lo = mid; else hi = mid - 1;
+    }
+    si = lo;
+  } else if (plan.nseries > 1 && r >= plan.s_inl[1].rc_off) {
+    si = 1;
+  }
+  const SeriesDesc S = plan.series(si);
+  const int64_t i = r - S.rc_off;
+  using V4 = typename FTraits<F>::V4;
+  V4 *rc = reinterpret_cast<V4 *>(w.rc);
+  if (i >= S.l) {  // padding
+    rc[r] = FTraits<F>::zero4();
+    return;
+  }
+  const Tin *x = Tb + S.t_off + i;
+  const int m = S.m;
+  bool fin = true;
+  double s = 0.0, lo = 0.0, hi = 0.0;
+  for (int u = 0; u < m; ++u) {
+    double v = (double)x[u];
+    if (!isfinite(v)) { fin = false; v = 0.0; }
+    if (u == 0) { lo = v; hi = v; }
+    lo = fmin(lo, v);
+    hi = fmax(hi, v);
+    s += v;
+  }
+  const double mu = s / m;
+  double q = 0.0;
+  for (int u = 0; u < m; ++u) {
+    double v = (double)x[u];
+    if (!isfinite(v)) v = 0.0;
+    const double dv = v - mu;
+    q = fma(dv, dv, q);
+  }
+  const double sig = sqrt(q / m);
+  const bool cst = fin && (lo == hi);
+  double x0 = (double)x[0];
+  if (!isfinite(x0)) x0 = 0.0;
+  double a = 0.0;
+  if (i + m < S.n) {
+    double xm = (double)x[m];
+    if (!isfinite(xm)) xm = 0.0;
+    a = xm - x0;
+  }
+  const double g = (x0 - mu) + a * ((double)(m - 1) / (2.0 * m));
+  const double sc = (fin && !cst && sig > 0.0) ? 1.0 / (sqrt((double)m) * sig) : 0.0;
+  const double uu = fin ? (cst ? 0.5 : 1.0) : 4.0;
+  const int64_t wi = S.w_off + i;
+  w.mu[wi] = mu;
+  w.sig[wi] = sig;
+  w.flags[wi] = (uint8_t)((fin ? 1 : 0) | (cst ? 2 : 0));
+  w.keys[wi] = ~0ull;
+  rc[r] = FTraits<F>::make4(a, g, sc, uu);
+  const int bits = (fin ? 0 : 1) | (cst ? 2 : 0);
+  if (bits) atomicOr(&w.special[si], bits);
+}
+
+hipError_t launch_stats(const Plan &plan, const Work &w, const void *T, bool t_f64, bool f64_sweep,
+                        int64_t total_rc, hipStream_t st) {
+  const dim3 blk(256), grd((unsigned)((total_rc + 255) / 256));
+  if (t_f64) {
+    if (f64_sweep)
+      hipLaunchKernelGGL((k_stats<double, double>), grd, blk, 0, st, plan, w, (const double *)T, total_rc);
+    else
+      hipLaunchKernelGGL((k_stats<float, double>), grd, blk, 0, st, plan, w, (const double *)T, total_rc);
+  } else {
+    if (f64_sweep)
+      hipLaunchKernelGGL((k_stats<double, float>), grd, blk, 0, st, plan, w, (const float *)T, total_rc);
+    else
+      hipLaunchKernelGGL((k_stats<float, float>), grd, blk, 0, st, plan, w, (const float *)T, total_rc);
+  }
+  return hipGetLastError();
+}
+
+// -------------------------------------------------------------- special
+// For a series with constant or invalid windows: next_const[x] / next_valid[x]
+// = smallest constant / valid window index >= x, or l if none (x in [0, l]).
+// One workgroup per series; it exits at once when the series has neither.
+__global__ void __launch_bounds__(1024) k_special(Plan plan, Work w) {
+  const int si = blockIdx.x;
+  if (w.special[si] == 0) return;
+  const SeriesDesc S = plan.series(si);
+  __shared__ int32_t cmin[1024], vmin[1024];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int64_t l = S.l;
+  const int64_t per = (l + nt - 1) / nt;
+  const int64_t a = min(l, (int64_t)tid * per), b = min(l, a + per);
+  int32_t fc = (int32_t)l, fv = (int32_t)l;
+  for (int64_t x = b - 1; x >= a; --x) {
+    const uint8_t f = w.flags[S.w_off + x];
+    if (f & 1) fv = (int32_t)x;
+    if (f & 2) fc = (int32_t)x;
+  }
+  cmin[tid] = fc;
+  vmin[tid] = fv;
+  __syncthreads();
+  if (tid == 0) {  // suffix minimum over the chunks, shifted by one chunk
+    int32_t rc = (int32_t)l, rv = (int32_t)l;
+    for (int q = nt - 1; q >= 0; --q) {
+      const int32_t c = cmin[q], v = vmin[q];
+      cmin[q] = rc;
+      vmin[q] = rv;
+      rc = min(rc, c);
+      rv = min(rv, v);
+    }
+  }
+  __syncthreads();
+  int32_t nc = cmin[tid], nv = vmin[tid];
+  for (int64_t x = b - 1; x >= a; --x) {
+    const uint8_t f = w.flags[S.w_off + x];
+    if (f & 1) nv = (int32_t)x;
+    if (f & 2) nc = (int32_t)x;
+    w.next_const[S.x_off + x] = nc;
+    w.next_valid[S.x_off + x] = nv;
+  }
+  if (tid == 0) {
+    w.next_const[S.x_off + l] = (int32_t)l;
+    w.next_valid[S.x_off + l] = (int32_t)l;
+  }
+}
+
+hipError_t launch_special(const Plan &plan, const Work &w, hipStream_t st) {
+  hipLaunchKernelGGL(k_special, dim3(plan.nseries), dim3(1024), 0, st, plan, w);
+  return hipGetLastError();
+}
+
+}  // namespace mpx

@@ -1,0 +1,369 @@
+// The diagonal sweep: every admissible cell (i, j) of the distance matrix is
+// visited once, in O(1) work, and contributes to the minimum of row i and of
+// column j (matrix profile = row minima, Section 2 of the tsmp paper; the
+// O(1) update of one row's dot products from the previous row is the STOMP
+// idea of Section 3.3.2, applied here along diagonals so that tiles are
+// independent, as in the column-independent order of Section 3.3.3).
+//
+// Work decomposition (one wave per tile):
+//   strip   W = 64*DT consecutive diagonals k0 .. k0+W-1; lane L owns the DT
+//           diagonals k0 + L*DT + t, t = 0..DT-1 ("slots").
+//   tile    R consecutive rows i0 .. i0+R-1 of one strip; the cross product
+//           of every diagonal is seeded in FP64 at row i0 (so R is also the
+//           reseed interval of the FP32 sweep).
+// At row i every lane handles cells (i, i + k0 + L*DT + t).  The per-row
+// values (a_i, g_i, s_i, u_i) are wave-uniform scalar loads.  Column values
+// move one lane down per row: slot t at row i+1 reads the column slot t+1
+// held at row i, so slots rotate through registers (full unroll by DT) and
+// the last slot receives lane L+1's first slot through a DPP wave shift;
+// lane 63 receives the one new column from a scalar load.  Column minima
+// travel the same way and leave the strip through lane 0.
+//
+// Per cell: key = u_i - (C s_i) s_j  (= 1 - Pearson rho for valid windows),
+// the low CB bits of the key are replaced by the slot's code (its diagonal
+// inside the strip), then one integer min for the column and one for the
+// row; C advances with two FMAs: C += a_j g_i + a_i g_j.
+// Row minima of the 64 lanes are reduced through LDS every TP rows; the
+// winners are merged into global packed (key, index) words with a 64-bit
+// atomic minimum, which is order independent, so results are deterministic.
+#include <climits>
+#include <cmath>
+#include <type_traits>
+
+#include "mp_internal.h"
+#include "mp_types.h"
+
+namespace mpx {
+
+namespace {
+
+constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v >> 1); }
+
+// Lane L receives v from lane L+1; lane 63 receives `fill`.
+__device__ __forceinline__ int shl1(int v, int fill) {
+  return __builtin_amdgcn_update_dpp(fill, v, 0x130 /* wave_shl:1 */, 0xF, 0xF, false);
+}
+__device__ __forceinline__ float shl1f(float v, float fill) {
+  return __int_as_float(shl1(__float_as_int(v), __float_as_int(fill)));
+}
+__device__ __forceinline__ double shl1d(double v, double fill) {
+  const long long b = __double_as_longlong(v), f = __double_as_longlong(fill);
+  const int lo = shl1((int)(b & 0xffffffffll), (int)(f & 0xffffffffll));
+  const int hi = shl1((int)(b >> 32), (int)(f >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ int64_t rfl64(int64_t v) {
+  const int lo = __builtin_amdgcn_readfirstlane((int)(v & 0xffffffff));
+  const int hi = __builtin_amdgcn_readfirstlane((int)(v >> 32));
+  return ((int64_t)hi << 32) | (unsigned int)lo;
+}
+
+// In-wave key handling.  FP32 keys live as int bit patterns so that the
+// minimum is an integer min (order of non-negative floats; the rare tiny
+// negative key of a perfect match sorts below every positive one).
+template <typename F, int CB>
+struct InKey;
+
+template <int CB>
+struct InKey<float, CB> {
+  using K = int;
+  static constexpr int kBig = 0x7F61B1E6;  // 3.0e38f
+  static constexpr unsigned kMask = (1u << CB) - 1u;
+  static __device__ __forceinline__ K make(float key, unsigned code) {
+    return (int)((__float_as_uint(key) & ~kMask) | code);
+  }
+  static __device__ __forceinline__ K kmin(K a, K b) { return min(a, b); }
+  static __device__ __forceinline__ K shl(K v) { return shl1(v, kBig); }
+  static __device__ __forceinline__ unsigned code(K k) { return (unsigned)k & kMask; }
+  static __device__ __forceinline__ double value(K k) {
+    return (double)__uint_as_float((unsigned)k & ~kMask);
+  }
+  static __device__ __forceinline__ K big() { return kBig; }
+};
+
+template <int CB>
+struct InKey<double, CB> {
+  using K = double;
+  static constexpr unsigned kMask = (1u << CB) - 1u;
+  static __device__ __forceinline__ K make(double key, unsigned code) {
+    const long long b = __double_as_longlong(key);
+    const unsigned lo = ((unsigned)(b & 0xffffffffll) & ~kMask) | code;
+    return __longlong_as_double((b & ~0xffffffffll) | lo);
+  }
+  static __device__ __forceinline__ K kmin(K a, K b) { return __builtin_fmin(a, b); }
+  static __device__ __forceinline__ K shl(K v) { return shl1d(v, 1.0e300); }
+  static __device__ __forceinline__ unsigned code(K k) {
+    return (unsigned)(__double_as_longlong(k) & 0xffffffffll) & kMask;
+  }
+  static __device__ __forceinline__ double value(K k) {
+    const long long b = __double_as_longlong(k);
+    return __longlong_as_double(b & ~(long long)kMask);
+  }
+  static __device__ __forceinline__ K big() { return 1.0e300; }
+};
+
+template <typename F>
+__device__ __forceinline__ F shlv(F v, F fill);
+template <>
+__device__ __forceinline__ float shlv<float>(float v, float fill) { return shl1f(v, fill); }
+template <>
+__device__ __forceinline__ double shlv<double>(double v, double fill) { return shl1d(v, fill); }
+
+// Non-finite samples read as 0 (the exponent test keeps working when the
+// translation unit is compiled without NaN semantics).
+__device__ __forceinline__ double clean(float v) {
+  return ((__float_as_uint(v) >> 23) & 0xffu) == 0xffu ? 0.0 : (double)v;
+}
+__device__ __forceinline__ double clean(double v) {
+  return ((__double_as_longlong(v) >> 52) & 0x7ff) == 0x7ff ? 0.0 : v;
+}
+
+// Load of a wave-uniform address through the constant address space, so that
+// it becomes a scalar load (the data was written by an earlier kernel and is
+// read-only here).
+template <typename T>
+__device__ __forceinline__ T ldu(const T *p) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  static_assert(sizeof(T) % 4 == 0, "ldu loads whole dwords");
+  typedef const uint32_t __attribute__((address_space(4))) *cptr;
+  const cptr q = (cptr)(p);
+  T out;
+  uint32_t *o = reinterpret_cast<uint32_t *>(&out);
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(T) / 4); ++i) o[i] = q[i];
+  return out;
+#else
+  return *p;
+#endif
+}
+
+}  // namespace
+
+template <typename F, typename Tin, int DT, int TP>
+__global__ void __launch_bounds__(64)
+    k_sweep(const Plan plan, const typename FTraits<F>::V4 *__restrict__ rcb,
+            const double *__restrict__ mu, const int64_t *__restrict__ seg_prefix,
+            const int32_t *__restrict__ seg_sweep, const SeriesDesc *__restrict__ s_ext,
+            const SweepDesc *__restrict__ w_ext, uint64_t *__restrict__ keys,
+            unsigned long long *__restrict__ counter, const Tin *__restrict__ Tb, const int R,
+            const int64_t total_tiles, const int64_t nseg) {
+  constexpr int W = 64 * DT;
+  constexpr int CB = ilog2c(W);
+  using IK = InKey<F, CB>;
+  using K = typename IK::K;
+  using V4 = typename FTraits<F>::V4;
+
+  __shared__ K lrow[TP][65];
+  __shared__ K lcol[TP];
+
+  const int lane = threadIdx.x;
+  auto series = [&](int i) -> SeriesDesc { return s_ext ? ldu(s_ext + i) : plan.s_inl[i]; };
+  auto sweep = [&](int i) -> SweepDesc { return w_ext ? ldu(w_ext + i) : plan.w_inl[i]; };
+
+  for (;;) {
+    int64_t tile = 0;
+    if (lane == 0) tile = (int64_t)atomicAdd(counter, 1ull);
+    tile = rfl64(tile);
+    if (tile >= total_tiles) break;
+
+    // ---- decode the tile: strip g (binary search of the tile table)
+    int64_t lo = 0, hi = nseg - 1;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi + 1) >> 1;
+      if (ldu(seg_prefix + mid) <= tile) lo = mid; else hi = mid - 1;
+    }
+    const int64_t g = lo;
+    const SweepDesc d = sweep(ldu(seg_sweep + g));
+    const SeriesDesc RS = series(d.rs), CS = series(d.cs);
+    const int64_t k0 = rfl64(d.k_lo + (g - d.seg_base) * (int64_t)W);
+    const int64_t L = min(RS.l, CS.l - k0);
+    const int64_t i0 = rfl64((tile - ldu(seg_prefix + g)) * (int64_t)R);
+    const int64_t nr = min((int64_t)R, L - i0);
+    const int64_t lc = CS.l;
+    const bool full = (nr == R) && (k0 + W - 1 <= d.k_hi) && (i0 + R - 1 + k0 + W - 1 <= lc - 1);
+    const int64_t nsteps = full ? (int64_t)R : ((nr + DT - 1) / DT) * DT;
+    const int m = RS.m;
+
+    uint64_t *rkeys = keys + series(d.rk).w_off;
+    uint64_t *ckeys = keys + series(d.ck).w_off;
+    // wave-uniform bases (made explicit so the row loads stay scalar)
+    const V4 *__restrict__ rowd = rcb + rfl64(RS.rc_off);
+    const V4 *__restrict__ cold = rcb + rfl64(CS.rc_off);
+    const int ib = d.idx_bits;
+
+    // ---- FP64 seed of every slot's diagonal at row i0:
+    // C = sum_u (x_r[i0+u] - mu_r) (x_c[c+u] - mu_c)
+    //   = sum_u (x_r[i0+u] - mu_r) x_c[c+u] - mu_c * sum_u (x_r[i0+u] - mu_r),
+    // evaluated as a sliding product: column sample c0+v meets row sample v-t.
+    const int64_t c0 = i0 + k0 + (int64_t)lane * DT;
+    F C[DT];
+    {
+      const Tin *__restrict__ Tr = Tb + RS.t_off + i0;
+      const Tin *__restrict__ Tc = Tb + CS.t_off;
+      const double mur = ldu(mu + RS.w_off + i0);
+      const int64_t ncol = CS.n;
+      double acc[DT], xr[DT];
+#pragma unroll
+      for (int t = 0; t < DT; ++t) { acc[t] = 0.0; xr[t] = 0.0; }
+      double Sx = 0.0;
+      const int vend = m + DT - 1;
+      for (int vb = 0; vb < vend; vb += DT) {
+#pragma unroll
+        for (int u = 0; u < DT; ++u) {
+          const int v = vb + u;
+          double xn = 0.0;
+          if (v < m) xn = clean(ldu(Tr + v)) - mur;
+          Sx += xn;
+          xr[u] = xn;
+          const int64_t ci = c0 + v;
+          const double y = (ci < ncol) ? clean(Tc[ci]) : 0.0;
+#pragma unroll
+          for (int t = 0; t < DT; ++t) acc[t] = fma(xr[(u - t + DT) % DT], y, acc[t]);
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < DT; ++t) {
+        const int64_t cw = min(c0 + t, lc - 1);
+        C[t] = (F)(acc[t] - mu[CS.w_off + cw] * Sx);
+      }
+    }
+
+    // ---- column window and column minima
+    F A[DT], G[DT], S[DT];
+    K CP[DT];
+    int lim[DT];
+#pragma unroll
+    for (int t = 0; t < DT; ++t) {
+      const V4 v = cold[c0 + t];
+      A[t] = v.x;
+      G[t] = v.y;
+      S[t] = v.z;
+      CP[t] = IK::big();
+      const int64_t kt = k0 + (int64_t)lane * DT + t;
+      const int64_t lm = (kt > d.k_hi) ? -1 : min(nr - 1, lc - 1 - kt - i0);
+      lim[t] = (int)max(lm, (int64_t)-1);
+    }
+
+    auto emit_row = [&](int64_t i, K kb) {
+      const double val = IK::value(kb);
+      if (val < 1.0e30) {
+        const int64_t j = i + k0 + (int64_t)IK::code(kb);
+        atomicMin((unsigned long long *)(rkeys + i), (unsigned long long)pack_global(val, j, ib));
+      }
+    };
+    auto emit_col = [&](int64_t c, K kb) {
+      const double val = IK::value(kb);
+      if (c < lc && val < 1.0e30) {
+        const int64_t i = c - k0 - (int64_t)IK::code(kb);
+        atomicMin((unsigned long long *)(ckeys + c), (unsigned long long)pack_global(val, i, ib));
+      }
+    };
+    // Rows [fb, fb+cnt) of this tile: reduce the 64 lane partials of each
+    // row (one row per lane) and merge; merge the column minima that left
+    // the strip through lane 0 at those rows.
+    auto flush = [&](int64_t fb, int cnt) {
+      __syncthreads();
+      if (lane < cnt) {
+        K best = lrow[lane][0];
+#pragma unroll 8
+        for (int q = 1; q < 64; ++q) best = IK::kmin(best, lrow[lane][q]);
+        const int64_t s = fb + lane;
+        if (s < nr) emit_row(i0 + s, best);
+        emit_col(i0 + s + k0, lcol[lane]);
+      }
+      __syncthreads();
+    };
+
+    auto run = [&](auto masked_tag) {
+      constexpr bool MASKED = decltype(masked_tag)::value;
+      int64_t fb = 0;
+      for (int64_t sb = 0; sb < nsteps; sb += DT) {
+#pragma unroll
+        for (int u = 0; u < DT; ++u) {
+          const int64_t s = sb + u;
+          const int64_t i = i0 + s;
+          const V4 rd = ldu(rowd + i);
+          const F ai = rd.x, gi = rd.y, si = rd.z, ui = rd.w;
+          K rmin = IK::big();
+#pragma unroll
+          for (int t = 0; t < DT; ++t) {
+            const int p = (t + u) % DT;
+            const F key = fma(-(C[p] * si), S[p], ui);
+            K kb = IK::make(key, (unsigned)(lane * DT + t));
+            if (MASKED) kb = ((int)s <= lim[t]) ? kb : IK::big();
+            CP[p] = IK::kmin(CP[p], kb);
+            rmin = IK::kmin(rmin, kb);
+            C[p] = fma(A[p], gi, C[p]);
+            C[p] = fma(G[p], ai, C[p]);
+          }
+          const int slot = (int)(s & (TP - 1));
+          lrow[slot][lane] = rmin;
+          if (lane == 0) lcol[slot] = CP[u];
+          const V4 nc = cold[i + k0 + W];  // lands in VGPRs: feeds the DPP fill
+          CP[u] = IK::shl(CP[u]);
+          A[u] = shlv<F>(A[u], nc.x);
+          G[u] = shlv<F>(G[u], nc.y);
+          S[u] = shlv<F>(S[u], nc.z);
+          if (slot == TP - 1) {
+            flush(fb, TP);
+            fb += TP;
+          }
+        }
+      }
+      if (fb < nsteps) flush(fb, (int)(nsteps - fb));
+    };
+    if (full) run(std::false_type{}); else run(std::true_type{});
+
+    // columns still in flight after the last row: slot t of lane L holds the
+    // minimum of column i0 + nsteps + k0 + L*DT + t
+#pragma unroll
+    for (int t = 0; t < DT; ++t) emit_col(i0 + nsteps + k0 + (int64_t)lane * DT + t, CP[t]);
+  }
+}
+
+int sweep_grid(bool f64_sweep, int slots) {
+  static int cus = -1;
+  if (cus < 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
+    else cus = 256;
+  }
+  int per = 0;
+  hipError_t e;
+  if (f64_sweep)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_sweep<double, float, 8, 16>, 64, 0);
+  else if (slots == 8)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_sweep<float, float, 8, 32>, 64, 0);
+  else
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_sweep<float, float, 16, 32>, 64, 0);
+  if (e != hipSuccess || per <= 0) per = 8;
+  return cus * per;
+}
+
+hipError_t launch_sweep(const Plan &plan, const Work &w, const void *T, bool t_f64, bool f64_sweep,
+                        int slots, int R, int64_t total_tiles, int64_t nseg, int grid,
+                        hipStream_t st) {
+  const dim3 blk(64), grd((unsigned)grid);
+#define MPX_LAUNCH(F, TIN, DT, TP)                                                              \
+  hipLaunchKernelGGL((k_sweep<F, TIN, DT, TP>), grd, blk, 0, st, plan,                         \
+                     (const typename FTraits<F>::V4 *)w.rc, (const double *)w.mu,              \
+                     (const int64_t *)w.seg_prefix, (const int32_t *)w.seg_sweep, plan.s_ext,   \
+                     plan.w_ext, w.keys, w.counters, (const TIN *)T, R, total_tiles, nseg)
+  if (f64_sweep) {
+    if (t_f64) MPX_LAUNCH(double, double, 8, 16);
+    else MPX_LAUNCH(double, float, 8, 16);
+  } else if (slots == 8) {
+    if (t_f64) MPX_LAUNCH(float, double, 8, 32);
+    else MPX_LAUNCH(float, float, 8, 32);
+  } else {
+    if (t_f64) MPX_LAUNCH(float, double, 16, 32);
+    else MPX_LAUNCH(float, float, 16, 32);
+  }
+#undef MPX_LAUNCH
+  return hipGetLastError();
+}
+
+}  // namespace mpx

@@ -1,0 +1,118 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every symbol include/mp.h declares, and rejects bad arguments before it
+touches a device."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1904_12626_amd import _binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mp.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(mp_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_header_and_binding_agree():
+    assert sorted(B.EXPORTS) == _declared()
+
+
+def test_library_exports_every_declared_symbol():
+    lib = B.lib()
+    for name in _declared():
+        assert hasattr(lib, name), name
+    assert lib.mp_abi_version() == 1
+
+
+def test_strerror():
+    lib = B.lib()
+    for s in (0, -1, -2, -3, -4):
+        assert lib.mp_strerror(s)
+
+
+def test_cell_counts():
+    # self-join: (l-ez-1)(l-ez)/2 admissible pairs; AB-join: lA*lB
+    assert B.selfjoin_cells(4096, 64, 16) == 8066136
+    assert B.selfjoin_cells(1 << 20, 256, 64) == 549420844896
+    assert B.abjoin_cells(1 << 19, 1 << 19, 128) == 274744753921
+    assert B.selfjoin_cells(64, 64, 0) == 0
+
+
+def test_workspace_queries():
+    lib = B.lib()
+    opt = B.make_options("f32")
+    assert lib.mp_selfjoin_workspace(4096, 64, B.MP_F32, ctypes.byref(opt)) > 0
+    assert lib.mp_selfjoin_workspace(10, 64, B.MP_F32, ctypes.byref(opt)) == 0   # n < m
+    assert lib.mp_selfjoin_workspace(4096, 1, B.MP_F32, ctypes.byref(opt)) == 0  # m < 2
+    opt16 = B.make_options("f64", tile_slots=16)
+    assert lib.mp_selfjoin_workspace(4096, 64, B.MP_F64, ctypes.byref(opt16)) == 0
+    assert lib.mp_abjoin_workspace(1000, 900, 32, B.MP_F64, None) > 0
+    assert lib.mp_recheck_workspace(1000, 32) >= 969
+
+
+@pytest.mark.parametrize("args,expect", [
+    (dict(n=100, m=1, ez=0), B.MP_EINVAL),
+    (dict(n=10, m=20, ez=0), B.MP_EINVAL),
+    (dict(n=100, m=10, ez=-1), B.MP_EINVAL),
+])
+def test_selfjoin_rejects_bad_sizes(args, expect):
+    lib = B.lib()
+    fake = ctypes.c_void_p(1 << 20)
+    st = lib.mp_selfjoin(fake, args["n"], args["m"], args["ez"], B.MP_F32, None, fake, fake, fake,
+                         1 << 30, None)
+    assert st == expect
+
+
+def test_selfjoin_rejects_null_and_misaligned():
+    lib = B.lib()
+    ok = ctypes.c_void_p(1 << 20)
+    assert lib.mp_selfjoin(None, 100, 10, 2, B.MP_F32, None, ok, ok, ok, 1 << 30, None) == B.MP_EINVAL
+    odd = ctypes.c_void_p((1 << 20) + 2)
+    assert lib.mp_selfjoin(odd, 100, 10, 2, B.MP_F32, None, ok, ok, ok, 1 << 30, None) == B.MP_EINVAL
+    # workspace: null, misaligned, too small
+    assert lib.mp_selfjoin(ok, 100, 10, 2, B.MP_F32, None, ok, ok, None, 1 << 30, None) == B.MP_EWORKSPACE
+    assert lib.mp_selfjoin(ok, 100, 10, 2, B.MP_F32, None, ok, ok, ctypes.c_void_p((1 << 20) + 64), 1 << 30,
+                           None) == B.MP_EWORKSPACE
+    assert lib.mp_selfjoin(ok, 100, 10, 2, B.MP_F32, None, ok, ok, ok, 16, None) == B.MP_EWORKSPACE
+
+
+def test_bad_options():
+    lib = B.lib()
+    ok = ctypes.c_void_p(1 << 20)
+    for opt in (B.mp_options(7, 0, 0, 1), B.mp_options(1, 100, 0, 1), B.mp_options(1, 0, 12, 1),
+                B.mp_options(1, 0, 0, 8)):
+        assert lib.mp_selfjoin(ok, 1000, 10, 2, B.MP_F32, ctypes.byref(opt), ok, ok, ok, 1 << 30,
+                               None) == B.MP_EINVAL
+    opt = B.mp_options(0, 0, 16, 1)
+    assert lib.mp_selfjoin(ok, 1000, 10, 2, B.MP_F64, ctypes.byref(opt), ok, ok, ok, 1 << 30,
+                           None) == B.MP_EUNSUPPORTED
+
+
+def test_batch_plan_host_side():
+    lib = B.lib()
+    off = (ctypes.c_int64 * 4)(0, 100, 350, 1000)
+    m = (ctypes.c_int32 * 3)(8, 16, 32)
+    ez = (ctypes.c_int32 * 3)(2, 4, 8)
+    h = ctypes.c_void_p()
+    assert lib.mp_batch_plan_create(3, off, m, ez, B.MP_F32, None, ctypes.byref(h)) == 0
+    assert lib.mp_batch_plan_profile_length(h) == (100 - 7) + (250 - 15) + (650 - 31)
+    cells = sum(B.selfjoin_cells(n, mm, e) for n, mm, e in ((100, 8, 2), (250, 16, 4), (650, 32, 8)))
+    assert lib.mp_batch_plan_cells(h) == cells
+    assert lib.mp_batch_plan_workspace(h) > 0
+    lib.mp_batch_plan_destroy(h)
+    bad = (ctypes.c_int64 * 4)(0, 100, 90, 1000)   # a series shorter than its window
+    assert lib.mp_batch_plan_create(3, bad, m, ez, B.MP_F32, None, ctypes.byref(h)) == B.MP_EINVAL
+
+
+def test_exclusion_zone_rule():
+    from fractions import Fraction
+    assert B.exclusion_zone(80, Fraction(1, 2)) == 40
+    assert B.exclusion_zone(50, Fraction(1, 4)) == 13
+    assert B.exclusion_zone(64, 0.25) == 16

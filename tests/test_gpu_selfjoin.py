@@ -1,0 +1,131 @@
+"""GPU parity of the self-join against the FP64 oracle (through the C ABI)."""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import cimpl
+from oracle import mp_oracle as O
+from tests.parity import compare_profile
+from workloads import random_walk, selfjoin_small
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _run(T, m, ez, precision, slots=0, reseed=0, finalize=True):
+    import paper_1904_12626_amd as mpx
+    Tg = torch.from_numpy(np.ascontiguousarray(T)).to(DEV)
+    P, I = mpx.selfjoin(Tg, m, ez, precision=precision, tile_slots=slots, reseed_rows=reseed,
+                        fp64_finalize=finalize)
+    torch.cuda.synchronize()
+    return P.cpu().numpy(), I.cpu().numpy()
+
+
+def test_dpp_wave_shift_direction():
+    """The sweep moves column data with a DPP wave shift: lane L must read
+    lane L+1 (checked here through a tiny join whose answer depends on it)."""
+    T = random_walk(700, 3, np.float64)
+    P, I = _run(T, 16, 4, "f64")
+    Po, Io = cimpl.selfjoin(T, 16, 4)
+    compare_profile(T, 16, P, I, Po, Io, 1e-9, ez=4, where="dpp")
+
+
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-9), ("f32", 1e-3 * 8.0)])
+def test_selfjoin_small_random_walk(precision, tol):
+    """n=4096 float64 random walk, m=64, ez=16: full oracle."""
+    T, m, ez = selfjoin_small()
+    P, I = _run(T, m, ez, precision)
+    Po, Io = cimpl.selfjoin(T, m, ez)
+    maxd, nd = compare_profile(T, m, P, I, Po, Io, tol, ez=ez, where=precision)
+    print(f"{precision}: max|dP|={maxd:.3e}, index differences (ties) {nd}")
+
+
+@pytest.mark.parametrize("n,m,ez,dtype,precision,slots", [
+    (300, 7, 1, np.float64, "f64", 8),
+    (1000, 2, 0, np.float64, "f64", 8),
+    (2500, 33, 8, np.float32, "f32", 8),
+    (2500, 33, 8, np.float32, "f32", 16),
+    (5000, 100, 25, np.float32, "f64", 8),
+    (1300, 64, 16, np.float64, "f32", 16),
+    (129, 64, 16, np.float64, "f64", 8),
+    (64, 64, 0, np.float64, "f64", 8),        # one window: no neighbour
+    (90, 64, 26, np.float64, "f32", 8),       # l = 27 = ez + 1: no neighbour
+    (91, 64, 26, np.float64, "f32", 8),       # l = 28: exactly one admissible pair
+])
+def test_selfjoin_shapes(n, m, ez, dtype, precision, slots):
+    T = random_walk(n, n * 7 + m, dtype)
+    tol = 1e-9 if precision == "f64" else 1e-3 * np.sqrt(m)
+    P, I = _run(T, m, ez, precision, slots)
+    Po, Io = cimpl.selfjoin(T.astype(np.float64), m, ez)
+    compare_profile(T.astype(np.float64), m, P, I, Po, Io, tol, ez=ez, where=f"{n},{m},{ez}")
+
+
+@pytest.mark.parametrize("reseed", [64, 256, 1024])
+def test_tiling_does_not_change_the_answer(reseed):
+    """Traversal order is free (the paper's modes return equal results): other
+    tile heights give the same P and, up to ties, the same I."""
+    T, m, ez = selfjoin_small()
+    P, I = _run(T, m, ez, "f64", reseed=reseed)
+    P0, I0 = _run(T, m, ez, "f64")
+    np.testing.assert_allclose(P, P0, atol=1e-9)
+    Po, Io = cimpl.selfjoin(T, m, ez)
+    compare_profile(T, m, P, I, Po, Io, 1e-9, ez=ez)
+
+
+def test_raw_key_profile_without_fp64_finalize():
+    T, m, ez = selfjoin_small()
+    P, I = _run(T, m, ez, "f32", finalize=False)
+    Po, Io = cimpl.selfjoin(T, m, ez)
+    compare_profile(T, m, P, I, Po, Io, 1e-3 * np.sqrt(m), ez=ez)
+
+
+def test_deterministic_reruns():
+    T = random_walk(20000, 11, np.float32)
+    a = _run(T, 128, 32, "f32")
+    b = _run(T, 128, 32, "f32")
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_affine_invariance_large_offset():
+    """P(aT + b) = P(T); b = 1e6 stresses the FP32 sweep (the series itself
+    is first rounded to float32, the oracle sees the same values)."""
+    T = random_walk(6000, 17, np.float64)
+    m, ez = 50, 13
+    T2 = (-0.5 * T + 1e6).astype(np.float32).astype(np.float64)
+    P, I = _run(T2, m, ez, "f32")
+    Po, Io = cimpl.selfjoin(T2, m, ez)
+    compare_profile(T2, m, P, I, Po, Io, 1e-3 * np.sqrt(m), ez=ez)
+
+
+def test_constant_and_nonfinite_windows():
+    rng = np.random.default_rng(8)
+    m, ez = 16, 4
+    T = np.cumsum(rng.standard_normal(3000))
+    T[500:500 + 2 * m] = 2.0          # constant windows
+    T[1500:1500 + m + 3] = -7.0       # more constant windows
+    T[2200] = np.nan                  # invalid windows
+    T[2600] = np.inf
+    for prec in ("f64", "f32"):
+        P, I = _run(T, m, ez, prec)
+        Po, Io = O.selfjoin(T, m, ez)
+        compare_profile(T, m, P, I, Po, Io, 1e-9 if prec == "f64" else 1e-3 * np.sqrt(m), ez=ez,
+                        where=prec)
+
+
+def test_invalid_neighbour_rescan():
+    """A row whose best valid correlation is negative must not pick an
+    invalid window (exact rescan path)."""
+    m, ez = 4, 1
+    T = np.array([0, 1, 0, 1, 0, 1, 0, 1, np.nan, 5, 2, 9, 1, 3, 0, 8], dtype=np.float64)
+    P, I = _run(T, m, ez, "f64")
+    Po, Io = O.selfjoin(T, m, ez)
+    compare_profile(T, m, P, I, Po, Io, 1e-9, ez=ez)
+
+
+def test_sine_profile_is_zero():
+    t = np.arange(4000)
+    T = np.sin(2 * np.pi * t / 97)
+    P, I = _run(T, 64, 16, "f32")
+    assert np.max(P) < 1e-3
