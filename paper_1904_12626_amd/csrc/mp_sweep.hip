@@ -288,14 +288,16 @@ __global__ void __launch_bounds__(64)
           K rmin = IK::big();
 #pragma unroll
           for (int t = 0; t < DT; ++t) {
+            // slot t is a fixed diagonal (C[t], its code, its limit); the
+            // column it meets moves one register per row (p)
             const int p = (t + u) % DT;
-            const F key = fma(-(C[p] * si), S[p], ui);
+            const F key = fma(-(C[t] * si), S[p], ui);
             K kb = IK::make(key, (unsigned)(lane * DT + t));
             if (MASKED) kb = ((int)s <= lim[t]) ? kb : IK::big();
             CP[p] = IK::kmin(CP[p], kb);
             rmin = IK::kmin(rmin, kb);
-            C[p] = fma(A[p], gi, C[p]);
-            C[p] = fma(G[p], ai, C[p]);
+            C[t] = fma(A[p], gi, C[t]);
+            C[t] = fma(G[p], ai, C[t]);
           }
           const int slot = (int)(s & (TP - 1));
           lrow[slot][lane] = rmin;

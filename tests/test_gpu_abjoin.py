@@ -1,0 +1,82 @@
+"""GPU parity of the AB-join (both directions) against the FP64 oracle."""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import cimpl
+from oracle import mp_oracle as O
+from tests.parity import compare_profile
+from workloads import ecg_like, random_walk
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _run(A, B, m, precision, slots=0):
+    import paper_1904_12626_amd as mpx
+    Ag = torch.from_numpy(np.ascontiguousarray(A)).to(DEV)
+    Bg = torch.from_numpy(np.ascontiguousarray(B)).to(DEV)
+    out = mpx.abjoin(Ag, Bg, m, precision=precision, tile_slots=slots)
+    torch.cuda.synchronize()
+    return [x.cpu().numpy() for x in out]
+
+
+@pytest.mark.parametrize("nA,nB,m,precision,slots", [
+    (3000, 2500, 50, "f64", 8),
+    (2500, 3000, 50, "f32", 8),
+    (4000, 700, 64, "f32", 16),
+    (700, 4000, 64, "f64", 8),
+    (64, 64, 64, "f64", 8),
+    (300, 2000, 2, "f32", 8),
+])
+def test_abjoin_random_walks(nA, nB, m, precision, slots):
+    A = random_walk(nA, nA + 1, np.float64)
+    B = random_walk(nB, nB + 2, np.float64)
+    Pab, Iab, Pba, Iba = _run(A, B, m, precision, slots)
+    tol = 1e-9 if precision == "f64" else 1e-3 * np.sqrt(m)
+    Po, Io = cimpl.abjoin_rows(A, B, m, np.arange(nA - m + 1))
+    compare_profile(A, m, Pab, Iab, Po, Io, tol, TB=B, where="ab")
+    Po, Io = cimpl.abjoin_rows(B, A, m, np.arange(nB - m + 1))
+    compare_profile(B, m, Pba, Iba, Po, Io, tol, TB=A, where="ba")
+    assert abs(np.min(Pab) - np.min(Pba)) <= tol
+
+
+def test_abjoin_ecg_like():
+    A = ecg_like(6000, 31, np.float32)
+    B = ecg_like(5000, 32, np.float32)
+    m = 128
+    Pab, Iab, Pba, Iba = _run(A, B, m, "f32")
+    tol = 1e-3 * np.sqrt(m)
+    A64, B64 = A.astype(np.float64), B.astype(np.float64)
+    rows = np.random.default_rng(0).choice(A.size - m + 1, 300, replace=False)
+    Po, Io = cimpl.abjoin_rows(A64, B64, m, rows)
+    compare_profile(A64, m, Pab[rows], Iab[rows], Po, Io, tol, TB=B64)
+    # compare_profile works row by row on the listed rows only
+    cols = np.random.default_rng(1).choice(B.size - m + 1, 300, replace=False)
+    Po, Io = cimpl.abjoin_rows(B64, A64, m, cols)
+    Pc, Ic = Pba[cols], Iba[cols]
+    assert np.max(np.abs(Pc - Po)) <= tol or np.all(
+        [O.pair_distance(B64, int(c), A64, int(j), m) <= p + tol for c, j, p in zip(cols, Ic, Po)])
+
+
+def test_abjoin_with_itself_finds_identity():
+    A = random_walk(3000, 9, np.float64)
+    Pab, Iab, Pba, Iba = _run(A, A.copy(), 40, "f32")
+    assert np.max(Pab) < 1e-3 and np.max(Pba) < 1e-3
+    np.testing.assert_array_equal(Iab, np.arange(Iab.size))
+    np.testing.assert_array_equal(Iba, np.arange(Iba.size))
+
+
+def test_abjoin_degenerate_windows():
+    rng = np.random.default_rng(3)
+    m = 12
+    A = np.cumsum(rng.standard_normal(900))
+    B = np.cumsum(rng.standard_normal(800))
+    A[100:130] = 1.0
+    B[400:420] = -3.0
+    B[600] = np.nan
+    Pab, Iab, Pba, Iba = _run(A, B, m, "f64")
+    Po, Io, Po2, Io2 = O.abjoin(A, B, m)
+    compare_profile(A, m, Pab, Iab, Po, Io, 1e-9, TB=B)
+    compare_profile(B, m, Pba, Iba, Po2, Io2, 1e-9, TB=A)

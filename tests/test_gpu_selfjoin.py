@@ -57,6 +57,8 @@ def test_selfjoin_small_random_walk(precision, tol):
 def test_selfjoin_shapes(n, m, ez, dtype, precision, slots):
     T = random_walk(n, n * 7 + m, dtype)
     tol = 1e-9 if precision == "f64" else 1e-3 * np.sqrt(m)
+    if dtype == np.float32:   # P is returned in the input dtype
+        tol = max(tol, 2.0 ** -23 * 2 * np.sqrt(m))
     P, I = _run(T, m, ez, precision, slots)
     Po, Io = cimpl.selfjoin(T.astype(np.float64), m, ez)
     compare_profile(T.astype(np.float64), m, P, I, Po, Io, tol, ez=ez, where=f"{n},{m},{ez}")
@@ -115,13 +117,19 @@ def test_constant_and_nonfinite_windows():
 
 
 def test_invalid_neighbour_rescan():
-    """A row whose best valid correlation is negative must not pick an
-    invalid window (exact rescan path)."""
-    m, ez = 4, 1
-    T = np.array([0, 1, 0, 1, 0, 1, 0, 1, np.nan, 5, 2, 9, 1, 3, 0, 8], dtype=np.float64)
-    P, I = _run(T, m, ez, "f64")
+    """A row whose every admissible valid neighbour is anti-correlated
+    (P > sqrt(2m)) must not pick an invalid window: the sweep scores pairs
+    with an invalid column like rho = 0, so such rows go through the exact
+    rescan."""
+    m, ez = 3, 1
+    rng = np.random.default_rng(0)
+    T = rng.standard_normal(10)
+    T[int(rng.integers(3, 9))] = np.nan
     Po, Io = O.selfjoin(T, m, ez)
-    compare_profile(T, m, P, I, Po, Io, 1e-9, ez=ez)
+    assert Po[0] > np.sqrt(2 * m)          # the case this test is about
+    for prec in ("f64", "f32"):
+        P, I = _run(T, m, ez, prec)
+        compare_profile(T, m, P, I, Po, Io, 1e-9 if prec == "f64" else 1e-3 * np.sqrt(m), ez=ez)
 
 
 def test_sine_profile_is_zero():
