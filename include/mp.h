@@ -174,6 +174,17 @@ mp_status mp_recheck(const void *T, int64_t n, int32_t m, mp_dtype dtype, const 
                      const int64_t *I, int32_t k_motifs, int32_t k_discords, int64_t *out_idx,
                      double *out_dist, void *ws, size_t ws_bytes, void *stream);
 
+/* ------------------------------------------------------------------ timing
+ * Kernel timing for benchmarks.  While enabled, every mp_selfjoin, mp_abjoin
+ * and mp_batch call also records HIP events on its stream around the sweep
+ * kernel and around its whole launch sequence.  mp_timing_query waits for
+ * the recorded events, returns the summed durations (milliseconds) and the
+ * number of calls since the last query, then clears the record.  Host-side
+ * state of the process; not for use under stream capture.
+ */
+mp_status mp_timing_enable(int enable);
+mp_status mp_timing_query(double *sweep_ms, double *total_ms, int64_t *calls);
+
 /* --------------------------------------------------------------- helpers */
 const char *mp_strerror(mp_status status);
 int mp_abi_version(void);

@@ -14,7 +14,7 @@ package computes it with hand-written HIP kernels behind a C ABI
 
 from ._binding import (  # noqa: F401
     EXPORTS, LIB_PATH, MPError, BatchPlan, abjoin, abjoin_cells, exclusion_zone, lib, make_options,
-    recheck, selfjoin, selfjoin_cells,
+    recheck, selfjoin, selfjoin_cells, timing_enable, timing_query,
 )
 from .autograd import MatrixProfileFn, matrix_profile  # noqa: F401
 

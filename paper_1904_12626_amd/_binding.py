@@ -28,7 +28,7 @@ EXPORTS = (
     "mp_batch_plan_create", "mp_batch_plan_workspace", "mp_batch_plan_profile_length",
     "mp_batch_plan_cells", "mp_batch_plan_upload", "mp_batch", "mp_batch_plan_destroy",
     "mp_backward", "mp_recheck_workspace", "mp_recheck", "mp_strerror", "mp_abi_version",
-    "mp_selfjoin_cells", "mp_abjoin_cells",
+    "mp_selfjoin_cells", "mp_abjoin_cells", "mp_timing_enable", "mp_timing_query",
 )
 
 
@@ -77,6 +77,9 @@ def lib():
         "mp_abi_version": (ctypes.c_int, []),
         "mp_selfjoin_cells": (i64, [i64, i32, i32]),
         "mp_abjoin_cells": (i64, [i64, i64, i32]),
+        "mp_timing_enable": (ctypes.c_int, [ctypes.c_int]),
+        "mp_timing_query": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                           ctypes.POINTER(ctypes.c_int64)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -281,6 +284,19 @@ def recheck(T: torch.Tensor, m: int, P: torch.Tensor, I: torch.Tensor, k_motifs:
                                       k_motifs, k_discords, _ptr(out_idx), _ptr(out_dist), _ptr(ws),
                                       ws.numel(), _stream(stream)))
     return out_idx, out_dist
+
+
+def timing_enable(on: bool = True):
+    """Record HIP events around the sweep kernel and the whole launch
+    sequence of every join call (benchmark use)."""
+    _check("mp_timing_enable", lib().mp_timing_enable(1 if on else 0))
+
+
+def timing_query():
+    """(sweep_ms, total_ms, calls) summed over the calls since the last query."""
+    a, b, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
+    _check("mp_timing_query", lib().mp_timing_query(ctypes.byref(a), ctypes.byref(b), ctypes.byref(n)))
+    return a.value, b.value, n.value
 
 
 def selfjoin_cells(n: int, m: int, ez: int) -> int:

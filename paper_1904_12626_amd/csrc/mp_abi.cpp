@@ -215,6 +215,25 @@ mpx::Plan plan_of(const Job &j, const Layout &L, void *ws, bool external) {
 }
 
 bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+// Benchmark timing: event quadruples (start, sweep start, sweep end, end) per
+// call, recycled after each query.
+struct Timing {
+  bool on = false;
+  std::vector<hipEvent_t> pool;   // free events
+  std::vector<hipEvent_t> rec;    // 4 per recorded call
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+};
+Timing g_timing;
 size_t esize(mp_dtype dt) { return dt == MP_F64 ? 8 : 4; }
 
 mp_status check_ws(void *ws, size_t ws_bytes, size_t need) {
@@ -227,20 +246,31 @@ mp_status check_ws(void *ws, size_t ws_bytes, size_t need) {
 mp_status run_job(const Job &j, const mpx::Plan &plan, const mpx::Work &w, const void *T,
                   const mpx::Outputs &o, bool out_f64, hipStream_t st) {
   const Options &op = j.opt;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  if (g_timing.on) {
+    for (auto &e : ev) e = g_timing.get();
+    if (ev[0]) (void)hipEventRecord(ev[0], st);
+  }
   if (mpx::launch_plan(plan, w, j.W, j.R, j.nseg, st) != hipSuccess) return MP_ELAUNCH;
   if (mpx::launch_stats(plan, w, T, j.t_f64, op.f64, j.total_rc, st) != hipSuccess) return MP_ELAUNCH;
+  if (ev[1]) (void)hipEventRecord(ev[1], st);
   if (j.tiles > 0) {
     const int grid = (int)std::min<int64_t>(j.tiles, mpx::sweep_grid(op.f64, op.slots));
     if (mpx::launch_sweep(plan, w, T, j.t_f64, op.f64, op.slots, j.R, j.tiles, j.nseg, grid, st) !=
         hipSuccess)
       return MP_ELAUNCH;
   }
+  if (ev[2]) (void)hipEventRecord(ev[2], st);
   if (mpx::launch_special(plan, w, st) != hipSuccess) return MP_ELAUNCH;
   if (mpx::launch_finalize(plan, w, T, j.t_f64, o, out_f64, op.fp64_finalize, j.total_l, st) !=
       hipSuccess)
     return MP_ELAUNCH;
   if (mpx::launch_rescan(plan, w, T, j.t_f64, o, out_f64, op.fp64_finalize, st) != hipSuccess)
     return MP_ELAUNCH;
+  if (g_timing.on) {
+    if (ev[3]) (void)hipEventRecord(ev[3], st);
+    for (auto &e : ev) g_timing.rec.push_back(e);
+  }
   return MP_OK;
 }
 
@@ -443,6 +473,37 @@ mp_status mp_batch(const mp_batch_plan *pl, const void *T_cat, void *P_cat, int6
 }
 
 void mp_batch_plan_destroy(mp_batch_plan *pl) { delete pl; }
+
+mp_status mp_timing_enable(int enable) {
+  g_timing.on = enable != 0;
+  return MP_OK;
+}
+
+mp_status mp_timing_query(double *sweep_ms, double *total_ms, int64_t *calls) {
+  double sw = 0.0, tot = 0.0;
+  int64_t n = 0;
+  mp_status st = MP_OK;
+  for (size_t q = 0; q + 3 < g_timing.rec.size(); q += 4) {
+    hipEvent_t *e = &g_timing.rec[q];
+    float a = 0.f, b = 0.f;
+    if (e[0] && e[1] && e[2] && e[3] && hipEventSynchronize(e[3]) == hipSuccess &&
+        hipEventElapsedTime(&a, e[1], e[2]) == hipSuccess &&
+        hipEventElapsedTime(&b, e[0], e[3]) == hipSuccess) {
+      sw += a;
+      tot += b;
+      ++n;
+    } else {
+      st = MP_ELAUNCH;
+    }
+    for (int k = 0; k < 4; ++k)
+      if (e[k]) g_timing.pool.push_back(e[k]);
+  }
+  g_timing.rec.clear();
+  if (sweep_ms) *sweep_ms = sw;
+  if (total_ms) *total_ms = tot;
+  if (calls) *calls = n;
+  return st;
+}
 
 mp_status mp_backward(const mp_batch_plan *pl, const void *T_cat, const int64_t *I_cat,
                       const void *gP_cat, void *gT_cat, void *ws, size_t ws_bytes, void *stream) {
