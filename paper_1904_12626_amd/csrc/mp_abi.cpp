@@ -89,7 +89,8 @@ void add_sweep(Job &j, int rs, int cs, int rk, int ck, int64_t k_lo, int64_t k_h
   d.ck = ck;
   d.k_lo = k_lo;
   d.k_hi = k_hi;
-  d.idx_bits = bits_for(std::max(j.series[rk].l, j.series[ck].l));
+  // one spare index value, all ones, marks a minimum outside the series
+  d.idx_bits = bits_for(std::max(j.series[rk].l, j.series[ck].l) + 1);
   d.nseg = 0;
   j.sweeps.push_back(d);
 }

@@ -88,9 +88,9 @@ __device__ __forceinline__ void store_out(const Outputs &o, const SeriesDesc &S,
 //  * valid window whose partner series has constant windows: the smallest
 //    admissible constant partner at distance sqrt(m) competes (the sweep
 //    scores such pairs too high);
-//  * if the chosen partner is invalid (the sweep scores pairs with an
-//    invalid column window like rho = 0), the window is queued for an exact
-//    rescan.
+//  * if the chosen partner is invalid or past the end of the partner series
+//    (the sweep scores such columns like rho = 0), the window is queued for
+//    an exact rescan.
 template <typename Tin, typename Tout>
 __global__ void __launch_bounds__(256) k_finalize(Plan plan, Work wk, const Tin *__restrict__ Tb,
                                                   Outputs o, int fp64_finalize, int64_t total_l) {
@@ -106,7 +106,7 @@ __global__ void __launch_bounds__(256) k_finalize(Plan plan, Work wk, const Tin 
     return;
   }
   int ib = 1;
-  while (((int64_t)1 << ib) < max(S.l, Q.l)) ++ib;
+  while (((int64_t)1 << ib) < max(S.l, Q.l) + 1) ++ib;
   const uint64_t key = wk.keys[wi];
   double val = INFINITY;
   int64_t idx = -1;
@@ -139,7 +139,7 @@ __global__ void __launch_bounds__(256) k_finalize(Plan plan, Work wk, const Tin 
       idx = jc;
     }
   }
-  if ((sp & 1) && idx >= 0 && !(wk.flags[Q.w_off + idx] & 1)) {
+  if (idx >= Q.l || ((sp & 1) && idx >= 0 && !(wk.flags[Q.w_off + idx] & 1))) {
     const unsigned long long pos = atomicAdd(&wk.counters[1], 1ull);
     wk.rescan[pos] = wi;
     store_out<Tout>(o, S, w, INFINITY, -1);

@@ -91,8 +91,11 @@ __global__ void __launch_bounds__(256) k_stats(Plan plan, Work w, const Tin *__r
   const int64_t i = r - S.rc_off;
   using V4 = typename FTraits<F>::V4;
   V4 *rc = reinterpret_cast<V4 *>(w.rc);
-  if (i >= S.l) {  // padding
-    rc[r] = FTraits<F>::zero4();
+  if (i >= S.l) {
+    // padding past the last window: as a row its huge u makes every key
+    // huge (never a minimum); as a column its s = 0 scores like rho = 0, and
+    // a row whose minimum lands there is rescanned exactly (k_finalize)
+    rc[r] = FTraits<F>::pad4();
     return;
   }
   const Tin *x = Tb + S.t_off + i;

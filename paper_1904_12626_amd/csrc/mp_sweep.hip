@@ -29,6 +29,7 @@
 #include <climits>
 #include <cmath>
 #include <type_traits>
+#include <utility>
 
 #include "mp_internal.h"
 #include "mp_types.h"
@@ -39,9 +40,15 @@ namespace {
 
 constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v >> 1); }
 
-// Lane L receives v from lane L+1; lane 63 receives `fill`.
+// In-place wave shift: lane L receives v from lane L+1, then lane 63 takes
+// `fill` (a wave-uniform value) with one v_writelane_b32 (a VALU register
+// write, no memory access).  Keeping source and destination in one register
+// lets every rotating slot stay in a fixed register across the unrolled rows.
 __device__ __forceinline__ int shl1(int v, int fill) {
-  return __builtin_amdgcn_update_dpp(fill, v, 0x130 /* wave_shl:1 */, 0xF, 0xF, false);
+  int x = __builtin_amdgcn_update_dpp(v, v, 0x130 /* wave_shl:1 */, 0xF, 0xF, false);
+  fill = __builtin_amdgcn_readfirstlane(fill);
+  asm volatile("v_writelane_b32 %0, %1, 63" : "+v"(x) : "s"(fill));
+  return x;
 }
 __device__ __forceinline__ float shl1f(float v, float fill) {
   return __int_as_float(shl1(__float_as_int(v), __float_as_int(fill)));
@@ -119,6 +126,16 @@ __device__ __forceinline__ double clean(double v) {
   return ((__double_as_longlong(v) >> 52) & 0x7ff) == 0x7ff ? 0.0 : v;
 }
 
+// Compile-time loop: f(integral_constant<int, 0..N-1>), fully expanded.
+template <typename Fn, int... Ts>
+__device__ __forceinline__ void static_for_impl(Fn &&f, std::integer_sequence<int, Ts...>) {
+  (f(std::integral_constant<int, Ts>{}), ...);
+}
+template <int N, typename Fn>
+__device__ __forceinline__ void static_for(Fn &&f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
 // Load of a wave-uniform address through the constant address space, so that
 // it becomes a scalar load (the data was written by an earlier kernel and is
 // read-only here).
@@ -181,8 +198,11 @@ __global__ void __launch_bounds__(64)
     const int64_t i0 = rfl64((tile - ldu(seg_prefix + g)) * (int64_t)R);
     const int64_t nr = min((int64_t)R, L - i0);
     const int64_t lc = CS.l;
-    const bool full = (nr == R) && (k0 + W - 1 <= d.k_hi) && (i0 + R - 1 + k0 + W - 1 <= lc - 1);
-    const int64_t nsteps = full ? (int64_t)R : ((nr + DT - 1) / DT) * DT;
+    // Cells outside the join read padding records: rows >= l_r give huge
+    // keys; columns >= l_c score like rho = 0 and, should such a column be a
+    // row's minimum, it is reported with an out-of-range index that sends the
+    // row to the exact rescan.  So the last tile of a strip runs the same code.
+    const int64_t nsteps = ((nr + DT - 1) / DT) * DT;
     const int m = RS.m;
 
     uint64_t *rkeys = keys + series(d.rk).w_off;
@@ -232,7 +252,6 @@ __global__ void __launch_bounds__(64)
     // ---- column window and column minima
     F A[DT], G[DT], S[DT];
     K CP[DT];
-    int lim[DT];
 #pragma unroll
     for (int t = 0; t < DT; ++t) {
       const V4 v = cold[c0 + t];
@@ -240,15 +259,16 @@ __global__ void __launch_bounds__(64)
       G[t] = v.y;
       S[t] = v.z;
       CP[t] = IK::big();
-      const int64_t kt = k0 + (int64_t)lane * DT + t;
-      const int64_t lm = (kt > d.k_hi) ? -1 : min(nr - 1, lc - 1 - kt - i0);
-      lim[t] = (int)max(lm, (int64_t)-1);
     }
+    // the one new column per row (entering at lane 63) is a scalar load
+    const V4 *__restrict__ newcol = cold + (k0 + W + i0);
 
+    const int64_t past = ((int64_t)1 << ib) - 1;  // never a window index
     auto emit_row = [&](int64_t i, K kb) {
       const double val = IK::value(kb);
       if (val < 1.0e30) {
-        const int64_t j = i + k0 + (int64_t)IK::code(kb);
+        int64_t j = i + k0 + (int64_t)IK::code(kb);
+        if (j >= lc) j = past;
         atomicMin((unsigned long long *)(rkeys + i), (unsigned long long)pack_global(val, j, ib));
       }
     };
@@ -275,52 +295,47 @@ __global__ void __launch_bounds__(64)
       __syncthreads();
     };
 
-    auto run = [&](auto masked_tag) {
-      constexpr bool MASKED = decltype(masked_tag)::value;
-      int64_t fb = 0;
-      for (int64_t sb = 0; sb < nsteps; sb += DT) {
-#pragma unroll
-        for (int u = 0; u < DT; ++u) {
+    for (int64_t sb = 0; sb < nsteps; sb += TP) {
+      const int nb = (int)min((int64_t)TP, nsteps - sb);  // a multiple of DT
+      static_for<TP>([&](auto uc) {
+        constexpr int u = decltype(uc)::value;
+        constexpr int r = u % DT;  // rotation of the column slots
+        if (u < nb) {
           const int64_t s = sb + u;
           const int64_t i = i0 + s;
           const V4 rd = ldu(rowd + i);
           const F ai = rd.x, gi = rd.y, si = rd.z, ui = rd.w;
           K rmin = IK::big();
-#pragma unroll
-          for (int t = 0; t < DT; ++t) {
-            // slot t is a fixed diagonal (C[t], its code, its limit); the
-            // column it meets moves one register per row (p)
-            const int p = (t + u) % DT;
+          static_for<DT>([&](auto tc) {
+            // slot t is a fixed diagonal (C[t] and its code); the column it
+            // meets moves one register per row (p)
+            constexpr int t = decltype(tc)::value;
+            constexpr int p = (t + r) % DT;
             const F key = fma(-(C[t] * si), S[p], ui);
-            K kb = IK::make(key, (unsigned)(lane * DT + t));
-            if (MASKED) kb = ((int)s <= lim[t]) ? kb : IK::big();
+            const K kb = IK::make(key, (unsigned)(lane * DT + t));
             CP[p] = IK::kmin(CP[p], kb);
             rmin = IK::kmin(rmin, kb);
             C[t] = fma(A[p], gi, C[t]);
             C[t] = fma(G[p], ai, C[t]);
-          }
-          const int slot = (int)(s & (TP - 1));
-          lrow[slot][lane] = rmin;
-          if (lane == 0) lcol[slot] = CP[u];
-          const V4 nc = cold[i + k0 + W];  // lands in VGPRs: feeds the DPP fill
-          CP[u] = IK::shl(CP[u]);
-          A[u] = shlv<F>(A[u], nc.x);
-          G[u] = shlv<F>(G[u], nc.y);
-          S[u] = shlv<F>(S[u], nc.z);
-          if (slot == TP - 1) {
-            flush(fb, TP);
-            fb += TP;
-          }
+          });
+          lrow[u][lane] = rmin;
+          if (lane == 0) lcol[u] = CP[r];
+          const V4 nc = ldu(newcol + s);
+          CP[r] = IK::shl(CP[r]);
+          A[r] = shlv<F>(A[r], nc.x);
+          G[r] = shlv<F>(G[r], nc.y);
+          S[r] = shlv<F>(S[r], nc.z);
         }
-      }
-      if (fb < nsteps) flush(fb, (int)(nsteps - fb));
-    };
-    if (full) run(std::false_type{}); else run(std::true_type{});
+      });
+      flush(sb, nb);
+    }
 
     // columns still in flight after the last row: slot t of lane L holds the
     // minimum of column i0 + nsteps + k0 + L*DT + t
-#pragma unroll
-    for (int t = 0; t < DT; ++t) emit_col(i0 + nsteps + k0 + (int64_t)lane * DT + t, CP[t]);
+    static_for<DT>([&](auto tc) {
+      constexpr int t = decltype(tc)::value;
+      emit_col(i0 + nsteps + k0 + (int64_t)lane * DT + t, CP[t]);
+    });
   }
 }
 

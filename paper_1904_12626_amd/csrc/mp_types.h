@@ -18,6 +18,9 @@ template <>
 struct FTraits<float> {
   using V4 = float4;
   static __device__ __forceinline__ V4 zero4() { return make_float4(0.f, 0.f, 0.f, 0.f); }
+  // padding record: a = g = s = 0 and a huge finite u (see k_stats); finite,
+  // so that writing a code into its low mantissa bits cannot make a NaN
+  static __device__ __forceinline__ V4 pad4() { return make_float4(0.f, 0.f, 0.f, 3.0e38f); }
   static __device__ __forceinline__ V4 make4(double a, double b, double c, double d) {
     return make_float4((float)a, (float)b, (float)c, (float)d);
   }
@@ -27,6 +30,7 @@ template <>
 struct FTraits<double> {
   using V4 = Double4;
   static __device__ __forceinline__ V4 zero4() { return Double4{0.0, 0.0, 0.0, 0.0}; }
+  static __device__ __forceinline__ V4 pad4() { return Double4{0.0, 0.0, 0.0, 1.0e300}; }
   static __device__ __forceinline__ V4 make4(double a, double b, double c, double d) {
     return Double4{a, b, c, d};
   }
