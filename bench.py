@@ -43,6 +43,23 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def measured_traffic():
+    """HBM bytes per sweep launch from the committed rocprofv3 counter runs
+    (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the sweep
+    source has changed since they were taken."""
+    import hashlib
+    rec = os.path.join(ROOT, "profiles", "k_sweep_f32_traffic.json")
+    src = os.path.join(ROOT, "paper_1904_12626_amd", "csrc", "mp_sweep.hip")
+    try:
+        with open(rec) as f:
+            r = json.load(f)
+        with open(src, "rb") as f:
+            h = hashlib.sha256(f.read()).hexdigest()
+    except OSError:
+        return None
+    return r["traffic_bytes_per_launch"] if r.get("sweep_source_sha256") == h else None
+
+
 def workload(name: str, n_override=None):
     import workloads as W
     if name == "selfjoin_large":
@@ -74,6 +91,9 @@ def main():
     ap.add_argument("--reseed", type=int, default=0, help="rows per tile / reseed interval (0 = automatic)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU path comparison")
     ap.add_argument("--cpu-rows", type=int, default=256, help="oracle rows timed for the CPU baseline (0 = skip)")
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="first run one plain device copy of this many MiB (a known-traffic reference "
+                         "for hardware byte counters)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -89,6 +109,15 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
     dev = torch.device("cuda:0")
+    if args.copy_calib_mib > 0:
+        nb = args.copy_calib_mib << 20
+        src = torch.ones(nb // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copy calibration: {nb} bytes read, {nb} bytes written")
+        del src, dst
     wl = workload(args.workload, args.n)
     m = wl["m"]
     stream = torch.cuda.current_stream()
@@ -150,7 +179,9 @@ def main():
         "config": {"workload": wl["desc"] + "; FP32 sweep with FP64 stats and seeds, FP64 finalize and recheck",
                    "cells": cells},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_LANE_OPS / 1e12, "unit": "TOP/s",
-                     "frac": achieved / (PEAK_LANE_OPS / 1e12), "traffic": None,
+                     "frac": achieved / (PEAK_LANE_OPS / 1e12),
+                     "traffic": measured_traffic() if (wl["kind"] == "self" and args.n is None and not args.slots
+                                                       and not args.reseed and args.workload == "selfjoin_large") else None,
                      "kernel": "k_sweep<float>", "ops_per_cell": OPS_PER_CELL,
                      "sweep_ms_per_launch": sweep32, "sweep_cells_per_s": cells / (sweep32 / 1e3)},
     }

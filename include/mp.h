@@ -159,7 +159,7 @@ mp_status mp_backward(const mp_batch_plan *plan, const void *T_cat, const int64_
  * smallest finite P[i] with its pair (i, I[i]), then every index within m of
  * either member is masked) and k_discords discords (repeatedly the largest
  * finite P, masking within m), and recomputes their distances in FP64 from
- * T.  One workgroup; meant for small k (<= 64 each).
+ * T.  One launch per pick; meant for small k (<= 64 each).
  *   T        device, n values of `dtype`; P, I device, l values (a profile
  *            this library produced for T with window m)
  *   out_idx  device int64[2*k_motifs + k_discords]: motif pairs (i, j) first,
@@ -167,7 +167,7 @@ mp_status mp_backward(const mp_batch_plan *plan, const void *T_cat, const int64_
  *   out_dist device double[k_motifs + k_discords]: FP64 distance of each
  *            motif pair, then of each discord to its neighbour I; +inf where
  *            fewer exist
- *   ws       device scratch of mp_recheck_workspace(n, m) bytes
+ *   ws       device scratch of mp_recheck_workspace(n, m) bytes (a few KB)
  */
 size_t mp_recheck_workspace(int64_t n, int32_t m);
 mp_status mp_recheck(const void *T, int64_t n, int32_t m, mp_dtype dtype, const void *P,

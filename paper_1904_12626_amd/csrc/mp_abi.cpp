@@ -524,7 +524,7 @@ mp_status mp_backward(const mp_batch_plan *pl, const void *T_cat, const int64_t 
 
 size_t mp_recheck_workspace(int64_t n, int32_t m) {
   if (m < 2 || n < m) return 0;
-  return align_up((size_t)(n - m + 1));
+  return align_up(mpx::recheck_state_bytes());
 }
 
 mp_status mp_recheck(const void *T, int64_t n, int32_t m, mp_dtype dtype, const void *P,

@@ -94,7 +94,8 @@ hipError_t launch_rescan(const Plan &plan, const Work &w, const void *T, bool t_
                          const Outputs &o, bool out_f64, bool fp64_finalize, hipStream_t st);
 hipError_t launch_recheck(const void *T, bool t_f64, int64_t n, int32_t m, const void *P,
                           bool p_f64, const int64_t *I, int32_t km, int32_t kd, int64_t *out_idx,
-                          double *out_dist, uint8_t *mask, hipStream_t st);
+                          double *out_dist, uint8_t *ws, hipStream_t st);
+size_t recheck_state_bytes();
 hipError_t launch_backward(const Plan &plan, const Work &w, const void *T, bool t_f64,
                            const int64_t *I, const void *gP, void *gT, int64_t total_l,
                            int64_t total_n, hipStream_t st);

@@ -2,6 +2,7 @@
 // sweep cannot express exactly (constant and invalid windows), optionally
 // recompute P in FP64 from the chosen pair, and the FP64 recheck of the best
 // motif pairs and discords.
+#include <algorithm>
 #include <cmath>
 
 #include "mp_internal.h"
@@ -251,59 +252,56 @@ hipError_t launch_rescan(const Plan &plan, const Work &w, const void *T, bool t_
 }
 
 // ------------------------------------------------------------------ recheck
-// One workgroup: k_motifs rounds of "smallest finite unmasked P -> pair
-// (i, I[i]), mask within m of both", then k_discords rounds of "largest
-// finite unmasked P, mask within m"; every reported pair is re-measured in
-// FP64.  Ties go to the smallest index.
+// Motif pairs: repeatedly the smallest finite P[i] not within m of an earlier
+// pick, reported with its pair (i, I[i]), both members then masked; discords:
+// repeatedly the largest finite P, masking within m.  One launch per pick:
+// every workgroup reduces a slice to (value, index) (smallest index on ties),
+// the last workgroup to finish (atomic ticket) reduces the partial results,
+// re-measures the pair in FP64 and appends the new mask centres.
+struct RecheckState {
+  double pv[512];         // per-workgroup partial values
+  int64_t pi[512];        // per-workgroup partial indices
+  int64_t centres[192];   // motif members, then discords
+  unsigned int ticket;
+  int done;               // a pick found nothing: later picks report none
+};
+constexpr int kRecheckBlocks = 512;
+
 template <typename Tin, typename Tp>
-__global__ void __launch_bounds__(1024) k_recheck(const Tin *__restrict__ T, int64_t n, int m,
-                                                  const Tp *__restrict__ P,
-                                                  const int64_t *__restrict__ I, int km, int kd,
-                                                  int64_t *out_idx, double *out_dist,
-                                                  uint8_t *mask) {
-  __shared__ double bv[1024];
-  __shared__ int64_t bi[1024];
-  const int tid = threadIdx.x, nt = blockDim.x;
+__global__ void __launch_bounds__(256)
+    k_pick(const Tin *__restrict__ T, int64_t n, int m, const Tp *__restrict__ P,
+           const int64_t *__restrict__ I, int discord, int q, int km, int64_t *out_idx,
+           double *out_dist, RecheckState *st) {
+  __shared__ double bv[256];
+  __shared__ int64_t bi[256];
+  __shared__ int64_t cen[192];
+  __shared__ int last;
+  const int tid = threadIdx.x;
   const int64_t l = n - m + 1;
-  auto stats = [&](int64_t i, double &mu, double &sg, bool &cst) {
-    double s = 0.0, lo = 0.0, hi = 0.0;
-    for (int u = 0; u < m; ++u) {
-      const double v = sample(T + i + u);
-      if (u == 0) { lo = v; hi = v; }
-      lo = fmin(lo, v);
-      hi = fmax(hi, v);
-      s += v;
-    }
-    mu = s / m;
-    double q = 0.0;
-    for (int u = 0; u < m; ++u) {
-      const double dv = sample(T + i + u) - mu;
-      q = fma(dv, dv, q);
-    }
-    sg = sqrt(q / m);
-    cst = (lo == hi);
-  };
-  auto dist = [&](int64_t i, int64_t j) -> double {
-    double mi, si, mj, sj;
-    bool ci, cj;
-    stats(i, mi, si, ci);
-    stats(j, mj, sj, cj);
-    return pair_dist64(T + i, mi, si, ci, T + j, mj, sj, cj, m);
-  };
-  // block argmin (sign = +1) or argmax (sign = -1) of finite unmasked P
-  auto pick = [&](double sign) -> int64_t {
-    double best = INFINITY;
-    int64_t arg = -1;
-    for (int64_t x = tid; x < l; x += nt) {
+  // mask centres of earlier picks of this kind
+  const int ncen = discord ? q : 2 * q;
+  const int64_t *src = st->centres + (discord ? 2 * km : 0);
+  for (int c = tid; c < ncen; c += blockDim.x) cen[c] = src[c];
+  __syncthreads();
+  const double sign = discord ? -1.0 : 1.0;
+  double best = INFINITY;
+  int64_t arg = -1;
+  if (!st->done) {
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + tid; x < l; x += (int64_t)gridDim.x * blockDim.x) {
       const double p = (double)P[x];
-      if (mask[x] || !isfinite(p)) continue;
+      if (!isfinite(p)) continue;
+      bool masked = false;
+      for (int c = 0; c < ncen; ++c) masked |= llabs(x - cen[c]) <= m;
+      if (masked) continue;
       const double v = sign * p;
       if (v < best) { best = v; arg = x; }
     }
+  }
+  auto reduce = [&]() {
     bv[tid] = best;
     bi[tid] = arg;
     __syncthreads();
-    for (int h = nt / 2; h > 0; h >>= 1) {
+    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
       if (tid < h) {
         const double v2 = bv[tid + h];
         const int64_t i2 = bi[tid + h];
@@ -314,67 +312,112 @@ __global__ void __launch_bounds__(1024) k_recheck(const Tin *__restrict__ T, int
       }
       __syncthreads();
     }
-    const int64_t r = bi[0];
-    __syncthreads();
-    return r;
   };
-  auto mask_around = [&](int64_t c) {
-    for (int64_t x = max((int64_t)0, c - m) + tid; x <= min(l - 1, c + m); x += nt) mask[x] = 1;
-    __syncthreads();
-  };
-  for (int64_t x = tid; x < l; x += nt) mask[x] = 0;
-  __syncthreads();
-  for (int q = 0; q < km; ++q) {
-    const int64_t i = pick(1.0);
-    const int64_t j = (i >= 0) ? I[i] : -1;
-    if (tid == 0) {
-      out_idx[2 * q] = (j >= 0) ? i : -1;
-      out_idx[2 * q + 1] = j;
-      out_dist[q] = (j >= 0) ? dist(i, j) : INFINITY;
-    }
-    if (j < 0) {
-      for (int r = q + 1; r < km && tid == 0; ++r) {
-        out_idx[2 * r] = -1;
-        out_idx[2 * r + 1] = -1;
-        out_dist[r] = INFINITY;
-      }
-      break;
-    }
-    mask_around(i);
-    mask_around(j);
+  reduce();
+  if (tid == 0) {
+    st->pv[blockIdx.x] = bv[0];
+    st->pi[blockIdx.x] = bi[0];
+    __threadfence();
+    last = (atomicAdd(&st->ticket, 1u) == gridDim.x - 1);
   }
-  for (int64_t x = tid; x < l; x += nt) mask[x] = 0;
   __syncthreads();
-  for (int q = 0; q < kd; ++q) {
-    const int64_t i = pick(-1.0);
+  if (!last) return;
+  __threadfence();
+  best = INFINITY;
+  arg = -1;
+  for (int b = tid; b < (int)gridDim.x; b += blockDim.x) {
+    const volatile double *pv = st->pv;
+    const volatile int64_t *pi = st->pi;
+    const double v = pv[b];
+    const int64_t i = pi[b];
+    if (i >= 0 && (arg < 0 || v < best || (v == best && i < arg))) { best = v; arg = i; }
+  }
+  reduce();
+  if (tid == 0) {
+    st->ticket = 0;
+    const int64_t i = bi[0];
     const int64_t j = (i >= 0) ? I[i] : -1;
-    if (tid == 0) {
+    double d = INFINITY;
+    if (i >= 0 && j >= 0) {
+      auto stats = [&](int64_t w, double &mu, double &sg, bool &cst) {
+        double s = 0.0, lo = 0.0, hi = 0.0;
+        for (int u = 0; u < m; ++u) {
+          const double v = sample(T + w + u);
+          if (u == 0) { lo = v; hi = v; }
+          lo = fmin(lo, v);
+          hi = fmax(hi, v);
+          s += v;
+        }
+        mu = s / m;
+        double qq = 0.0;
+        for (int u = 0; u < m; ++u) {
+          const double dv = sample(T + w + u) - mu;
+          qq = fma(dv, dv, qq);
+        }
+        sg = sqrt(qq / m);
+        cst = (lo == hi);
+      };
+      double mi, si, mj, sj;
+      bool ci, cj;
+      stats(i, mi, si, ci);
+      stats(j, mj, sj, cj);
+      d = pair_dist64(T + i, mi, si, ci, T + j, mj, sj, cj, m);
+    }
+    if (!discord) {
+      const bool ok = (i >= 0 && j >= 0);
+      out_idx[2 * q] = ok ? i : -1;
+      out_idx[2 * q + 1] = ok ? j : -1;
+      out_dist[q] = ok ? d : INFINITY;
+      if (ok) {
+        st->centres[2 * q] = i;
+        st->centres[2 * q + 1] = j;
+      } else {
+        st->done = 1;
+      }
+    } else {
       out_idx[2 * km + q] = i;
-      out_dist[km + q] = (i >= 0 && j >= 0) ? dist(i, j) : INFINITY;
+      out_dist[km + q] = (i >= 0 && j >= 0) ? d : INFINITY;
+      if (i >= 0) st->centres[2 * km + q] = i; else st->done = 1;
     }
-    if (i < 0) {
-      for (int r = q + 1; r < kd && tid == 0; ++r) {
-        out_idx[2 * km + r] = -1;
-        out_dist[km + r] = INFINITY;
-      }
-      break;
-    }
-    mask_around(i);
   }
+}
+
+__global__ void k_recheck_init(RecheckState *st) {
+  if (threadIdx.x == 0) {
+    st->ticket = 0;
+    st->done = 0;
+  }
+}
+
+__global__ void k_recheck_phase(RecheckState *st) {
+  if (threadIdx.x == 0) st->done = 0;   // discords do not depend on motif exhaustion
 }
 
 hipError_t launch_recheck(const void *T, bool t_f64, int64_t n, int32_t m, const void *P,
                           bool p_f64, const int64_t *I, int32_t km, int32_t kd, int64_t *out_idx,
-                          double *out_dist, uint8_t *mask, hipStream_t st) {
-  const dim3 blk(1024), grd(1);
-  if (t_f64) {
-    if (p_f64) hipLaunchKernelGGL((k_recheck<double, double>), grd, blk, 0, st, (const double *)T, n, m, (const double *)P, I, km, kd, out_idx, out_dist, mask);
-    else hipLaunchKernelGGL((k_recheck<double, float>), grd, blk, 0, st, (const double *)T, n, m, (const float *)P, I, km, kd, out_idx, out_dist, mask);
-  } else {
-    if (p_f64) hipLaunchKernelGGL((k_recheck<float, double>), grd, blk, 0, st, (const float *)T, n, m, (const double *)P, I, km, kd, out_idx, out_dist, mask);
-    else hipLaunchKernelGGL((k_recheck<float, float>), grd, blk, 0, st, (const float *)T, n, m, (const float *)P, I, km, kd, out_idx, out_dist, mask);
+                          double *out_dist, uint8_t *ws, hipStream_t st) {
+  RecheckState *rs = reinterpret_cast<RecheckState *>(ws);
+  const int64_t l = n - m + 1;
+  const int grid = (int)std::min<int64_t>(kRecheckBlocks, std::max<int64_t>(1, (l + 255) / 256));
+  hipLaunchKernelGGL(k_recheck_init, dim3(1), dim3(64), 0, st, rs);
+  for (int pass = 0; pass < 2; ++pass) {
+    const int k = pass == 0 ? km : kd;
+    if (pass == 1) hipLaunchKernelGGL(k_recheck_phase, dim3(1), dim3(64), 0, st, rs);
+    for (int q = 0; q < k; ++q) {
+#define MPX_PICK(TIN, TP)                                                                      \
+  hipLaunchKernelGGL((k_pick<TIN, TP>), dim3(grid), dim3(256), 0, st, (const TIN *)T, n, m,  \
+                     (const TP *)P, I, pass, q, km, out_idx, out_dist, rs)
+      if (t_f64) {
+        if (p_f64) MPX_PICK(double, double); else MPX_PICK(double, float);
+      } else {
+        if (p_f64) MPX_PICK(float, double); else MPX_PICK(float, float);
+      }
+#undef MPX_PICK
+    }
   }
   return hipGetLastError();
 }
+
+size_t recheck_state_bytes() { return sizeof(RecheckState); }
 
 }  // namespace mpx
