@@ -76,6 +76,16 @@ def workload(name: str, n_override=None):
         n = n_override or (1 << 19)
         return dict(kind="ab", A=W.ecg_like(n, 31), B=W.ecg_like(n, 32), m=128,
                     desc=f"AB-join, two float32 ECG-like series n={n}, m=128")
+    if name == "batch_ragged":
+        rb = W.batch_ragged(n_override or 512)
+        return dict(kind="batch", rb=rb, m=None,
+                    desc=f"{len(rb.series)} float32 random walks, lengths U{{2048..65536}}, m in {{32,64,128}}, "
+                         "ez=m/4, one launch sequence replayed from a captured graph")
+    if name == "diff_batch":
+        T, m, ez = W.diff_batch(64, n_override or 16384)
+        return dict(kind="diff", T=T, m=m, ez=ez,
+                    desc=f"differentiable profile: {T.shape[0]} float32 random walks n={T.shape[1]}, m={m}, ez={ez}; "
+                         "forward + backward of L = sum(P)")
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -85,7 +95,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="selfjoin_large",
-                    choices=["selfjoin_large", "selfjoin_small", "abjoin_ecg"])
+                    choices=["selfjoin_large", "selfjoin_small", "abjoin_ecg", "batch_ragged", "diff_batch"])
     ap.add_argument("--n", type=int, default=None, help="override the series length")
     ap.add_argument("--slots", type=int, default=0, help="diagonals per lane (0 = automatic)")
     ap.add_argument("--reseed", type=int, default=0, help="rows per tile / reseed interval (0 = automatic)")
@@ -134,13 +144,44 @@ def main():
             P, I = mpx.selfjoin(Tg, m, ez, precision=precision, tile_slots=args.slots, reseed_rows=args.reseed)
             idx, dist = mpx.recheck(Tg, m, P, I, km, kd)
             return P, I, idx, dist
-    else:
+    elif wl["kind"] == "ab":
         A, B = wl["A"], wl["B"]
         Ag, Bg = torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev)
         cells = mpx.abjoin_cells(A.size, B.size, m)
 
         def step(precision):
             return mpx.abjoin(Ag, Bg, m, precision=precision, tile_slots=args.slots, reseed_rows=args.reseed)
+    elif wl["kind"] == "batch":
+        rb = wl["rb"]
+        Tc, _ = rb.concat()
+        Tg = torch.from_numpy(Tc).to(dev)
+        plans = {}
+
+        def plan_for(precision):
+            if precision not in plans:
+                plans[precision] = mpx.BatchPlan([s.size for s in rb.series], rb.m, rb.ez, dtype=torch.float32,
+                                                 device=dev, precision=precision, tile_slots=args.slots,
+                                                 reseed_rows=args.reseed)
+            return plans[precision]
+        cells = plan_for("f32").cells
+
+        def step(precision):
+            return plan_for(precision).run(Tg)
+    else:
+        T, ez = wl["T"], wl["ez"]
+        Tg = torch.from_numpy(T).to(dev)
+        cells = T.shape[0] * mpx.selfjoin_cells(T.shape[1], m, ez)
+        plans = {}
+
+        def step(precision):
+            if precision not in plans:
+                plans[precision] = mpx.BatchPlan([T.shape[1]] * T.shape[0], [m] * T.shape[0], [ez] * T.shape[0],
+                                                 dtype=torch.float32, device=dev, precision=precision,
+                                                 tile_slots=args.slots, reseed_rows=args.reseed)
+            x = Tg.clone().requires_grad_(True)
+            P, I = mpx.MatrixProfileFn.apply(x, plans[precision])
+            P.sum().backward()
+            return P, I, x.grad
 
     def timed(precision, steps, warmup):
         for _ in range(warmup):
@@ -186,11 +227,47 @@ def main():
                      "sweep_ms_per_launch": sweep32, "sweep_cells_per_s": cells / (sweep32 / 1e3)},
     }
 
-    if not args.no_fp64:
+    if wl["kind"] == "batch":
+        plan = plan_for("f32")
+        Pg = torch.empty(plan.profile_length, dtype=torch.float32, device=dev)
+        Ig = torch.empty(plan.profile_length, dtype=torch.int64, device=dev)
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            plan.run(Tg, Pg, Ig)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            plan.run(Tg, Pg, Ig)
+        for _ in range(args.warmup):
+            graph.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            graph.replay()
+        torch.cuda.synchronize()
+        msg = (time.perf_counter() - t0) * 1e3 / args.steps
+        same = bool(torch.equal(Pg, out32[0]) and torch.equal(Ig, out32[1]))
+        log(f"[bench] graph replay: {msg:.2f} ms/step (eager {ms32:.2f}); replay equals eager: {same}")
+        result["eager_ms_per_step"] = ms32
+        result["ms_per_step"] = msg
+        result["value"] = cells / (msg / 1e3)
+        result["graph_replay_equals_eager"] = same
+        result["config"]["series"] = len(wl["rb"].series)
+    if wl["kind"] == "diff":
+        result["config"]["note"] = "value counts forward cells per second of forward+backward steps"
+
+    if not args.no_fp64 and wl["kind"] in ("self", "ab"):
         out64, ms64, sweep64, tot64 = timed("f64", max(1, min(args.steps, 3)), 1)
         log(f"[bench] f64: {ms64:.2f} ms/step, sweep {sweep64:.2f} ms")
         P32, I32 = out32[0].double().cpu().numpy(), out32[1].cpu().numpy()
         P64, I64 = out64[0].double().cpu().numpy(), out64[1].cpu().numpy()
+        if wl["kind"] == "ab":   # both directions
+            P32 = np.concatenate([P32, out32[2].double().cpu().numpy()])
+            I32 = np.concatenate([I32, out32[3].cpu().numpy()])
+            P64 = np.concatenate([P64, out64[2].double().cpu().numpy()])
+            I64 = np.concatenate([I64, out64[3].cpu().numpy()])
         fin = np.isfinite(P64)
         raw = None
         if wl["kind"] == "self":
@@ -235,6 +312,27 @@ def main():
         if not args.no_fp64:
             P64r = out64[0].double().cpu().numpy()[rows]
             result["oracle_check"]["max_abs_dP_f64_vs_oracle"] = float(np.max(np.abs(P64r - Po)))
+    if args.cpu_rows > 0 and wl["kind"] == "ab":
+        from oracle import cimpl
+        rng = np.random.default_rng(0)
+        A64, B64 = wl["A"].astype(np.float64), wl["B"].astype(np.float64)
+        lA, lB = A64.size - m + 1, B64.size - m + 1
+        ra = np.sort(rng.choice(lA, args.cpu_rows // 2, replace=False))
+        rb_ = np.sort(rng.choice(lB, args.cpu_rows // 2, replace=False))
+        t0 = time.perf_counter()
+        Pa, Ia = cimpl.abjoin_rows(A64, B64, m, ra)
+        Pb, Ib = cimpl.abjoin_rows(B64, A64, m, rb_)
+        dt = time.perf_counter() - t0
+        pairs = int(ra.size * lB + rb_.size * lA)
+        result["cpu_baseline"] = {
+            "value": pairs / dt, "unit": "cells/s", "cores": cimpl.max_threads(), "kind": "oracle",
+            "sample": f"{ra.size} rows of P_ab and {rb_.size} rows of P_ba, {pairs} pairs, each O(m) in FP64, "
+                      f"{dt:.1f} s"}
+        result["oracle_check"] = {
+            "rows": int(ra.size + rb_.size),
+            "max_abs_dP_f32_vs_oracle": float(max(np.max(np.abs(out32[0].double().cpu().numpy()[ra] - Pa)),
+                                                  np.max(np.abs(out32[2].double().cpu().numpy()[rb_] - Pb)))),
+        }
     print(json.dumps(result), flush=True)
 
 

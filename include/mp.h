@@ -85,9 +85,11 @@ typedef enum {
 
 typedef struct {
   int32_t precision;     /* MP_PREC_F64 or MP_PREC_F32                        */
-  int32_t reseed_rows;   /* rows per tile = reseed interval; 0 = automatic   */
-  int32_t tile_slots;    /* diagonals per lane (8 or 16; F64 supports 8);
+  int32_t reseed_rows;   /* rows per tile = reseed interval, a multiple of 64
+                            (rounded up to the sweep's flush period);
                             0 = automatic                                   */
+  int32_t tile_slots;    /* diagonals per lane: 8, 12 or 16 (the FP64 sweep
+                            supports 8); 0 = automatic (8)                   */
   int32_t flags;         /* MP_FLAG_*                                        */
 } mp_options;
 

@@ -34,8 +34,10 @@ mp_status parse_options(const mp_options *opt, Options &o) {
   if (!opt) return MP_OK;
   if (opt->precision != MP_PREC_F64 && opt->precision != MP_PREC_F32) return MP_EINVAL;
   o.f64 = opt->precision == MP_PREC_F64;
-  if (opt->tile_slots != 0 && opt->tile_slots != 8 && opt->tile_slots != 16) return MP_EINVAL;
-  if (o.f64 && opt->tile_slots == 16) return MP_EUNSUPPORTED;
+  if (opt->tile_slots != 0 && opt->tile_slots != 8 && opt->tile_slots != 12 &&
+      opt->tile_slots != 16)
+    return MP_EINVAL;
+  if (o.f64 && opt->tile_slots != 0 && opt->tile_slots != 8) return MP_EUNSUPPORTED;
   o.slots = opt->tile_slots ? opt->tile_slots : 8;
   if (opt->reseed_rows < 0) return MP_EINVAL;
   if (opt->reseed_rows != 0 && (opt->reseed_rows % 64 != 0 || opt->reseed_rows > (1 << 20)))
@@ -125,16 +127,21 @@ int64_t sweep_cells(int64_t lr, int64_t lc, int64_t k_lo, int64_t k_hi) {
   return c;
 }
 
+// Rows per LDS flush of the sweep (a multiple of the slot count).
+int flush_rows(int slots) { return slots == 12 ? 36 : (slots == 16 ? 32 : (slots == 8 ? 32 : 16)); }
+
 // Tiling: W = 64 * slots diagonals per strip, R rows per tile (also the
-// reseed interval).  Automatic R starts at 4096 and halves (down to 64)
-// while the job has fewer than ~8 tiles per SIMD.
+// reseed interval), a multiple of the flush period.  Automatic R starts at
+// 4096 and halves (down to 64) while the job has fewer than ~8 tiles per
+// SIMD.
 void finish_job(Job &j) {
   j.W = 64 * j.opt.slots;
   int R = j.opt.reseed ? j.opt.reseed : 4096;
   if (!j.opt.reseed) {
     while (R > 64 && count_tiles(j, j.W, R) < 8 * 1024) R /= 2;
   }
-  j.R = R;
+  const int tp = flush_rows(j.opt.f64 ? 8 : j.opt.slots);
+  j.R = ((R + tp - 1) / tp) * tp;
   int64_t seg = 0;
   j.cells = 0;
   for (SweepDesc &d : j.sweeps) {

@@ -157,8 +157,14 @@ __device__ __forceinline__ T ldu(const T *p) {
 
 }  // namespace
 
+// Minimum resident waves per SIMD the register allocation must allow.
+template <typename FE, int NS>
+struct SweepMinWaves {
+  static constexpr int value = (sizeof(FE) == 4 && NS <= 12) ? 4 : 2;
+};
+
 template <typename F, typename Tin, int DT, int TP>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(64, (SweepMinWaves<F, DT>::value))
     k_sweep(const Plan plan, const typename FTraits<F>::V4 *__restrict__ rcb,
             const double *__restrict__ mu, const int64_t *__restrict__ seg_prefix,
             const int32_t *__restrict__ seg_sweep, const SeriesDesc *__restrict__ s_ext,
@@ -354,6 +360,8 @@ int sweep_grid(bool f64_sweep, int slots) {
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_sweep<double, float, 8, 16>, 64, 0);
   else if (slots == 8)
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_sweep<float, float, 8, 32>, 64, 0);
+  else if (slots == 12)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_sweep<float, float, 12, 36>, 64, 0);
   else
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_sweep<float, float, 16, 32>, 64, 0);
   if (e != hipSuccess || per <= 0) per = 8;
@@ -375,6 +383,9 @@ hipError_t launch_sweep(const Plan &plan, const Work &w, const void *T, bool t_f
   } else if (slots == 8) {
     if (t_f64) MPX_LAUNCH(float, double, 8, 32);
     else MPX_LAUNCH(float, float, 8, 32);
+  } else if (slots == 12) {
+    if (t_f64) MPX_LAUNCH(float, double, 12, 36);
+    else MPX_LAUNCH(float, float, 12, 36);
   } else {
     if (t_f64) MPX_LAUNCH(float, double, 16, 32);
     else MPX_LAUNCH(float, float, 16, 32);

@@ -53,6 +53,8 @@ def test_workspace_queries():
     assert lib.mp_selfjoin_workspace(4096, 1, B.MP_F32, ctypes.byref(opt)) == 0  # m < 2
     opt16 = B.make_options("f64", tile_slots=16)
     assert lib.mp_selfjoin_workspace(4096, 64, B.MP_F64, ctypes.byref(opt16)) == 0
+    opt12 = B.make_options("f32", tile_slots=12)
+    assert lib.mp_selfjoin_workspace(4096, 64, B.MP_F32, ctypes.byref(opt12)) > 0
     assert lib.mp_abjoin_workspace(1000, 900, 32, B.MP_F64, None) > 0
     assert lib.mp_recheck_workspace(1000, 32) >= 969
 
@@ -86,7 +88,7 @@ def test_selfjoin_rejects_null_and_misaligned():
 def test_bad_options():
     lib = B.lib()
     ok = ctypes.c_void_p(1 << 20)
-    for opt in (B.mp_options(7, 0, 0, 1), B.mp_options(1, 100, 0, 1), B.mp_options(1, 0, 12, 1),
+    for opt in (B.mp_options(7, 0, 0, 1), B.mp_options(1, 100, 0, 1), B.mp_options(1, 0, 10, 1),
                 B.mp_options(1, 0, 0, 8)):
         assert lib.mp_selfjoin(ok, 1000, 10, 2, B.MP_F32, ctypes.byref(opt), ok, ok, ok, 1 << 30,
                                None) == B.MP_EINVAL

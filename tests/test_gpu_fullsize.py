@@ -1,0 +1,212 @@
+"""Parity at the benchmark sizes, in the launch configuration bench.py times.
+
+The FP64 oracle is exact on every row it computes, so large joins are
+checked on sampled rows (plus every planted window) against it, and in full
+against the library's FP64 sweep, whose own parity is established on the
+small cases.  Tolerance 1e-3*sqrt(m) on P; indices equal up to near-ties."""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import cimpl
+from oracle import mp_oracle as O
+from tests.parity import compare_profile
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _np(x):
+    return x.double().cpu().numpy() if x.is_floating_point() else x.cpu().numpy()
+
+
+def _invariants(T64, m, ez, P, I, rng, nsample=64):
+    l = P.size
+    fin = np.isfinite(P)
+    assert fin.all()
+    assert np.all(P >= 0) and np.all(P <= 2 * math.sqrt(m) + 1e-3)
+    assert np.all((I >= 0) & (I < l))
+    if ez is not None:
+        assert np.all(np.abs(np.arange(l) - I) > ez)
+    for i in rng.choice(l, nsample, replace=False):
+        assert abs(P[i] - O.pair_distance(T64, int(i), T64, int(I[i]), m)) < 1e-4
+
+
+def test_selfjoin_large_planted_walk():
+    """n=2^20 float32 planted random walk, m=256, ez=64 (the benchmark join)."""
+    import paper_1904_12626_amd as mpx
+    pw, ez = W.selfjoin_large()
+    m = pw.m
+    Tg = torch.from_numpy(pw.T).to(DEV)
+    P32, I32 = mpx.selfjoin(Tg, m, ez)
+    P64, I64 = mpx.selfjoin(Tg, m, ez, precision="f64")
+    Praw, _ = mpx.selfjoin(Tg, m, ez, fp64_finalize=False)
+    torch.cuda.synchronize()
+    P32, I32, P64, I64, Praw = _np(P32), _np(I32), _np(P64), _np(I64), _np(Praw)
+    tol = 1e-3 * math.sqrt(m)
+    T64 = pw.T.astype(np.float64)
+    rng = np.random.default_rng(0)
+    # FP32-mixed vs FP64 GPU path over the whole profile
+    assert np.max(np.abs(P32 - P64)) <= tol
+    assert np.max(np.abs(Praw - P64)) <= tol
+    assert np.mean(I32 == I64) > 0.99
+    # exact oracle rows: random rows and every planted window
+    rows = list(rng.choice(P32.size, 48, replace=False))
+    for a, b in pw.motif_pairs:
+        rows += [a, b]
+    rows += list(pw.discords)
+    rows = np.array(sorted(set(int(r) for r in rows)))
+    Po, Io = cimpl.selfjoin_rows(T64, m, ez, rows)
+    for P, I, where in ((P32, I32, "f32"), (P64, I64, "f64")):
+        for r, po, io in zip(rows, Po, Io):
+            if I[r] != io:
+                assert abs(r - I[r]) > ez
+                assert O.pair_distance(T64, int(r), T64, int(I[r]), m) <= po + tol, (where, r)
+        assert np.max(np.abs(P[rows] - Po)) <= tol, where
+    _invariants(T64, m, ez, P32, I32, rng)
+    # planted motif pairs are the top motifs, re-measured in FP64
+    idx, dist = mpx.recheck(Tg, m, torch.from_numpy(P32.astype(np.float32)).to(DEV),
+                            torch.from_numpy(I32).to(DEV), 8, 4)
+    idx, dist = idx.cpu().numpy(), dist.cpu().numpy()
+    found = [tuple(sorted(p)) for p in idx[:16].reshape(8, 2)]
+    for a, b in pw.motif_pairs:
+        assert any(abs(a - x) <= m // 8 and abs(b - y) <= m // 8 for x, y in found), (a, b, found)
+    for q, (i, j) in enumerate(idx[:16].reshape(8, 2)):
+        assert abs(dist[q] - O.pair_distance(T64, int(i), T64, int(j), m)) < 1e-9
+    # noisy planted pairs: d ~ sqrt(m * 0.05^2 * (s_a^-2 + s_b^-2)) in [0.57, 2.26]
+    assert np.all(dist[:8] > 0.3) and np.all(dist[:8] < 3.0)
+
+
+def test_abjoin_ecg_full():
+    """Two n=2^19 float32 ECG-like series, m=128: both directions."""
+    import paper_1904_12626_amd as mpx
+    A, B, m = W.abjoin_ecg()
+    Ag, Bg = torch.from_numpy(A).to(DEV), torch.from_numpy(B).to(DEV)
+    out32 = [_np(x) for x in mpx.abjoin(Ag, Bg, m)]
+    out64 = [_np(x) for x in mpx.abjoin(Ag, Bg, m, precision="f64")]
+    tol = 1e-3 * math.sqrt(m)
+    assert np.max(np.abs(out32[0] - out64[0])) <= tol
+    assert np.max(np.abs(out32[2] - out64[2])) <= tol
+    assert abs(out32[0].min() - out32[2].min()) <= tol
+    A64, B64 = A.astype(np.float64), B.astype(np.float64)
+    rng = np.random.default_rng(3)
+    ra = rng.choice(out32[0].size, 40, replace=False)
+    rb = rng.choice(out32[2].size, 40, replace=False)
+    Po, Io = cimpl.abjoin_rows(A64, B64, m, ra)
+    for r, po, io in zip(ra, Po, Io):
+        for P, I in ((out32[0], out32[1]), (out64[0], out64[1])):
+            assert abs(P[r] - po) <= tol
+            if I[r] != io:
+                assert O.pair_distance(A64, int(r), B64, int(I[r]), m) <= po + tol
+    Po, Io = cimpl.abjoin_rows(B64, A64, m, rb)
+    for r, po, io in zip(rb, Po, Io):
+        for P, I in ((out32[2], out32[3]), (out64[2], out64[3])):
+            assert abs(P[r] - po) <= tol
+            if I[r] != io:
+                assert O.pair_distance(B64, int(r), A64, int(I[r]), m) <= po + tol
+
+
+def test_batch_ragged_full():
+    """512 float32 random walks, lengths U{2048..65536}, m in {32,64,128},
+    ez = m/4, one launch sequence; graph replay equals the eager run."""
+    import paper_1904_12626_amd as mpx
+    rb = W.batch_ragged()
+    Tc, _ = rb.concat()
+    plan = mpx.BatchPlan([s.size for s in rb.series], rb.m, rb.ez, dtype=torch.float32, device=DEV)
+    Tg = torch.from_numpy(Tc).to(DEV)
+    P, I = plan.run(Tg)
+    torch.cuda.synchronize()
+    Ph, Ih = _np(P), _np(I)
+    Ps, Is = plan.split(Ph), plan.split(Ih)
+    lens = np.array([s.size for s in rb.series])
+    rng = np.random.default_rng(4)
+    # full oracle on the 8 shortest series
+    for s in np.argsort(lens)[:8]:
+        T64 = rb.series[s].astype(np.float64)
+        m, ez = rb.m[s], rb.ez[s]
+        Po, Io = cimpl.selfjoin(T64, m, ez)
+        compare_profile(T64, m, Ps[s], Is[s], Po, Io, 1e-3 * math.sqrt(m), ez=ez, where=f"series {s}")
+    # sampled rows on 8 random series
+    for s in rng.choice(len(rb.series), 8, replace=False):
+        T64 = rb.series[s].astype(np.float64)
+        m, ez = rb.m[s], rb.ez[s]
+        rows = rng.choice(Ps[s].size, 8, replace=False)
+        Po, Io = cimpl.selfjoin_rows(T64, m, ez, rows)
+        assert np.max(np.abs(Ps[s][rows] - Po)) <= 1e-3 * math.sqrt(m)
+    # a few series against single joins (identical launch arithmetic)
+    for s in rng.choice(len(rb.series), 3, replace=False):
+        P1, I1 = mpx.selfjoin(torch.from_numpy(rb.series[s]).to(DEV), rb.m[s], rb.ez[s])
+        torch.cuda.synchronize()
+        assert np.array_equal(_np(P1), Ps[s]) and np.array_equal(_np(I1), Is[s])
+    # graph capture and replay
+    Pg = torch.empty_like(P)
+    Ig = torch.empty_like(I)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        plan.run(Tg, Pg, Ig)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.run(Tg, Pg, Ig)
+    for rep in range(2):
+        Pg.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(_np(Pg), Ph) and np.array_equal(_np(Ig), Ih), rep
+
+
+def test_differentiable_batch_full():
+    """64 float32 walks of n=16384, m=100, ez=25; L = sum(P); kernel gradient
+    vs the FP64 reference gradient on sampled series and central differences
+    (h=1e-3) on 32 coordinates, redrawn where the argmin flips."""
+    import paper_1904_12626_amd as mpx
+    T, m, ez = W.diff_batch()
+    Tg = torch.from_numpy(T).to(DEV).requires_grad_(True)
+    P, I = mpx.matrix_profile(Tg, m, ez)
+    P.sum().backward()
+    g = Tg.grad.double().cpu().numpy()
+    Ih = I.cpu().numpy()
+    rng = np.random.default_rng(5)
+    for b in rng.choice(T.shape[0], 3, replace=False):
+        ref = O.reference_gradient(T[b].astype(np.float64), m, Ih[b], np.ones(Ih.shape[1]))
+        err = np.max(np.abs(g[b] - ref)) / np.max(np.abs(ref))
+        assert err <= 1e-4, (b, err)
+    # central differences of the fixed-index loss (only rows touching t move);
+    # a coordinate is redrawn when the FP64 profile's argmin changes at T +- h
+    checked = flips = 0
+    base = {}
+    while checked < 32:
+        b, t = int(rng.integers(T.shape[0])), int(rng.integers(T.shape[1]))
+        T64 = T[b].astype(np.float64)
+        h = 1e-3
+        if b not in base:
+            base[b] = mpx.selfjoin(torch.from_numpy(T64).to(DEV), m, ez, precision="f64")[1].cpu().numpy()
+        flip = False
+        for sgn in (1, -1):
+            Tp = T64.copy()
+            Tp[t] += sgn * h
+            _, Ip = mpx.selfjoin(torch.from_numpy(Tp).to(DEV), m, ez, precision="f64")
+            flip |= not np.array_equal(Ip.cpu().numpy(), base[b])
+        if flip:
+            flips += 1
+            assert flips < 64
+            continue
+        rows = [i for i in range(Ih.shape[1]) if (i <= t < i + m) or (Ih[b, i] <= t < Ih[b, i] + m)]
+
+        def loss(x):
+            return sum(O.pair_distance(x, i, x, int(Ih[b, i]), m) for i in rows)
+
+        Tp, Tm = T64.copy(), T64.copy()
+        Tp[t] += h
+        Tm[t] -= h
+        fd = (loss(Tp) - loss(Tm)) / (2 * h)
+        assert abs(fd - g[b, t]) <= 1e-3 * max(1.0, abs(fd)), (b, t, fd, g[b, t])
+        checked += 1
+    print(f"FD checked {checked} coordinates, redrawn {flips}")

@@ -49,6 +49,7 @@ def test_selfjoin_small_random_walk(precision, tol):
     (2500, 33, 8, np.float32, "f32", 16),
     (5000, 100, 25, np.float32, "f64", 8),
     (1300, 64, 16, np.float64, "f32", 16),
+    (3100, 40, 10, np.float32, "f32", 12),
     (129, 64, 16, np.float64, "f64", 8),
     (64, 64, 0, np.float64, "f64", 8),        # one window: no neighbour
     (90, 64, 26, np.float64, "f32", 8),       # l = 27 = ez + 1: no neighbour
