@@ -100,6 +100,8 @@ def main():
     ap.add_argument("--slots", type=int, default=0, help="diagonals per lane (0 = automatic)")
     ap.add_argument("--reseed", type=int, default=0, help="rows per tile / reseed interval (0 = automatic)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU path comparison")
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick tile slots and reseed rows with the autotuner before timing (search logged)")
     ap.add_argument("--cpu-rows", type=int, default=256, help="oracle rows timed for the CPU baseline (0 = skip)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (a known-traffic reference "
@@ -183,6 +185,18 @@ def main():
             P.sum().backward()
             return P, I, x.grad
 
+    if args.autotune and wl["kind"] in ("self", "ab", "batch"):
+        from paper_1904_12626_amd import autotune as AT
+        if wl["kind"] == "self":
+            ch = AT.tune_selfjoin(Tg, m, ez, log=log)
+        elif wl["kind"] == "ab":
+            ch = AT.tune_abjoin(Ag, Bg, m, log=log)
+        else:
+            rb = wl["rb"]
+            ch = AT.tune_batch(Tg, [s.size for s in rb.series], rb.m, rb.ez, log=log)
+        args.slots, args.reseed = ch["tile_slots"], ch["reseed_rows"]
+        plans.clear() if wl["kind"] == "batch" else None
+
     def timed(precision, steps, warmup):
         for _ in range(warmup):
             step(precision)
@@ -218,7 +232,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": wl["desc"] + "; FP32 sweep with FP64 stats and seeds, FP64 finalize and recheck",
-                   "cells": cells},
+                   "cells": cells, "tile_slots": args.slots or "auto", "reseed_rows": args.reseed or "auto"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_LANE_OPS / 1e12, "unit": "TOP/s",
                      "frac": achieved / (PEAK_LANE_OPS / 1e12),
                      "traffic": measured_traffic() if (wl["kind"] == "self" and args.n is None and not args.slots

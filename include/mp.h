@@ -89,7 +89,8 @@ typedef struct {
                             (rounded up to the sweep's flush period);
                             0 = automatic                                   */
   int32_t tile_slots;    /* diagonals per lane: 8, 12 or 16 (the FP64 sweep
-                            supports 8); 0 = automatic (8)                   */
+                            supports 8); 0 = automatic (12 for the FP32
+                            sweep, 8 for FP64)                               */
   int32_t flags;         /* MP_FLAG_*                                        */
 } mp_options;
 

@@ -24,7 +24,7 @@ size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 struct Options {
   bool f64 = false;      // FP64 sweep
-  int slots = 8;         // diagonals per lane
+  int slots = 12;        // diagonals per lane (FP32 default 12, FP64 8)
   int reseed = 0;        // 0 = automatic
   bool fp64_finalize = true;
 };
@@ -38,7 +38,7 @@ mp_status parse_options(const mp_options *opt, Options &o) {
       opt->tile_slots != 16)
     return MP_EINVAL;
   if (o.f64 && opt->tile_slots != 0 && opt->tile_slots != 8) return MP_EUNSUPPORTED;
-  o.slots = opt->tile_slots ? opt->tile_slots : 8;
+  o.slots = opt->tile_slots ? opt->tile_slots : (o.f64 ? 8 : 12);
   if (opt->reseed_rows < 0) return MP_EINVAL;
   if (opt->reseed_rows != 0 && (opt->reseed_rows % 64 != 0 || opt->reseed_rows > (1 << 20)))
     return MP_EINVAL;

@@ -172,7 +172,7 @@ __global__ void __launch_bounds__(64, (SweepMinWaves<F, DT>::value))
             unsigned long long *__restrict__ counter, const Tin *__restrict__ Tb, const int R,
             const int64_t total_tiles, const int64_t nseg) {
   constexpr int W = 64 * DT;
-  constexpr int CB = ilog2c(W);
+  constexpr int CB = ilog2c(W - 1) + 1;  // bits for codes 0 .. W-1
   using IK = InKey<F, CB>;
   using K = typename IK::K;
   using V4 = typename FTraits<F>::V4;

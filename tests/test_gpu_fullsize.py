@@ -137,11 +137,21 @@ def test_batch_ragged_full():
         rows = rng.choice(Ps[s].size, 8, replace=False)
         Po, Io = cimpl.selfjoin_rows(T64, m, ez, rows)
         assert np.max(np.abs(Ps[s][rows] - Po)) <= 1e-3 * math.sqrt(m)
-    # a few series against single joins (identical launch arithmetic)
-    for s in rng.choice(len(rb.series), 3, replace=False):
+    # a few series against single joins: within the tolerance with automatic
+    # tiling, and bitwise with the same tile height (= reseed interval)
+    pick = rng.choice(len(rb.series), 3, replace=False)
+    for s in pick:
         P1, I1 = mpx.selfjoin(torch.from_numpy(rb.series[s]).to(DEV), rb.m[s], rb.ez[s])
         torch.cuda.synchronize()
-        assert np.array_equal(_np(P1), Ps[s]) and np.array_equal(_np(I1), Is[s])
+        assert np.max(np.abs(_np(P1) - Ps[s])) <= 1e-3 * math.sqrt(rb.m[s])
+    fixed = mpx.BatchPlan([s.size for s in rb.series], rb.m, rb.ez, dtype=torch.float32, device=DEV,
+                          reseed_rows=1024)
+    Pf, If = fixed.run(Tg)
+    Pfs, Ifs = fixed.split(_np(Pf)), fixed.split(_np(If))
+    for s in pick:
+        P1, I1 = mpx.selfjoin(torch.from_numpy(rb.series[s]).to(DEV), rb.m[s], rb.ez[s], reseed_rows=1024)
+        torch.cuda.synchronize()
+        assert np.array_equal(_np(P1), Pfs[s]) and np.array_equal(_np(I1), Ifs[s])
     # graph capture and replay
     Pg = torch.empty_like(P)
     Ig = torch.empty_like(I)
