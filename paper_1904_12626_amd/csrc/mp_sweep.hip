@@ -66,6 +66,16 @@ __device__ __forceinline__ int64_t rfl64(int64_t v) {
   return ((int64_t)hi << 32) | (unsigned int)lo;
 }
 
+// Compile-time loop: f(integral_constant<int, 0..N-1>), fully expanded.
+template <typename Fn, int... Ts>
+__device__ __forceinline__ void static_for_impl(Fn &&f, std::integer_sequence<int, Ts...>) {
+  (f(std::integral_constant<int, Ts>{}), ...);
+}
+template <int N, typename Fn>
+__device__ __forceinline__ void static_for(Fn &&f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
 // In-wave key handling.  FP32 keys live as int bit patterns so that the
 // minimum is an integer min (order of non-negative floats; the rare tiny
 // negative key of a perfect match sorts below every positive one).
@@ -81,6 +91,17 @@ struct InKey<float, CB> {
     return (int)((__float_as_uint(key) & ~kMask) | code);
   }
   static __device__ __forceinline__ K kmin(K a, K b) { return min(a, b); }
+  static __device__ __forceinline__ K kmin3(K a, K b, K c) { return min(min(a, b), c); }
+  template <int N>
+  static __device__ __forceinline__ K rowmin(const K (&k)[N]) {
+    K r = min(k[0], k[1]);
+    static_for<(N - 2) / 2>([&](auto q) {
+      constexpr int j = 2 + 2 * decltype(q)::value;
+      r = min(min(r, k[j]), k[j + 1]);
+    });
+    if constexpr (N % 2 == 1) r = min(r, k[N - 1]);
+    return r;
+  }
   static __device__ __forceinline__ K shl(K v) { return shl1(v, kBig); }
   static __device__ __forceinline__ unsigned code(K k) { return (unsigned)k & kMask; }
   static __device__ __forceinline__ double value(K k) {
@@ -99,6 +120,13 @@ struct InKey<double, CB> {
     return __longlong_as_double((b & ~0xffffffffll) | lo);
   }
   static __device__ __forceinline__ K kmin(K a, K b) { return __builtin_fmin(a, b); }
+  static __device__ __forceinline__ K kmin3(K a, K b, K c) { return __builtin_fmin(__builtin_fmin(a, b), c); }
+  template <int N>
+  static __device__ __forceinline__ K rowmin(const K (&k)[N]) {
+    K r = k[0];
+    static_for<N - 1>([&](auto q) { r = __builtin_fmin(r, k[1 + decltype(q)::value]); });
+    return r;
+  }
   static __device__ __forceinline__ K shl(K v) { return shl1d(v, 1.0e300); }
   static __device__ __forceinline__ unsigned code(K k) {
     return (unsigned)(__double_as_longlong(k) & 0xffffffffll) & kMask;
@@ -124,16 +152,6 @@ __device__ __forceinline__ double clean(float v) {
 }
 __device__ __forceinline__ double clean(double v) {
   return ((__double_as_longlong(v) >> 52) & 0x7ff) == 0x7ff ? 0.0 : v;
-}
-
-// Compile-time loop: f(integral_constant<int, 0..N-1>), fully expanded.
-template <typename Fn, int... Ts>
-__device__ __forceinline__ void static_for_impl(Fn &&f, std::integer_sequence<int, Ts...>) {
-  (f(std::integral_constant<int, Ts>{}), ...);
-}
-template <int N, typename Fn>
-__device__ __forceinline__ void static_for(Fn &&f) {
-  static_for_impl(f, std::make_integer_sequence<int, N>{});
 }
 
 // Load of a wave-uniform address through the constant address space, so that
@@ -301,36 +319,67 @@ __global__ void __launch_bounds__(64, (SweepMinWaves<F, DT>::value))
       __syncthreads();
     };
 
+    // Rows are processed in pairs: a column register receives one cell from
+    // each row of the pair, so its minimum is a single 3-input min, and each
+    // row's own minimum is a chain of 3-input mins.
+    static_assert(TP % 2 == 0 && DT % 2 == 0, "row pairs");
     for (int64_t sb = 0; sb < nsteps; sb += TP) {
-      const int nb = (int)min((int64_t)TP, nsteps - sb);  // a multiple of DT
-      static_for<TP>([&](auto uc) {
-        constexpr int u = decltype(uc)::value;
-        constexpr int r = u % DT;  // rotation of the column slots
-        if (u < nb) {
-          const int64_t s = sb + u;
-          const int64_t i = i0 + s;
-          const V4 rd = ldu(rowd + i);
-          const F ai = rd.x, gi = rd.y, si = rd.z, ui = rd.w;
-          K rmin = IK::big();
-          static_for<DT>([&](auto tc) {
-            // slot t is a fixed diagonal (C[t] and its code); the column it
-            // meets moves one register per row (p)
-            constexpr int t = decltype(tc)::value;
-            constexpr int p = (t + r) % DT;
-            const F key = fma(-(C[t] * si), S[p], ui);
-            const K kb = IK::make(key, (unsigned)(lane * DT + t));
-            CP[p] = IK::kmin(CP[p], kb);
-            rmin = IK::kmin(rmin, kb);
-            C[t] = fma(A[p], gi, C[t]);
-            C[t] = fma(G[p], ai, C[t]);
+      const int nb = (int)min((int64_t)TP, nsteps - sb);  // a multiple of DT (even)
+      static_for<TP / 2>([&](auto qc) {
+        constexpr int u0 = 2 * decltype(qc)::value, u1 = u0 + 1;
+        constexpr int r0 = u0 % DT, r1 = u1 % DT;  // register of slot 0 in each row
+        if (u0 < nb) {
+          K k0[DT], k1[DT];
+          // ---- row u0
+          {
+            const V4 rd = ldu(rowd + i0 + sb + u0);
+            const F ai = rd.x, gi = rd.y, si = rd.z, ui = rd.w;
+            static_for<DT>([&](auto tc) {
+              constexpr int t = decltype(tc)::value;
+              constexpr int p = (t + r0) % DT;
+              k0[t] = IK::make(fma(-(C[t] * si), S[p], ui), (unsigned)(lane * DT + t));
+              C[t] = fma(A[p], gi, C[t]);
+              C[t] = fma(G[p], ai, C[t]);
+            });
+            lrow[u0][lane] = IK::rowmin(k0);
+            CP[r0] = IK::kmin(CP[r0], k0[0]);
+            if (lane == 0) lcol[u0] = CP[r0];
+            const V4 nc = ldu(newcol + sb + u0);
+            CP[r0] = IK::shl(CP[r0]);
+            A[r0] = shlv<F>(A[r0], nc.x);
+            G[r0] = shlv<F>(G[r0], nc.y);
+            S[r0] = shlv<F>(S[r0], nc.z);
+          }
+          // ---- row u1
+          {
+            const V4 rd = ldu(rowd + i0 + sb + u1);
+            const F ai = rd.x, gi = rd.y, si = rd.z, ui = rd.w;
+            static_for<DT>([&](auto tc) {
+              constexpr int t = decltype(tc)::value;
+              constexpr int p = (t + r1) % DT;
+              k1[t] = IK::make(fma(-(C[t] * si), S[p], ui), (unsigned)(lane * DT + t));
+              C[t] = fma(A[p], gi, C[t]);
+              C[t] = fma(G[p], ai, C[t]);
+            });
+            lrow[u1][lane] = IK::rowmin(k1);
+          }
+          // ---- column minima: register p met slot p-r0 in row u0 and slot
+          // p-r1 in row u1; register r0 holds the column that entered after
+          // row u0 and met only slot DT-1 of row u1
+          static_for<DT>([&](auto pc) {
+            constexpr int p = decltype(pc)::value;
+            if constexpr (p == r0) {
+              CP[p] = IK::kmin(CP[p], k1[DT - 1]);
+            } else {
+              CP[p] = IK::kmin3(CP[p], k0[(p - r0 + DT) % DT], k1[(p - r1 + DT) % DT]);
+            }
           });
-          lrow[u][lane] = rmin;
-          if (lane == 0) lcol[u] = CP[r];
-          const V4 nc = ldu(newcol + s);
-          CP[r] = IK::shl(CP[r]);
-          A[r] = shlv<F>(A[r], nc.x);
-          G[r] = shlv<F>(G[r], nc.y);
-          S[r] = shlv<F>(S[r], nc.z);
+          if (lane == 0) lcol[u1] = CP[r1];
+          const V4 nc = ldu(newcol + sb + u1);
+          CP[r1] = IK::shl(CP[r1]);
+          A[r1] = shlv<F>(A[r1], nc.x);
+          G[r1] = shlv<F>(G[r1], nc.y);
+          S[r1] = shlv<F>(S[r1], nc.z);
         }
       });
       flush(sb, nb);
