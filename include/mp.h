@@ -147,10 +147,15 @@ void mp_batch_plan_destroy(mp_batch_plan *plan);
  * derivative of d(i, j) = ||z_i - z_j|| through z = (x - mean)/sigma):
  *   dd/dT[i:i+m] = (rho z_i - z_j) / (sigma_i d),
  *   dd/dT[j:j+m] = (rho z_j - z_i) / (sigma_j d),   rho = z_i.z_j / m.
- * Rows with I < 0, d == 0 or a constant window contribute nothing.
+ * Rows with I < 0 (or I outside the series), a zero or non-finite gP, d == 0,
+ * or a constant or non-finite window on either side contribute nothing.
+ * Accumulation is in FP64 without atomics on values: the same inputs give
+ * bitwise the same gT.  Any I is accepted (hub neighbours included); the
+ * cost is O(total_l * m) plus, per neighbour window, the square of its
+ * number of referring rows.
  * Uses the batch plan's layout: T_cat / I_cat / gP_cat as for mp_batch,
  * gT_cat (n values per series, `dtype`) is overwritten.  The workspace is
- * the plan's workspace.
+ * the plan's workspace (its forward contents are overwritten).
  */
 mp_status mp_backward(const mp_batch_plan *plan, const void *T_cat, const int64_t *I_cat,
                       const void *gP_cat, void *gT_cat, void *ws, size_t ws_bytes,

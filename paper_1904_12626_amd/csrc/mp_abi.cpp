@@ -155,8 +155,9 @@ void finish_job(Job &j) {
 }
 
 struct Layout {
-  size_t mu, sig, keys, flags, nc, nv, rc, special, counters, segp, segs, rescan, grad, sdesc,
-      wdesc, total;
+  size_t mu, sig, keys, flags, nc, nv, rc, special, counters, segp, segs, rescan, sdesc, wdesc;
+  size_t b_mu, b_isig, b_coef, b_nbr, b_count, b_fill, b_off, b_tmp, b_rows, b_chunk;
+  size_t total;
 };
 
 Layout layout_of(const Job &j, bool with_batch_tables) {
@@ -181,7 +182,16 @@ Layout layout_of(const Job &j, bool with_batch_tables) {
   L.segs = take(4 * std::max<size_t>(1, (size_t)j.nseg));
   L.rescan = take(8 * tl);
   if (with_batch_tables) {
-    L.grad = take(8 * (size_t)j.total_n);
+    L.b_mu = take(8 * tl);
+    L.b_isig = take(8 * tl);
+    L.b_coef = take(32 * tl);
+    L.b_nbr = take(8 * tl);
+    L.b_count = take(4 * tl);
+    L.b_fill = take(4 * tl);
+    L.b_off = take(8 * (tl + 1));
+    L.b_tmp = take(8 * tl);
+    L.b_rows = take(8 * tl);
+    L.b_chunk = take(8 * ((tl + 1023) / 1024 + 1));
     L.sdesc = take(sizeof(SeriesDesc) * j.series.size());
     L.wdesc = take(sizeof(SweepDesc) * j.sweeps.size());
   }
@@ -204,7 +214,22 @@ mpx::Work work_of(const Layout &L, void *ws) {
   w.seg_prefix = (int64_t *)(b + L.segp);
   w.seg_sweep = (int32_t *)(b + L.segs);
   w.rescan = (int64_t *)(b + L.rescan);
-  w.grad = L.grad ? (double *)(b + L.grad) : nullptr;
+  return w;
+}
+
+mpx::BwdWork bwd_work_of(const Layout &L, void *ws) {
+  char *b = (char *)ws;
+  mpx::BwdWork w{};
+  w.mu = (double *)(b + L.b_mu);
+  w.isig = (double *)(b + L.b_isig);
+  w.coef = (double *)(b + L.b_coef);
+  w.nbr = (int64_t *)(b + L.b_nbr);
+  w.count = (int32_t *)(b + L.b_count);
+  w.fill = (int32_t *)(b + L.b_fill);
+  w.off = (int64_t *)(b + L.b_off);
+  w.tmp = (int64_t *)(b + L.b_tmp);
+  w.rows = (int64_t *)(b + L.b_rows);
+  w.chunk = (int64_t *)(b + L.b_chunk);
   return w;
 }
 
@@ -521,7 +546,7 @@ mp_status mp_backward(const mp_batch_plan *pl, const void *T_cat, const int64_t 
     return MP_EINVAL;
   mp_status s = check_ws(ws, ws_bytes, pl->lay.total);
   if (s != MP_OK) return s;
-  const mpx::Work w = work_of(pl->lay, ws);
+  const mpx::BwdWork w = bwd_work_of(pl->lay, ws);
   const mpx::Plan p = plan_of(pl->job, pl->lay, ws, true);
   if (mpx::launch_backward(p, w, T_cat, pl->job.t_f64, I_cat, gP_cat, gT_cat, pl->job.total_l,
                            pl->job.total_n, (hipStream_t)stream) != hipSuccess)

@@ -71,7 +71,21 @@ struct Work {
   int64_t *seg_prefix; // [nseg + 1] first tile of each strip
   int32_t *seg_sweep;  // [nseg] sweep of each strip
   int64_t *rescan;     // [total_l] windows needing an exact row scan
-  double *grad;        // [total_n] FP64 gradient accumulator (batch plans)
+};
+
+// Backward workspace (batch plans): per-window gradient coefficients and the
+// rows bucketed by neighbour window.
+struct BwdWork {
+  double *mu;          // [total_l] window mean
+  double *isig;        // [total_l] 1/sigma, 0 for constant or non-finite windows
+  double *coef;        // [4 total_l] per row: own-window z_i, z_j, neighbour-window z_j, z_i
+  int64_t *nbr;        // [total_l] neighbour window (global), -1 if the row contributes nothing
+  int32_t *count;      // [total_l] rows per neighbour window
+  int32_t *fill;       // [total_l] placement cursor per bucket
+  int64_t *off;        // [total_l + 1] bucket offsets (exclusive prefix of count)
+  int64_t *tmp;        // [total_l] rows in placement order
+  int64_t *rows;       // [total_l] rows per bucket in increasing order
+  int64_t *chunk;      // [ceil(total_l / 1024)] scan partials
 };
 
 struct Outputs {
@@ -96,7 +110,7 @@ hipError_t launch_recheck(const void *T, bool t_f64, int64_t n, int32_t m, const
                           bool p_f64, const int64_t *I, int32_t km, int32_t kd, int64_t *out_idx,
                           double *out_dist, uint8_t *ws, hipStream_t st);
 size_t recheck_state_bytes();
-hipError_t launch_backward(const Plan &plan, const Work &w, const void *T, bool t_f64,
+hipError_t launch_backward(const Plan &plan, const BwdWork &b, const void *T, bool t_f64,
                            const int64_t *I, const void *gP, void *gT, int64_t total_l,
                            int64_t total_n, hipStream_t st);
 

@@ -49,3 +49,61 @@ def test_backward_float32_against_fd():
         assert abs(fd - g[b, t]) <= 1e-3 * max(1.0, abs(fd)), (b, t, fd, g[b, t])
     ref = O.reference_gradient(T64[0], m, Ih[0], np.ones(Ih.shape[1]))
     np.testing.assert_allclose(g[0], ref, rtol=1e-4, atol=1e-4 * np.abs(ref).max())
+
+
+def _batch(lengths, ms, seed, dtype):
+    rng = np.random.default_rng(seed)
+    return [np.cumsum(rng.standard_normal(n)).astype(dtype) for n in lengths]
+
+
+def test_backward_ragged_deterministic():
+    """Ragged batch, different windows per series: the gradient matches the
+    FP64 reference per series and two runs are bitwise equal."""
+    import paper_1904_12626_amd as mpx
+    lengths, ms = [900, 333, 1500, 64], [24, 16, 40, 8]
+    zs = [m // 4 for m in ms]
+    series = _batch(lengths, ms, 11, np.float64)
+    Tg = torch.from_numpy(np.concatenate(series)).to(DEV)
+    plan = mpx.BatchPlan(lengths, ms, zs, dtype=torch.float64, device=DEV, precision="f64")
+    P, I = plan.run(Tg)
+    gP = torch.from_numpy(np.random.default_rng(12).uniform(-1, 2, P.shape)).to(DEV)
+    g1 = plan.backward(Tg, I, gP).clone()
+    g2 = plan.backward(Tg, I, gP)
+    torch.cuda.synchronize()
+    assert torch.equal(g1, g2)
+    gs = np.split(g1.cpu().numpy(), np.cumsum(lengths)[:-1])
+    Is, gPs = plan.split(I.cpu().numpy()), plan.split(gP.cpu().numpy())
+    for s in range(len(lengths)):
+        ref = O.reference_gradient(series[s], ms[s], Is[s], gPs[s])
+        np.testing.assert_allclose(gs[s], ref, rtol=1e-9, atol=1e-9 * max(1.0, np.abs(ref).max()))
+
+
+def test_backward_hub_constant_and_nan_windows():
+    """A hand-made index with hub neighbours (half the rows point at one
+    window), out-of-range and negative entries, a constant stretch and a NaN
+    sample, exact repeats and a self pair: the kernel takes the same
+    subgradient-0 rules as the reference."""
+    import paper_1904_12626_amd as mpx
+    n, m = 1200, 32
+    T = np.cumsum(np.random.default_rng(21).standard_normal(n))
+    T[300:400] = 2.5              # constant windows 300..368
+    T[800] = np.nan               # windows 769..800 invalid
+    T[600:640] = T[100:140]       # exact repeats: d(100, 600) = d(101, 601) = 0
+    l = n - m + 1
+    rng = np.random.default_rng(22)
+    I = rng.integers(0, l, l)
+    I[::2] = 500                  # hub
+    I[1::7] = 123                 # second hub
+    I[5::11] = -1
+    I[3::13] = l + 5              # outside the series: ignored
+    I[100], I[101], I[413] = 600, 601, 413   # zero distance, self pair
+    gP = rng.uniform(0.5, 1.5, l)
+    plan = mpx.BatchPlan([n], [m], [m // 4], dtype=torch.float64, device=DEV, precision="f64")
+    Tg = torch.from_numpy(T).to(DEV)
+    g = plan.backward(Tg, torch.from_numpy(I).to(DEV), torch.from_numpy(gP).to(DEV))
+    g = g.cpu().numpy()
+    Iref = np.where(I >= l, -1, I)
+    ref = O.reference_gradient(T, m, Iref, gP)
+    assert np.all(np.isfinite(g))
+    bad = np.flatnonzero(np.abs(g - ref) > 1e-9 * np.abs(ref).max() + 1e-9 * np.abs(ref))
+    assert bad.size == 0, (bad[:70].tolist(), g[bad[:8]].tolist(), ref[bad[:8]].tolist())
