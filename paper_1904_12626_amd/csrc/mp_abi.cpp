@@ -156,7 +156,7 @@ void finish_job(Job &j) {
 
 struct Layout {
   size_t mu, sig, keys, flags, nc, nv, rc, special, counters, segp, segs, rescan, sdesc, wdesc;
-  size_t b_mu, b_isig, b_coef, b_nbr, b_count, b_fill, b_off, b_tmp, b_rows, b_chunk;
+  size_t b_mu, b_isig, b_coef, b_nbr, b_count, b_fill, b_off, b_tmp, b_erec, b_wrec, b_chunk;
   size_t total;
 };
 
@@ -186,11 +186,12 @@ Layout layout_of(const Job &j, bool with_batch_tables) {
     L.b_isig = take(8 * tl);
     L.b_coef = take(32 * tl);
     L.b_nbr = take(8 * tl);
-    L.b_count = take(4 * tl);
-    L.b_fill = take(4 * tl);
+    L.b_count = take(8 * tl);
+    L.b_fill = take(8 * tl);
     L.b_off = take(8 * (tl + 1));
-    L.b_tmp = take(8 * tl);
-    L.b_rows = take(8 * tl);
+    L.b_tmp = take(8 * 2 * tl);  // indexed like erec
+    L.b_erec = take(sizeof(mpx::BwdEdge) * 2 * tl);
+    L.b_wrec = take(sizeof(mpx::BwdWin) * tl);
     L.b_chunk = take(8 * ((tl + 1023) / 1024 + 1));
     L.sdesc = take(sizeof(SeriesDesc) * j.series.size());
     L.wdesc = take(sizeof(SweepDesc) * j.sweeps.size());
@@ -224,11 +225,12 @@ mpx::BwdWork bwd_work_of(const Layout &L, void *ws) {
   w.isig = (double *)(b + L.b_isig);
   w.coef = (double *)(b + L.b_coef);
   w.nbr = (int64_t *)(b + L.b_nbr);
-  w.count = (int32_t *)(b + L.b_count);
-  w.fill = (int32_t *)(b + L.b_fill);
+  w.count = (unsigned long long *)(b + L.b_count);
+  w.fill = (unsigned long long *)(b + L.b_fill);
   w.off = (int64_t *)(b + L.b_off);
   w.tmp = (int64_t *)(b + L.b_tmp);
-  w.rows = (int64_t *)(b + L.b_rows);
+  w.erec = (mpx::BwdEdge *)(b + L.b_erec);
+  w.wrec = (mpx::BwdWin *)(b + L.b_wrec);
   w.chunk = (int64_t *)(b + L.b_chunk);
   return w;
 }

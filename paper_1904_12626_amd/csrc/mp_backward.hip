@@ -9,10 +9,14 @@
 // Deterministic gather: each row's contribution is four coefficients
 //   on window i:  alpha z_i + beta z_j,   alpha = g rho/(sigma_i d), beta = -g/(sigma_i d)
 //   on window j:  gamma z_j + delta z_i,  gamma = g rho/(sigma_j d), delta = -g/(sigma_j d)
-// Rows are bucketed by their neighbour j (counting sort, each bucket then
-// ordered by row index), and every output sample sums, in a fixed order, the rows
-// whose own window covers it and the rows whose neighbour window covers it.
-// No floating-point atomics: reruns are bitwise identical.
+// Per destination window w, the multiples of z_w (its own alpha and the
+// gammas of the rows whose neighbour is w) are summed in a fixed order; the
+// multiples of other windows' z are edges grouped by w (the row's own beta
+// edge, then the rows naming w as neighbour, in increasing row order).  A
+// wave then produces 64 consecutive gradient samples by walking the windows
+// that cover them in order, with the window and edge records uniform across
+// the wave and the source samples loaded contiguously.  No floating-point
+// atomics: reruns are bitwise identical.
 #include <cmath>
 
 #include "mp_internal.h"
@@ -77,8 +81,8 @@ __global__ void __launch_bounds__(256) k_bwd_stats(Plan plan, BwdWork b, const T
   const double sg = sqrt(q / m);
   b.mu[wi] = ok ? mu : 0.0;
   b.isig[wi] = (ok && lo != hi && sg > 0.0) ? 1.0 / sg : 0.0;
-  b.count[wi] = 0;
-  b.fill[wi] = 0;
+  b.count[wi] = 0ull;
+  b.fill[wi] = 0ull;
 }
 
 // Per-row coefficients; counts rows per neighbour window.
@@ -120,17 +124,20 @@ __global__ void __launch_bounds__(256) k_bwd_coef(Plan plan, BwdWork b, const Ti
   reinterpret_cast<Double4 *>(b.coef)[wi] = c;
   const bool live = (c.x != 0.0 || c.y != 0.0 || c.z != 0.0 || c.w != 0.0);
   b.nbr[wi] = live ? jw : -1;
-  if (live) atomicAdd(&b.count[jw], 1);
+  if (live) {
+    atomicAdd(&b.count[jw], 1ull);  // bucket edge on the neighbour window
+    atomicAdd(&b.count[wi], 1ull);  // own edge
+  }
 }
 
 // Exclusive prefix sum of count[0..n) into off[0..n]: one workgroup per
 // chunk of 1024 entries, then a single workgroup over the chunk totals, then
 // the chunk offsets are added back.
-__global__ void __launch_bounds__(1024) k_scan_chunks(const int32_t *__restrict__ cnt, int64_t *off,
+__global__ void __launch_bounds__(1024) k_scan_chunks(const unsigned long long *__restrict__ cnt, int64_t *off,
                                                       int64_t *chunk_tot, int64_t n) {
   __shared__ int64_t sh[1024];
   const int64_t x = (int64_t)blockIdx.x * 1024 + threadIdx.x;
-  const int64_t v = x < n ? cnt[x] : 0;
+  const int64_t v = x < n ? (int64_t)cnt[x] : 0;
   sh[threadIdx.x] = v;
   __syncthreads();
   for (int d = 1; d < 1024; d <<= 1) {
@@ -177,69 +184,99 @@ __global__ void __launch_bounds__(1024) k_scan_add(int64_t *off, const int64_t *
   if (x < n) off[x] += chunk_tot[blockIdx.x];
 }
 
-// Bucket the live rows by neighbour window (arbitrary order within a bucket).
+// Own edge of each live row (first slot of its window) and its bucket entry
+// on the neighbour window (after that window's own edge, arbitrary order).
 __global__ void __launch_bounds__(256) k_bwd_place(BwdWork b, int64_t total_l) {
   const int64_t wi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (wi >= total_l) return;
   const int64_t jw = b.nbr[wi];
   if (jw < 0) return;
-  const int pos = atomicAdd(&b.fill[jw], 1);
-  b.tmp[b.off[jw] + pos] = wi;
+  const Double4 c = reinterpret_cast<const Double4 *>(b.coef)[wi];
+  b.erec[b.off[wi]] = BwdEdge{c.y * b.isig[jw], b.mu[jw], jw - wi, 0.0};
+  const int64_t base = b.off[jw] + (b.nbr[jw] >= 0 ? 1 : 0);
+  const unsigned long long pos = atomicAdd(&b.fill[jw], 1ull);
+  b.tmp[base + (int64_t)pos] = wi;
 }
 
-// Deterministic order within each bucket: a row's slot is the number of rows
-// of its bucket with a smaller index.
+// Bucket edges in increasing row order: a row's slot is the number of rows of
+// its bucket with a smaller index.
 __global__ void __launch_bounds__(256) k_bwd_rank(BwdWork b, int64_t total_l) {
   const int64_t wi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (wi >= total_l) return;
   const int64_t jw = b.nbr[wi];
   if (jw < 0) return;
-  const int64_t a = b.off[jw], e = b.off[jw + 1];
+  const int64_t a = b.off[jw] + (b.nbr[jw] >= 0 ? 1 : 0), e = b.off[jw + 1];
   int64_t r = 0;
   for (int64_t p = a; p < e; ++p) r += b.tmp[p] < wi;
-  b.rows[a + r] = wi;
+  const Double4 c = reinterpret_cast<const Double4 *>(b.coef)[wi];
+  b.erec[a + r] = BwdEdge{c.w * b.isig[wi], b.mu[wi], wi - jw, c.z};
 }
 
-// One output sample: contributions of the rows whose window covers it and of
-// the rows whose neighbour window covers it, in increasing window order.
+// Per window: its own alpha plus the gammas of its bucket, in edge order.
+__global__ void __launch_bounds__(256) k_bwd_window(BwdWork b, int64_t total_l) {
+  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= total_l) return;
+  const bool own = b.nbr[w] >= 0;
+  double s = own ? b.coef[4 * w] : 0.0;
+  for (int64_t p = b.off[w] + (own ? 1 : 0), e = b.off[w + 1]; p < e; ++p) s += b.erec[p].gam;
+  b.wrec[w] = BwdWin{s * b.isig[w], b.mu[w]};
+}
+
+__device__ __forceinline__ int64_t uni64(int64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Windows covering global sample x: [lo, hi] (global window indices).
+__device__ __forceinline__ void covering(const Plan &plan, int64_t x, int64_t &lo, int64_t &hi) {
+  const SeriesDesc S = plan.series(find_series_by_t(plan, x));
+  const int64_t t = x - S.t_off;
+  lo = S.w_off + max((int64_t)0, t - S.m + 1);
+  hi = S.w_off + min(t, S.l - 1);
+}
+
+// One wave = 64 consecutive samples.  Every sample of a series is covered by
+// at least one window and the covering ranges are non-decreasing in the
+// sample index, so the wave walks [lo(first sample), hi(last sample)].
 template <typename Tin, typename Tg>
 __global__ void __launch_bounds__(256) k_bwd_gather(Plan plan, BwdWork b, const Tin *__restrict__ Tb,
                                                     Tg *gT, int64_t total_n) {
   const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (x >= total_n) return;
-  const SeriesDesc S = plan.series(find_series_by_t(plan, x));
-  const int64_t t = x - S.t_off;
-  const int m = S.m;
-  const double xt = (double)Tb[x];
-  const int64_t w_lo = max((int64_t)0, t - m + 1), w_hi = min(t, S.l - 1);
+  const int64_t x0 = uni64(x - (int64_t)(threadIdx.x & 63));
+  if (x0 >= total_n) return;
+  const int64_t xl = min(x0 + 63, total_n - 1);
+  const bool act = x < total_n;
+  int64_t lo_t, hi_t, lo_w, hi_w, dummy;
+  covering(plan, act ? x : xl, lo_t, hi_t);
+  if (!act) { lo_t = 1; hi_t = 0; }
+  covering(plan, x0, lo_w, dummy);
+  covering(plan, xl, dummy, hi_w);
+  lo_w = uni64(lo_w);
+  hi_w = uni64(hi_w);
+  const Tin *xp = Tb + (act ? x : xl);
+  const double xt = (double)*xp;
+  const BwdWin *__restrict__ wrec = b.wrec;
+  const BwdEdge *__restrict__ erec = b.erec;
+  const int64_t *__restrict__ off = b.off;
   double acc = 0.0;
-  for (int64_t w = w_lo; w <= w_hi; ++w) {
-    const int64_t wi = S.w_off + w;
-    // row w's own window covers t
-    const int64_t jw = b.nbr[wi];
-    if (jw >= 0) {
-      const Double4 c = reinterpret_cast<const Double4 *>(b.coef)[wi];
-      const int64_t u = t - w;
-      const double zi = (xt - b.mu[wi]) * b.isig[wi];
-      const double zj = ((double)Tb[S.t_off + (jw - S.w_off) + u] - b.mu[jw]) * b.isig[jw];
-      acc = fma(c.x, zi, acc);
-      acc = fma(c.y, zj, acc);
-    }
-    // rows whose neighbour is window w
-    const int64_t a = b.off[wi], e = b.off[wi + 1];
-    if (a < e) {
-      const double zw = (xt - b.mu[wi]) * b.isig[wi];
-      const int64_t u = t - w;
-      for (int64_t p = a; p < e; ++p) {
-        const int64_t ri = b.rows[p];
-        const Double4 c = reinterpret_cast<const Double4 *>(b.coef)[ri];
-        const double zr = ((double)Tb[S.t_off + (ri - S.w_off) + u] - b.mu[ri]) * b.isig[ri];
-        acc = fma(c.z, zw, acc);
-        acc = fma(c.w, zr, acc);
+  int64_t e0 = off[lo_w];
+  for (int64_t d = lo_w; d <= hi_w; ++d) {
+    const BwdWin wr = wrec[d];
+    const int64_t e1 = off[d + 1];
+    const bool in = d >= lo_t && d <= hi_t;
+    if (in) {
+      // sc is 0 for windows without gradient, including non-finite ones
+      // whose samples must not reach the sum
+      if (wr.sc != 0.0) acc = fma(wr.sc, xt - wr.mu, acc);
+      for (int64_t p = e0; p < e1; ++p) {
+        const BwdEdge q = erec[p];
+        acc = fma(q.c, (double)xp[q.delta] - q.mu, acc);
       }
     }
+    e0 = e1;
   }
-  gT[x] = (Tg)acc;
+  if (act) gT[x] = (Tg)acc;
 }
 
 hipError_t launch_backward(const Plan &plan, const BwdWork &b, const void *T, bool t_f64,
@@ -257,13 +294,14 @@ hipError_t launch_backward(const Plan &plan, const BwdWork &b, const void *T, bo
     hipLaunchKernelGGL((k_bwd_coef<float, float>), gl, blk, 0, st, plan, b, (const float *)T, I,
                        (const float *)gP, total_l);
   }
-  hipLaunchKernelGGL(k_scan_chunks, dim3((unsigned)nchunks), dim3(1024), 0, st, (const int32_t *)b.count,
+  hipLaunchKernelGGL(k_scan_chunks, dim3((unsigned)nchunks), dim3(1024), 0, st, (const unsigned long long *)b.count,
                      b.off, b.chunk, total_l);
   hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(1024), 0, st, b.chunk, nchunks, b.off, total_l);
   hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nchunks), dim3(1024), 0, st, b.off, (const int64_t *)b.chunk,
                      total_l);
   hipLaunchKernelGGL(k_bwd_place, gl, blk, 0, st, b, total_l);
   hipLaunchKernelGGL(k_bwd_rank, gl, blk, 0, st, b, total_l);
+  hipLaunchKernelGGL(k_bwd_window, gl, blk, 0, st, b, total_l);
   if (t_f64)
     hipLaunchKernelGGL((k_bwd_gather<double, double>), gn, blk, 0, st, plan, b, (const double *)T,
                        (double *)gT, total_n);

@@ -73,19 +73,35 @@ struct Work {
   int64_t *rescan;     // [total_l] windows needing an exact row scan
 };
 
-// Backward workspace (batch plans): per-window gradient coefficients and the
-// rows bucketed by neighbour window.
+// Backward workspace (batch plans).  The gradient of one row i -> j is a
+// multiple of z_i plus a multiple of z_j on window i, and the same on window
+// j.  Per destination window the multiples of its own z are summed into one
+// coefficient (`wrec`); every multiple of another window's z is an edge
+// (`erec`): coefficient, source mean and source offset.  Edges are grouped by
+// destination window (CSR `off`), the row's own edge first, then the rows
+// that name this window as neighbour, in increasing row order.
+struct BwdEdge {
+  double c;      // coefficient on (x[t + delta] - mu)
+  double mu;     // mean of the source window
+  int64_t delta; // source window start - destination window start
+  double gam;    // (bucket edges) the row's multiple of the destination z
+};
+struct BwdWin {
+  double sc;     // summed multiple of this window's z, times 1/sigma
+  double mu;     // mean of this window
+};
 struct BwdWork {
   double *mu;          // [total_l] window mean
   double *isig;        // [total_l] 1/sigma, 0 for constant or non-finite windows
-  double *coef;        // [4 total_l] per row: own-window z_i, z_j, neighbour-window z_j, z_i
+  double *coef;        // [4 total_l] per row: alpha, beta (window i), gamma, delta (window j)
   int64_t *nbr;        // [total_l] neighbour window (global), -1 if the row contributes nothing
-  int32_t *count;      // [total_l] rows per neighbour window
-  int32_t *fill;       // [total_l] placement cursor per bucket
-  int64_t *off;        // [total_l + 1] bucket offsets (exclusive prefix of count)
-  int64_t *tmp;        // [total_l] rows in placement order
-  int64_t *rows;       // [total_l] rows per bucket in increasing order
-  int64_t *chunk;      // [ceil(total_l / 1024)] scan partials
+  unsigned long long *count;  // [total_l] edges per destination window
+  unsigned long long *fill;   // [total_l] placement cursor per bucket
+  int64_t *off;        // [total_l + 1] edge offsets (exclusive prefix of count)
+  int64_t *tmp;        // [2 total_l] bucket rows in placement order (edge slots)
+  BwdEdge *erec;       // [2 total_l] edges
+  BwdWin *wrec;        // [total_l] per-window self coefficient
+  int64_t *chunk;      // [ceil(total_l / 1024) + 1] scan partials
 };
 
 struct Outputs {
