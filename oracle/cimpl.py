@@ -38,6 +38,8 @@ def _load():
     d, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
     lib.mpo_selfjoin_rows.argtypes = [d, i64, i32, i64, d, i64, d, d]
     lib.mpo_selfjoin_rows.restype = ctypes.c_int
+    lib.mpo_selfjoin_rows_restricted.argtypes = [d, i64, i32, i64, d, i32, d, i64, d, d]
+    lib.mpo_selfjoin_rows_restricted.restype = ctypes.c_int
     lib.mpo_abjoin_rows.argtypes = [d, i64, d, i64, i32, d, i64, d, d]
     lib.mpo_abjoin_rows.restype = ctypes.c_int
     lib.mpo_window_stats.argtypes = [d, i64, i32, d, d, d]
@@ -78,6 +80,31 @@ def abjoin_rows(A, B, m: int, rows):
     rc = lib.mpo_abjoin_rows(_p(A), A.size, _p(B), B.size, m, _p(rows), rows.size, _p(P), _p(I))
     if rc != 0:
         raise ValueError("mpo_abjoin_rows: bad arguments")
+    return P, I
+
+
+_SIDES = {"both": 0, "right": 1, "left": 2}
+
+
+def selfjoin_rows_restricted(T, m: int, ez: int, rows, allowed=None, side: str = "both"):
+    """Self-join entries for `rows` over the candidates j on `side` of i
+    ("right": j > i, "left": j < i) whose offset |i - j| has allowed[k]
+    (boolean array of l entries; None = every offset)."""
+    lib = _load()
+    T = np.ascontiguousarray(T, dtype=np.float64)
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    l = T.size - m + 1
+    al = None
+    if allowed is not None:
+        al = np.ascontiguousarray(np.asarray(allowed, dtype=bool).astype(np.uint8))
+        if al.size != l:
+            raise ValueError("allowed must have l entries")
+    P = np.empty(rows.size)
+    I = np.empty(rows.size, dtype=np.int64)
+    rc = lib.mpo_selfjoin_rows_restricted(_p(T), T.size, m, ez, None if al is None else _p(al), _SIDES[side],
+                                          _p(rows), rows.size, _p(P), _p(I))
+    if rc != 0:
+        raise ValueError("mpo_selfjoin_rows_restricted: bad arguments")
     return P, I
 
 

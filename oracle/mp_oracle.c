@@ -66,17 +66,22 @@ static void znorm_window(const double *w, int32_t m, double mu, double sig,
 }
 
 /* Row i of A against every window of B.  ez < 0 means "no exclusion"
- * (AB-join); otherwise pairs with |i - j| <= ez are skipped (self-join). */
+ * (AB-join); otherwise pairs with |i - j| <= ez are skipped (self-join).
+ * Self-joins may be narrowed further: side 1 keeps j > i only, side 2 j < i
+ * only; allow (may be NULL) keeps the offsets k = |i - j| with allow[k]. */
 static void one_row(const double *A, const double *B, int64_t lB, int32_t m,
                     int64_t ez, int64_t i, const double *za, const double *muB,
                     const double *sgB, const int8_t *fB, double *zb,
-                    double *P, int64_t *I) {
+                    const uint8_t *allow, int side, double *P, int64_t *I) {
   double best = INFINITY;
   int64_t arg = -1;
   (void)A;
   for (int64_t j = 0; j < lB; j++) {
     if (!(fB[j] & 1)) continue;
     if (ez >= 0 && llabs(i - j) <= ez) continue;
+    if (ez >= 0 && side == 1 && j < i) continue;
+    if (ez >= 0 && side == 2 && j > i) continue;
+    if (ez >= 0 && allow && !allow[llabs(i - j)]) continue;
     znorm_window(B + j, m, muB[j], sgB[j], fB[j], zb);
     double s = 0.0;
     for (int32_t u = 0; u < m; u++) {
@@ -94,8 +99,8 @@ static void one_row(const double *A, const double *B, int64_t lB, int32_t m,
 }
 
 static int join_rows(const double *A, int64_t nA, const double *B, int64_t nB,
-                     int32_t m, int64_t ez, const int64_t *rows, int64_t nrows,
-                     double *P, int64_t *I) {
+                     int32_t m, int64_t ez, const uint8_t *allow, int side,
+                     const int64_t *rows, int64_t nrows, double *P, int64_t *I) {
   int64_t lA = nA - m + 1, lB = nB - m + 1;
   if (m < 2 || lA < 1 || lB < 1) return -1;
   double *muA = malloc(sizeof(double) * lA), *sgA = malloc(sizeof(double) * lA);
@@ -122,7 +127,8 @@ static int join_rows(const double *A, int64_t nA, const double *B, int64_t nB,
         continue;
       }
       znorm_window(A + i, m, muA[i], sgA[i], fA[i], za);
-      one_row(A, B, lB, m, ez, i, za, muB, sgB, fB, zb, P + r, I + r);
+      one_row(A, B, lB, m, ez, i, za, muB, sgB, fB, zb, allow, side, P + r,
+              I + r);
     }
     free(za);
     free(zb);
@@ -143,7 +149,18 @@ int mpo_selfjoin_rows(const double *T, int64_t n, int32_t m, int64_t ez,
                       const int64_t *rows, int64_t nrows, double *P,
                       int64_t *I) {
   if (ez < 0) return -1;
-  return join_rows(T, n, T, n, m, ez, rows, nrows, P, I);
+  return join_rows(T, n, T, n, m, ez, NULL, 0, rows, nrows, P, I);
+}
+
+/* Self-join entries restricted to one side (side 1: j > i, the right
+ * profile; side 2: j < i, the left profile; 0: both) and to the offsets
+ * |i - j| with allow[|i - j|] != 0 (allow has l entries; NULL = all). */
+int mpo_selfjoin_rows_restricted(const double *T, int64_t n, int32_t m,
+                                 int64_t ez, const uint8_t *allow, int32_t side,
+                                 const int64_t *rows, int64_t nrows, double *P,
+                                 int64_t *I) {
+  if (ez < 0 || side < 0 || side > 2) return -1;
+  return join_rows(T, n, T, n, m, ez, allow, side, rows, nrows, P, I);
 }
 
 /* Exact AB-join entries P_AB[r], I_AB[r] for rows[r] of A (call with the
@@ -151,7 +168,7 @@ int mpo_selfjoin_rows(const double *T, int64_t n, int32_t m, int64_t ez,
 int mpo_abjoin_rows(const double *A, int64_t nA, const double *B, int64_t nB,
                     int32_t m, const int64_t *rows, int64_t nrows, double *P,
                     int64_t *I) {
-  return join_rows(A, nA, B, nB, m, -1, rows, nrows, P, I);
+  return join_rows(A, nA, B, nB, m, -1, NULL, 0, rows, nrows, P, I);
 }
 
 int mpo_max_threads(void) {

@@ -55,6 +55,7 @@ __all__ = [
     "pair_distance",
     "distance_matrix",
     "selfjoin",
+    "selfjoin_restricted",
     "selfjoin_rows",
     "abjoin",
     "abjoin_rows",
@@ -194,6 +195,44 @@ def selfjoin(T, m: int, ez: int, block: int = 64):
         D = np.sqrt((diff * diff).sum(axis=2))
         D[:, ~valid] = np.inf
         D[np.abs(rows[:, None] - idx[None, :]) <= ez] = np.inf
+        for r, i in enumerate(rows):
+            if valid[i]:
+                P[i], I[i] = _row_min(D[r])
+    return P, I
+
+
+def selfjoin_restricted(T, m: int, ez: int, allowed=None, side: str = "both", block: int = 64):
+    """Self-join over a subset of the candidates: P[i] = min of d(i, j) over
+    |i-j| > ez with j on `side` of i ("right": j > i, "left": j < i,
+    "both") and allowed[|i-j|] (a boolean array over offsets 0..l-1; None =
+    every offset).
+
+    The anytime modes of Section 3.3 (STAMP, SCRIMP) return this profile for
+    the offsets processed so far; the left and right profiles used by time
+    series chains (Section 3.4.3) are its two one-sided cases.  Brute force
+    in the direct difference form, like `selfjoin`.
+    """
+    if side not in ("both", "left", "right"):
+        raise ValueError("side must be 'both', 'left' or 'right'")
+    Z, valid = znormalize(T, m)
+    l = Z.shape[0]
+    allow = np.ones(l, dtype=bool) if allowed is None else np.asarray(allowed, dtype=bool)
+    P = np.full(l, np.inf)
+    I = np.full(l, -1, dtype=np.int64)
+    Zv = np.where(valid[:, None], Z, 0.0)
+    idx = np.arange(l)
+    for s in range(0, l, block):
+        rows = idx[s:s + block]
+        diff = Zv[None, :, :] - Zv[rows, None, :]
+        D = np.sqrt((diff * diff).sum(axis=2))
+        D[:, ~valid] = np.inf
+        off = idx[None, :] - rows[:, None]          # j - i
+        D[np.abs(off) <= ez] = np.inf
+        D[~allow[np.abs(off)]] = np.inf
+        if side == "right":
+            D[off < 0] = np.inf
+        elif side == "left":
+            D[off > 0] = np.inf
         for r, i in enumerate(rows):
             if valid[i]:
                 P[i], I[i] = _row_min(D[r])

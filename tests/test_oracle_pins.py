@@ -331,6 +331,17 @@ def test_top_motifs_recover_planted_pairs():
             assert any(abs(a - x) <= pw.m // 8 and abs(b - y) <= pw.m // 8 for x, y in found)
 
 
+def test_top_discords_recover_planted_bursts():
+    """Windows overwritten by white noise are the top discords (the masked
+    argmax of P lands within m of each burst)."""
+    from workloads import planted_walk
+    for seed in (123, 77):
+        pw = planted_walk(6000, 64, seed=seed, n_motifs=3, n_discords=2, dtype=np.float64)
+        P, _ = cimpl.selfjoin(pw.T, pw.m, pw.m // 4)
+        for d in O.top_discords(P, pw.m, 2):
+            assert min(abs(d - b) for b in pw.discords) <= pw.m
+
+
 def test_top_discord_on_corrupted_sine():
     """A sine with one cycle replaced by noise: the top discord overlaps the
     corruption, and the motif pairs lie a whole number of periods apart."""
@@ -343,3 +354,91 @@ def test_top_discord_on_corrupted_sine():
     assert 1500 - m < d < 1550
     for i, j in O.top_motifs(P, I, m, 3):
         assert abs(i - j) % p == 0
+
+
+# ----------------------------------------------- restricted and one-sided joins
+
+def _pure_python_restricted(T, m, ez, allowed, side):
+    """Definition by loops: every pair through pair_distance."""
+    l = len(T) - m + 1
+    P = np.full(l, np.inf)
+    I = np.full(l, -1, dtype=np.int64)
+    for i in range(l):
+        for j in range(l):
+            k = j - i
+            if abs(k) <= ez or not allowed[abs(k)]:
+                continue
+            if (side == "right" and k < 0) or (side == "left" and k > 0):
+                continue
+            d = O.pair_distance(T, i, T, j, m)
+            if d < P[i]:
+                P[i], I[i] = d, j
+    return P, I
+
+
+@pytest.mark.parametrize("side", ["both", "left", "right"])
+def test_restricted_join_equals_loops(side):
+    rng = np.random.default_rng(40)
+    T = np.cumsum(rng.standard_normal(70))
+    m, ez = 8, 2
+    l = len(T) - m + 1
+    allowed = rng.random(l) < 0.4
+    P, I = O.selfjoin_restricted(T, m, ez, allowed, side)
+    Pl, Il = _pure_python_restricted(T, m, ez, allowed, side)
+    np.testing.assert_allclose(P, Pl, rtol=0, atol=1e-12)
+    assert np.array_equal(I, Il)
+    Pc, Ic = cimpl.selfjoin_rows_restricted(T, m, ez, np.arange(l), allowed, side)
+    np.testing.assert_allclose(Pc, P, rtol=0, atol=1e-12)
+    assert np.array_equal(Ic, I)
+
+
+def test_left_right_profiles_compose_the_profile():
+    """min(left, right) is the profile, the left one winning ties (its index
+    is the smaller); no left neighbour for i <= ez, no right one for
+    i >= l - 1 - ez."""
+    T = np.cumsum(np.random.default_rng(41).standard_normal(400))
+    m, ez = 20, 5
+    P, I = O.selfjoin(T, m, ez)
+    PL, IL = O.selfjoin_restricted(T, m, ez, side="left")
+    PR, IR = O.selfjoin_restricted(T, m, ez, side="right")
+    right = (IL < 0) | ((IR >= 0) & (PR < PL))
+    assert np.array_equal(np.where(right, PR, PL), P)
+    assert np.array_equal(np.where(right, IR, IL), I)
+    l = P.size
+    assert np.all(np.isinf(PL[:ez + 1])) and np.all(IL[:ez + 1] == -1)
+    assert np.all(np.isinf(PR[l - 1 - ez:])) and np.all(IR[l - 1 - ez:] == -1)
+    assert np.all(IL[ez + 1:] < np.arange(ez + 1, l) - ez)
+    assert np.all(IR[:l - 1 - ez] > np.arange(l - 1 - ez) + ez)
+
+
+def test_restricted_join_is_monotone_and_exact_on_its_offsets():
+    """More offsets never raise P; P[i] = d(i, I[i]) with |i - I[i]| allowed;
+    the full offset set gives the self-join."""
+    rng = np.random.default_rng(42)
+    T = np.cumsum(rng.standard_normal(500))
+    m, ez = 24, 6
+    l = T.size - m + 1
+    a = rng.random(l) < 0.2
+    b = a | (rng.random(l) < 0.3)
+    Pa, Ia = O.selfjoin_restricted(T, m, ez, a)
+    Pb, _ = O.selfjoin_restricted(T, m, ez, b)
+    assert np.all(Pb <= Pa)
+    for i in rng.choice(l, 20, replace=False):
+        if Ia[i] >= 0:
+            assert a[abs(i - Ia[i])] and abs(i - Ia[i]) > ez
+            assert abs(Pa[i] - O.pair_distance(T, i, T, int(Ia[i]), m)) < 1e-12
+    Pf, If = O.selfjoin_restricted(T, m, ez, np.ones(l, dtype=bool))
+    P, I = O.selfjoin(T, m, ez)
+    assert np.array_equal(Pf, P) and np.array_equal(If, I)
+
+
+def test_one_sided_profiles_of_a_sine():
+    """A sine of integer period p > ez repeats exactly p samples away: the
+    left profile vanishes from i = p on, the right one up to i = l - 1 - p."""
+    p, m, ez = 25, 20, 5
+    T = np.sin(2 * np.pi * np.arange(300) / p)
+    PL, IL = O.selfjoin_restricted(T, m, ez, side="left")
+    PR, IR = O.selfjoin_restricted(T, m, ez, side="right")
+    l = T.size - m + 1
+    assert np.all(PL[p:] < 1e-6) and np.all((np.arange(l) - IL)[p:] % p == 0)
+    assert np.all(PR[:l - p] < 1e-6) and np.all((IR - np.arange(l))[:l - p] % p == 0)

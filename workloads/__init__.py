@@ -58,7 +58,8 @@ def planted_walk(n: int, m: int, seed, n_motifs: int = 8, n_discords: int = 4,
     """Motif copies are planted in the increments of the walk, so that each
     planted window is an offset copy of s*p + e and the walk stays continuous
     around it (an overwrite would leave level jumps whose straddling windows
-    form spurious step-shaped motifs)."""
+    form spurious step-shaped motifs).  A discord burst overwrites its window
+    with N(0, 3^2) noise around the walk's level at the window start."""
     rng = np.random.default_rng(seed)
     steps = rng.standard_normal(n)
     pos = _spaced_positions(rng, n, m, 2 * n_motifs + n_discords, 2 * m)
@@ -74,7 +75,7 @@ def planted_walk(n: int, m: int, seed, n_motifs: int = 8, n_discords: int = 4,
     disc = []
     for k in range(n_discords):
         p = pos[2 * n_motifs + k]
-        T[p:p + m] += rng.normal(0.0, 3.0, m)
+        T[p:p + m] = T[p] + rng.normal(0.0, 3.0, m)
         disc.append(p)
     return Planted(T.astype(dtype), m, pairs, sorted(disc))
 
