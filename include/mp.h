@@ -141,6 +141,47 @@ mp_status mp_batch(const mp_batch_plan *plan, const void *T_cat, void *P_cat, in
                    void *ws, size_t ws_bytes, void *stream);
 void mp_batch_plan_destroy(mp_batch_plan *plan);
 
+/* ------------------------------------ partial and one-sided self-joins
+ * Sections 3.3.1 and 3.3.3 (STAMP, SCRIMP): the profile can be computed in a
+ * random order of its parts and read at any point as the best-so-far
+ * profile; the s_size argument of Section 3.2 stops such a run in a
+ * controlled way.  Here the parts are chunks of diagonal offsets: chunk c
+ * holds the pairs with |i - j| in [ez + 1 + c*W, ez + (c+1)*W] (W and the
+ * number of chunks from mp_selfjoin_chunks), and a plan restricted to a set
+ * of chunks returns exactly
+ *   P[i] = min over j with |i - j| in the set of d(i, j)
+ * (the best-so-far profile once those chunks are done; the full set gives
+ * the self-join, bitwise equal to mp_selfjoin with the same options).
+ * Time series chains (Section 3.4.3) and the arc counts of semantic
+ * segmentation (Section 3.4.2) work on the left and right profiles:
+ * P_left[i] = min over j < i - ez, P_right[i] = min over j > i + ez.  One
+ * sweep gives both (row minima look right, column minima look left).
+ *   sides   MP_SIDES_BOTH: the plan's profile has l entries;
+ *           MP_SIDES_LEFT_RIGHT: 3l entries [P | P_left | P_right] (I alike;
+ *           P is the better of the two, the left one on equal distances).
+ *   chunks  host, nchunks distinct chunk numbers in [0, count), any order;
+ *           NULL = every chunk.  nchunks = 0 with a non-NULL pointer is the
+ *           empty set (every P is +inf).
+ * The plan is a batch plan of one series: size its workspace with
+ * mp_batch_plan_workspace, upload it once with mp_batch_plan_upload and run
+ * it with mp_batch (T_cat = T, P_cat/I_cat of mp_batch_plan_profile_length
+ * entries).  mp_backward accepts MP_SIDES_BOTH plans (gradient of the
+ * restricted profile) and returns MP_EUNSUPPORTED for left/right plans.
+ * mp_selfjoin_chunks returns the number of chunks (0 if l <= ez + 1, -1 on
+ * invalid arguments) and stores W in *chunk_width when it is not NULL.
+ */
+#define MP_SIDES_BOTH 0
+#define MP_SIDES_LEFT_RIGHT 1
+int64_t mp_selfjoin_chunks(int64_t n, int32_t m, int32_t ez, const mp_options *opt,
+                           int64_t *chunk_width);
+mp_status mp_selfjoin_plan_create(int64_t n, int32_t m, int32_t ez, mp_dtype dtype,
+                                  const mp_options *opt, int32_t sides, int64_t nchunks,
+                                  const int64_t *chunks_host, mp_batch_plan **out);
+/* A uniformly random order of `count` chunk numbers (host array of count
+ * int64, written): Fisher-Yates shuffle driven by SplitMix64 seeded with
+ * `seed`.  An anytime run takes a prefix of it. */
+mp_status mp_anytime_order(int64_t count, uint64_t seed, int64_t *order_host);
+
 /* ---------------------------------------------------------------- backward
  * Gradient of a loss L(P) with respect to T through the z-normalised
  * distance of each row's argmin pair, holding I fixed (not in the paper; the

@@ -9,16 +9,20 @@ package computes it with hand-written HIP kernels behind a C ABI
     P, I = mpx.selfjoin(T, m, ez)                 # Section 3.2 self-join
     Pab, Iab, Pba, Iba = mpx.abjoin(A, B, m)      # Section 3.2 AB-join
     plan = mpx.BatchPlan(lengths, windows, zones) # many joins, one launch
-    P, I = mpx.MatrixProfileFn.apply(T, plan)     # differentiable profile
+    P, I = mpx.matrix_profile(T_batch, m, ez)     # differentiable profile
+    P, I, chunks = mpx.anytime_selfjoin(T, m, ez, fraction=0.05)  # Sections 3.3.1/3.3.3
+    P, I, PL, IL, PR, IR = mpx.left_right_profiles(T, m, ez)      # left/right profiles
 """
 
 from ._binding import (  # noqa: F401
-    EXPORTS, LIB_PATH, MPError, BatchPlan, abjoin, abjoin_cells, exclusion_zone, lib, make_options,
-    recheck, selfjoin, selfjoin_cells, timing_enable, timing_query,
+    EXPORTS, LIB_PATH, MPError, BatchPlan, SelfJoinPlan, abjoin, abjoin_cells, anytime_order,
+    anytime_selfjoin, exclusion_zone, left_right_profiles, lib, make_options, recheck, selfjoin,
+    selfjoin_cells, selfjoin_chunks, timing_enable, timing_query,
 )
 from .autograd import MatrixProfileFn, matrix_profile  # noqa: F401
 
 __all__ = [
     "selfjoin", "abjoin", "BatchPlan", "recheck", "MatrixProfileFn", "matrix_profile",
-    "exclusion_zone", "selfjoin_cells", "abjoin_cells", "MPError", "lib",
+    "exclusion_zone", "selfjoin_cells", "abjoin_cells", "MPError", "lib", "SelfJoinPlan",
+    "selfjoin_chunks", "anytime_order", "anytime_selfjoin", "left_right_profiles",
 ]

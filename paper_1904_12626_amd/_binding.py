@@ -11,6 +11,7 @@ import ctypes
 import math
 import os
 from fractions import Fraction
+from typing import Optional
 
 import torch
 
@@ -29,6 +30,7 @@ EXPORTS = (
     "mp_batch_plan_cells", "mp_batch_plan_upload", "mp_batch", "mp_batch_plan_destroy",
     "mp_backward", "mp_recheck_workspace", "mp_recheck", "mp_strerror", "mp_abi_version",
     "mp_selfjoin_cells", "mp_abjoin_cells", "mp_timing_enable", "mp_timing_query",
+    "mp_selfjoin_chunks", "mp_selfjoin_plan_create", "mp_anytime_order",
 )
 
 
@@ -77,6 +79,9 @@ def lib():
         "mp_abi_version": (ctypes.c_int, []),
         "mp_selfjoin_cells": (i64, [i64, i32, i32]),
         "mp_abjoin_cells": (i64, [i64, i64, i32]),
+        "mp_selfjoin_chunks": (i64, [i64, i32, i32, op, ctypes.POINTER(i64)]),
+        "mp_selfjoin_plan_create": (ctypes.c_int, [i64, i32, i32, i32, op, i32, i64, vp, ctypes.POINTER(vp)]),
+        "mp_anytime_order": (ctypes.c_int, [i64, ctypes.c_uint64, vp]),
         "mp_timing_enable": (ctypes.c_int, [ctypes.c_int]),
         "mp_timing_query": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                            ctypes.POINTER(ctypes.c_int64)]),
@@ -211,24 +216,28 @@ class BatchPlan:
             acc += n
         off[ns] = acc
         self.total_n = acc
+        self.t_off = [off[i] for i in range(ns + 1)]
         mm = (ctypes.c_int32 * ns)(*self.windows)
         ee = (ctypes.c_int32 * ns)(*self.zones)
         self._opt = make_options(precision, reseed_rows, tile_slots, fp64_finalize)
         h = ctypes.c_void_p()
         _check("mp_batch_plan_create", L.mp_batch_plan_create(ns, off, mm, ee, dt, ctypes.byref(self._opt),
                                                               ctypes.byref(h)))
-        self._h = h
-        self.t_off = [off[i] for i in range(ns + 1)]
-        self.profile_length = int(L.mp_batch_plan_profile_length(h))
-        self.cells = int(L.mp_batch_plan_cells(h))
-        self.ws_bytes = int(L.mp_batch_plan_workspace(h))
-        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
         self.p_off = []
         acc = 0
         for n, m in zip(self.lengths, self.windows):
             self.p_off.append(acc)
             acc += n - m + 1
         self.p_off.append(acc)
+        self._setup(h)
+
+    def _setup(self, h):
+        L = lib()
+        self._h = h
+        self.profile_length = int(L.mp_batch_plan_profile_length(h))
+        self.cells = int(L.mp_batch_plan_cells(h))
+        self.ws_bytes = int(L.mp_batch_plan_workspace(h))
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
         self.upload()
 
     def upload(self, stream=None):
@@ -266,6 +275,88 @@ class BatchPlan:
         if h is not None and h.value and _lib is not None:
             _lib.mp_batch_plan_destroy(h)
             self._h = None
+
+
+def selfjoin_chunks(n: int, m: int, ez: int, *, precision: str = "f32", tile_slots: int = 0):
+    """(number of chunks, chunk width W) of a self-join's diagonal offsets
+    ez+1 .. l-1 (mp_selfjoin_chunks)."""
+    opt = make_options(precision, 0, tile_slots)
+    w = ctypes.c_int64()
+    c = lib().mp_selfjoin_chunks(int(n), int(m), int(ez), ctypes.byref(opt), ctypes.byref(w))
+    if c < 0:
+        raise ValueError("invalid self-join arguments")
+    return int(c), int(w.value)
+
+
+def anytime_order(count: int, seed: int):
+    """Random order of `count` chunk numbers (mp_anytime_order), host list."""
+    arr = (ctypes.c_int64 * max(1, int(count)))()
+    _check("mp_anytime_order", lib().mp_anytime_order(int(count), ctypes.c_uint64(int(seed) & (2**64 - 1)),
+                                                      arr))
+    return [int(arr[i]) for i in range(int(count))]
+
+
+class SelfJoinPlan(BatchPlan):
+    """Self-join plan restricted to a set of diagonal chunks and/or giving the
+    left and right profiles (mp_selfjoin_plan_create).  `run(T)` returns
+    (P, I) of length l (sides="both") or 3l ([P | P_left | P_right],
+    sides="lr")."""
+
+    def __init__(self, n, m, ez, dtype=torch.float32, device="cuda", *, sides: str = "both", chunks=None,
+                 precision: str = "f32", reseed_rows: int = 0, tile_slots: int = 0, fp64_finalize: bool = True):
+        if sides not in ("both", "lr"):
+            raise ValueError("sides must be 'both' or 'lr'")
+        L = lib()
+        self.lengths, self.windows, self.zones = [int(n)], [int(m)], [int(ez)]
+        self.dtype = dtype
+        self.device = torch.device(device)
+        self.total_n = int(n)
+        self.t_off = [0, int(n)]
+        self.sides = sides
+        dt = MP_F64 if dtype == torch.float64 else MP_F32
+        self._opt = make_options(precision, reseed_rows, tile_slots, fp64_finalize)
+        if chunks is None:
+            arr, nch = None, 0
+        else:
+            chunks = [int(c) for c in chunks]
+            nch = len(chunks)
+            arr = (ctypes.c_int64 * max(1, nch))(*chunks)
+        h = ctypes.c_void_p()
+        _check("mp_selfjoin_plan_create",
+               L.mp_selfjoin_plan_create(int(n), int(m), int(ez), dt, ctypes.byref(self._opt),
+                                         1 if sides == "lr" else 0, nch, arr, ctypes.byref(h)))
+        l = int(n) - int(m) + 1
+        self.p_off = [0, l]
+        self._setup(h)
+
+
+def left_right_profiles(T: torch.Tensor, m: int, ez: Optional[int] = None, *,
+                        exclusion_zone_frac=Fraction(1, 2), chunks=None, stream=None, **opts):
+    """Profile and left/right profiles of one self-join sweep:
+    (P, I, P_left, I_left, P_right, I_right)."""
+    T = _series(T, "T")
+    if ez is None:
+        ez = exclusion_zone(m, exclusion_zone_frac)
+    plan = SelfJoinPlan(T.numel(), m, ez, dtype=T.dtype, device=T.device, sides="lr", chunks=chunks, **opts)
+    P, I = plan.run(T, stream=stream)
+    l = T.numel() - m + 1
+    return P[:l], I[:l], P[l:2 * l], I[l:2 * l], P[2 * l:], I[2 * l:]
+
+
+def anytime_selfjoin(T: torch.Tensor, m: int, ez: Optional[int] = None, *, fraction: float = 0.05,
+                     seed: int = 0, exclusion_zone_frac=Fraction(1, 2), stream=None, **opts):
+    """Best-so-far self-join after a random `fraction` of the diagonal chunks
+    (at least one when fraction > 0): returns (P, I, chunks used)."""
+    T = _series(T, "T")
+    if ez is None:
+        ez = exclusion_zone(m, exclusion_zone_frac)
+    count, _ = selfjoin_chunks(T.numel(), m, ez, precision=opts.get("precision", "f32"),
+                               tile_slots=opts.get("tile_slots", 0))
+    k = 0 if fraction <= 0 else min(count, max(1, int(math.ceil(fraction * count))))
+    chunks = anytime_order(count, seed)[:k]
+    plan = SelfJoinPlan(T.numel(), m, ez, dtype=T.dtype, device=T.device, chunks=chunks, **opts)
+    P, I = plan.run(T, stream=stream)
+    return P, I, chunks
 
 
 def recheck(T: torch.Tensor, m: int, P: torch.Tensor, I: torch.Tensor, k_motifs: int, k_discords: int,

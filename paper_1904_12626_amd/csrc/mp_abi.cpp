@@ -62,6 +62,10 @@ struct Job {
   int W = 512, R = 4096;
   Options opt;
   bool t_f64 = false;
+  bool lr = false;               // left/right job: outputs [P | P_left | P_right]
+  int64_t out_len = -1;          // profile entries written (default total_l)
+  std::vector<uint32_t> kmask;   // chunk set of a restricted self-join (empty: none)
+  int64_t kchunk = 0;            // offsets per chunk
 };
 
 void add_series(Job &j, int64_t t_off, int64_t n, int32_t m, int32_t ez, int partner, int out) {
@@ -72,10 +76,12 @@ void add_series(Job &j, int64_t t_off, int64_t n, int32_t m, int32_t ez, int par
   s.w_off = j.total_l;
   s.rc_off = j.total_rc;
   s.x_off = j.total_x;
+  s.p_off = s.w_off;
   s.m = m;
   s.ez = ez;
   s.partner = partner;
   s.out = out;
+  s.side = 0;
   j.total_l += s.l;
   j.total_rc += s.l + mpx::kRcPad;
   j.total_x += s.l + 1;
@@ -155,7 +161,7 @@ void finish_job(Job &j) {
 }
 
 struct Layout {
-  size_t mu, sig, keys, flags, nc, nv, rc, special, counters, segp, segs, rescan, sdesc, wdesc;
+  size_t mu, sig, keys, flags, nc, nv, rc, special, counters, segp, segs, rescan, sdesc, wdesc, kmask;
   size_t b_mu, b_isig, b_coef, b_nbr, b_count, b_fill, b_off, b_tmp, b_erec, b_wrec, b_chunk;
   size_t total;
 };
@@ -195,6 +201,7 @@ Layout layout_of(const Job &j, bool with_batch_tables) {
     L.b_chunk = take(8 * ((tl + 1023) / 1024 + 1));
     L.sdesc = take(sizeof(SeriesDesc) * j.series.size());
     L.wdesc = take(sizeof(SweepDesc) * j.sweeps.size());
+    L.kmask = take(4 * std::max<size_t>(1, j.kmask.size()));
   }
   L.total = o;
   return L;
@@ -242,6 +249,10 @@ mpx::Plan plan_of(const Job &j, const Layout &L, void *ws, bool external) {
   if (external) {
     p.s_ext = (const SeriesDesc *)((char *)ws + L.sdesc);
     p.w_ext = (const SweepDesc *)((char *)ws + L.wdesc);
+    if (!j.kmask.empty()) {
+      p.kmask = (const uint32_t *)((char *)ws + L.kmask);
+      p.kchunk = j.kchunk;
+    }
   } else {
     for (size_t i = 0; i < j.series.size() && i < 2; ++i) p.s_inl[i] = j.series[i];
     for (size_t i = 0; i < j.sweeps.size() && i < 2; ++i) p.w_inl[i] = j.sweeps[i];
@@ -302,6 +313,7 @@ mp_status run_job(const Job &j, const mpx::Plan &plan, const mpx::Work &w, const
     return MP_ELAUNCH;
   if (mpx::launch_rescan(plan, w, T, j.t_f64, o, out_f64, op.fp64_finalize, st) != hipSuccess)
     return MP_ELAUNCH;
+  if (j.lr && mpx::launch_lr_combine(o, out_f64, j.series[0].l, st) != hipSuccess) return MP_ELAUNCH;
   if (g_timing.on) {
     if (ev[3]) (void)hipEventRecord(ev[3], st);
     for (auto &e : ev) g_timing.rec.push_back(e);
@@ -334,6 +346,7 @@ mp_status build_abjoin(int64_t nA, int64_t nB, int64_t b_off, int32_t m, mp_dtyp
   j.t_f64 = dt == MP_F64;
   add_series(j, 0, nA, m, -1, 1, 0);
   add_series(j, b_off, nB, m, -1, 0, 1);
+  j.series[1].p_off = 0;  // second output array
   const int64_t lA = nA - m + 1, lB = nB - m + 1;
   add_sweep(j, 0, 1, 0, 1, 0, lB - 1);  // rows A, columns B, j >= i
   add_sweep(j, 1, 0, 1, 0, 1, lA - 1);  // rows B, columns A, i > j
@@ -346,8 +359,72 @@ mp_status build_abjoin(int64_t nA, int64_t nB, int64_t b_off, int32_t m, mp_dtyp
 struct mp_batch_plan {
   Job job;
   Layout lay;
-  std::vector<int64_t> p_off;
 };
+
+namespace {
+
+// Chunks of diagonal offsets of a self-join: offsets ez + 1 .. l - 1 in
+// runs of one strip width.
+int64_t chunk_count(int64_t l, int32_t ez, int W) {
+  const int64_t span = l - 1 - (int64_t)ez;
+  return span > 0 ? (span + W - 1) / W : 0;
+}
+
+mp_status build_selfjoin_plan(int64_t n, int32_t m, int32_t ez, mp_dtype dt, const mp_options *opt,
+                              int32_t sides, int64_t nchunks, const int64_t *chunks, Job &j) {
+  if (dt != MP_F64 && dt != MP_F32) return MP_EINVAL;
+  if (m < 2 || n < m || ez < 0) return MP_EINVAL;
+  if (n - m + 1 >= ((int64_t)1 << 31)) return MP_EINVAL;
+  if (sides != MP_SIDES_BOTH && sides != MP_SIDES_LEFT_RIGHT) return MP_EINVAL;
+  if (nchunks < 0 || (nchunks > 0 && !chunks)) return MP_EINVAL;
+  mp_status s = parse_options(opt, j.opt);
+  if (s != MP_OK) return s;
+  j.t_f64 = dt == MP_F64;
+  const int64_t l = n - m + 1;
+  const int W = 64 * j.opt.slots;
+  const int64_t nch = chunk_count(l, ez, W);
+  std::vector<int64_t> list;
+  if (chunks) {
+    j.kmask.assign((size_t)std::max<int64_t>(1, (nch + 31) / 32), 0u);
+    j.kchunk = W;
+    for (int64_t q = 0; q < nchunks; ++q) {
+      const int64_t c = chunks[q];
+      if (c < 0 || c >= nch) return MP_EINVAL;
+      uint32_t &word = j.kmask[(size_t)(c >> 5)];
+      if (word & (1u << (c & 31))) return MP_EINVAL;  // repeated chunk
+      word |= 1u << (c & 31);
+      list.push_back(c);
+    }
+  }
+  int rows = 0;
+  if (sides == MP_SIDES_BOTH) {
+    add_series(j, 0, n, m, ez, 0, 0);
+  } else {
+    // series 0 collects the left profile (column minima), series 1 the right
+    // profile (row minima); both read the same samples
+    add_series(j, 0, n, m, ez, 0, 0);
+    add_series(j, 0, n, m, ez, 1, 0);
+    j.series[0].side = mpx::kSideLeft;
+    j.series[0].p_off = l;
+    j.series[1].side = mpx::kSideRight;
+    j.series[1].p_off = 2 * l;
+    j.lr = true;
+    j.out_len = 3 * l;
+    rows = 1;
+  }
+  const int cols_key = 0;
+  if (!chunks) {
+    add_sweep(j, rows, rows, rows, cols_key, (int64_t)ez + 1, l - 1);
+  } else {
+    for (int64_t c : list)
+      add_sweep(j, rows, rows, rows, cols_key, (int64_t)ez + 1 + c * W,
+                std::min<int64_t>((int64_t)ez + (c + 1) * W, l - 1));
+  }
+  finish_job(j);
+  return MP_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -467,14 +544,59 @@ mp_status mp_batch_plan_create(int32_t nseries, const int64_t *t_off, const int3
     add_sweep(j, i, i, i, i, (int64_t)ez[i] + 1, j.series[i].l - 1);
   finish_job(j);
   pl->lay = layout_of(j, true);
-  pl->p_off.resize(nseries + 1);
-  for (int32_t i = 0; i <= nseries; ++i) pl->p_off[i] = i < nseries ? j.series[i].w_off : j.total_l;
   *out = pl;
   return MP_OK;
 }
 
+int64_t mp_selfjoin_chunks(int64_t n, int32_t m, int32_t ez, const mp_options *opt,
+                           int64_t *chunk_width) {
+  Options o;
+  if (m < 2 || n < m || ez < 0 || parse_options(opt, o) != MP_OK) return -1;
+  const int W = 64 * o.slots;
+  if (chunk_width) *chunk_width = W;
+  return chunk_count(n - m + 1, ez, W);
+}
+
+mp_status mp_selfjoin_plan_create(int64_t n, int32_t m, int32_t ez, mp_dtype dtype,
+                                  const mp_options *opt, int32_t sides, int64_t nchunks,
+                                  const int64_t *chunks, mp_batch_plan **out) {
+  if (!out) return MP_EINVAL;
+  *out = nullptr;
+  mp_batch_plan *pl = new (std::nothrow) mp_batch_plan();
+  if (!pl) return MP_EINVAL;
+  const mp_status s = build_selfjoin_plan(n, m, ez, dtype, opt, sides, nchunks, chunks, pl->job);
+  if (s != MP_OK) {
+    delete pl;
+    return s;
+  }
+  pl->lay = layout_of(pl->job, true);
+  *out = pl;
+  return MP_OK;
+}
+
+mp_status mp_anytime_order(int64_t count, uint64_t seed, int64_t *order) {
+  if (count < 0 || (count > 0 && !order)) return MP_EINVAL;
+  // Fisher-Yates driven by SplitMix64 (Steele, Lea, Flood 2014)
+  uint64_t x = seed;
+  auto next = [&x]() {
+    uint64_t z = (x += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  };
+  for (int64_t i = 0; i < count; ++i) order[i] = i;
+  for (int64_t i = count - 1; i > 0; --i) {
+    const int64_t r = (int64_t)(next() % (uint64_t)(i + 1));
+    std::swap(order[i], order[r]);
+  }
+  return MP_OK;
+}
+
 size_t mp_batch_plan_workspace(const mp_batch_plan *pl) { return pl ? pl->lay.total : 0; }
-int64_t mp_batch_plan_profile_length(const mp_batch_plan *pl) { return pl ? pl->job.total_l : 0; }
+int64_t mp_batch_plan_profile_length(const mp_batch_plan *pl) {
+  if (!pl) return 0;
+  return pl->job.out_len >= 0 ? pl->job.out_len : pl->job.total_l;
+}
 int64_t mp_batch_plan_cells(const mp_batch_plan *pl) { return pl ? pl->job.cells : 0; }
 
 mp_status mp_batch_plan_upload(const mp_batch_plan *pl, void *ws, size_t ws_bytes, void *stream) {
@@ -488,6 +610,10 @@ mp_status mp_batch_plan_upload(const mp_batch_plan *pl, void *ws, size_t ws_byte
     return MP_ELAUNCH;
   if (hipMemcpyAsync(b + pl->lay.wdesc, pl->job.sweeps.data(),
                      sizeof(SweepDesc) * pl->job.sweeps.size(), hipMemcpyHostToDevice, st) != hipSuccess)
+    return MP_ELAUNCH;
+  if (!pl->job.kmask.empty() &&
+      hipMemcpyAsync(b + pl->lay.kmask, pl->job.kmask.data(), 4 * pl->job.kmask.size(),
+                     hipMemcpyHostToDevice, st) != hipSuccess)
     return MP_ELAUNCH;
   return MP_OK;
 }
@@ -543,6 +669,7 @@ mp_status mp_timing_query(double *sweep_ms, double *total_ms, int64_t *calls) {
 mp_status mp_backward(const mp_batch_plan *pl, const void *T_cat, const int64_t *I_cat,
                       const void *gP_cat, void *gT_cat, void *ws, size_t ws_bytes, void *stream) {
   if (!pl || !T_cat || !I_cat || !gP_cat || !gT_cat) return MP_EINVAL;
+  if (pl->job.lr) return MP_EUNSUPPORTED;
   const size_t es = pl->job.t_f64 ? 8 : 4;
   if (!aligned(T_cat, es) || !aligned(gP_cat, es) || !aligned(gT_cat, es) || !aligned(I_cat, 8))
     return MP_EINVAL;

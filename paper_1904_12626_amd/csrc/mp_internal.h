@@ -26,11 +26,16 @@ struct SeriesDesc {
   int64_t w_off;   // first window in mu/sig/flags/keys/P/I and rescan ids
   int64_t rc_off;  // first entry in the padded row/column data array
   int64_t x_off;   // first entry in next_const/next_valid (l + 1 entries)
+  int64_t p_off;   // output position of window 0 within its output slot
   int32_t m;
   int32_t ez;       // >= 0: self-join zone; -1: AB side (no zone)
   int32_t partner;  // series whose windows are this series' candidates
   int32_t out;      // output slot: 0 (single array) or the AB side (0/1)
+  int32_t side;     // self-join candidates: 0 both sides, kSideRight j > i, kSideLeft j < i
+  int32_t pad_;
 };
+constexpr int32_t kSideRight = 1;
+constexpr int32_t kSideLeft = 2;
 
 // One diagonal sweep: rows from series rs, columns from series cs,
 // diagonals k = j - i in [k_lo, k_hi].  Row minima go to the keys of
@@ -52,6 +57,12 @@ struct Plan {
   SweepDesc w_inl[2];
   const SeriesDesc *s_ext;
   const SweepDesc *w_ext;
+  // Optional restriction of self-join candidates to a set of diagonal
+  // chunks: chunk c holds the offsets |j - i| in
+  // [ez + 1 + c * kchunk, ez + (c + 1) * kchunk]; bit c of kmask set = chunk
+  // in the set.  Null = every admissible offset.
+  const uint32_t *kmask;
+  int64_t kchunk;
 
   __device__ __forceinline__ SeriesDesc series(int i) const { return s_ext ? s_ext[i] : s_inl[i]; }
   __device__ __forceinline__ SweepDesc sweep(int i) const { return w_ext ? w_ext[i] : w_inl[i]; }
@@ -122,6 +133,7 @@ hipError_t launch_finalize(const Plan &plan, const Work &w, const void *T, bool 
                            hipStream_t st);
 hipError_t launch_rescan(const Plan &plan, const Work &w, const void *T, bool t_f64,
                          const Outputs &o, bool out_f64, bool fp64_finalize, hipStream_t st);
+hipError_t launch_lr_combine(const Outputs &o, bool out_f64, int64_t l, hipStream_t st);
 hipError_t launch_recheck(const void *T, bool t_f64, int64_t n, int32_t m, const void *P,
                           bool p_f64, const int64_t *I, int32_t km, int32_t kd, int64_t *out_idx,
                           double *out_dist, uint8_t *ws, hipStream_t st);

@@ -47,34 +47,77 @@ __device__ double pair_dist64(const Tin *TA, double muA, double sgA, bool cA, co
   return sqrt(s);
 }
 
-// Smallest window index of a partner series that is admissible for window w
-// (|w - j| > ez for a self-join, anything for an AB side) and has the
-// property tabulated in `next` (next[x] = smallest index >= x with it, or l).
-__device__ __forceinline__ int64_t first_admissible(const int32_t *next, int64_t l, int64_t w,
-                                                    int ez) {
-  const int64_t f = next[0];
-  if (f >= l) return -1;
-  if (ez < 0) return f;
-  if (f < w - ez) return f;
-  const int64_t x = w + ez + 1;
-  if (x >= l) return -1;
-  const int64_t g = next[x];
-  return g < l ? g : -1;
+// Is window j of the partner series a candidate of window w of series S?
+// AB sides: always.  Self-joins: |j - w| > ez, on S's side(s), and with the
+// offset |j - w| in the plan's chunk set when there is one.
+__device__ __forceinline__ bool candidate(const Plan &plan, const SeriesDesc &S, int64_t w,
+                                          int64_t j) {
+  if (S.ez < 0) return true;
+  const int64_t k = j - w;
+  const int64_t a = k < 0 ? -k : k;
+  if (a <= S.ez) return false;
+  if (S.side == kSideRight && k < 0) return false;
+  if (S.side == kSideLeft && k > 0) return false;
+  if (plan.kmask) {
+    const int64_t c = (a - S.ez - 1) / plan.kchunk;
+    if (!((plan.kmask[c >> 5] >> (c & 31)) & 1u)) return false;
+  }
+  return true;
 }
 
-// Same, when every partner window is valid.
-__device__ __forceinline__ int64_t first_admissible_all(int64_t l, int64_t w, int ez) {
-  if (l <= 0) return -1;
-  if (ez < 0 || 0 < w - ez) return 0;
-  const int64_t x = w + ez + 1;
-  return x < l ? x : -1;
+// Smallest candidate j of window w (see `candidate`) in a partner series of
+// l windows that is a member of the set tabulated by `next` (next[x] =
+// smallest member >= x, l if none; null: every window is a member), or -1.
+// The candidates form at most a few intervals of j (one per side, or one per
+// chunk of offsets); each interval costs one table lookup.
+__device__ int64_t first_candidate(const Plan &plan, const SeriesDesc &S, const int32_t *next,
+                                   int64_t l, int64_t w) {
+  auto first_in = [&](int64_t lo, int64_t hi) -> int64_t {
+    lo = lo < 0 ? 0 : lo;
+    hi = hi > l - 1 ? l - 1 : hi;
+    if (lo > hi) return -1;
+    const int64_t g = next ? (int64_t)next[lo] : lo;
+    return g <= hi ? g : -1;
+  };
+  if (S.ez < 0) return first_in(0, l - 1);
+  const int64_t ez = S.ez;
+  if (!plan.kmask) {
+    if (S.side != kSideRight) {
+      const int64_t g = first_in(0, w - ez - 1);
+      if (g >= 0) return g;
+    }
+    return S.side != kSideLeft ? first_in(w + ez + 1, l - 1) : -1;
+  }
+  const int64_t C = plan.kchunk;
+  const int64_t span = l - 1 - ez;  // offsets ez + 1 .. l - 1
+  if (span <= 0) return -1;
+  const int64_t nch = (span + C - 1) / C;
+  auto in_set = [&](int64_t c) { return ((plan.kmask[c >> 5] >> (c & 31)) & 1u) != 0; };
+  if (S.side != kSideRight && w - ez - 1 >= 0) {
+    // left of w: increasing j is decreasing offset
+    for (int64_t c = min(nch - 1, (w - ez - 1) / C); c >= 0; --c) {
+      if (!in_set(c)) continue;
+      const int64_t g = first_in(w - (ez + (c + 1) * C), w - (ez + 1 + c * C));
+      if (g >= 0) return g;
+    }
+  }
+  if (S.side != kSideLeft) {
+    for (int64_t c = 0; c < nch; ++c) {
+      const int64_t lo = w + ez + 1 + c * C;
+      if (lo > l - 1) break;
+      if (!in_set(c)) continue;
+      const int64_t g = first_in(lo, w + ez + (c + 1) * C);
+      if (g >= 0) return g;
+    }
+  }
+  return -1;
 }
 
 template <typename Tout>
 __device__ __forceinline__ void store_out(const Outputs &o, const SeriesDesc &S, int64_t w,
                                           double P, int64_t I) {
   const int slot = S.out;
-  const int64_t pos = (slot == 0 && o.P[1] == nullptr) ? (S.w_off + w) : w;
+  const int64_t pos = S.p_off + w;
   reinterpret_cast<Tout *>(o.P[slot])[pos] = (Tout)P;
   o.I[slot][pos] = I;
 }
@@ -120,13 +163,12 @@ __global__ void __launch_bounds__(256) k_finalize(Plan plan, Work wk, const Tin 
   const int32_t *nc = wk.next_const + Q.x_off;
   const int32_t *nv = wk.next_valid + Q.x_off;
   if (fw & 2) {  // constant window
-    const int64_t jc = (sp & 2) ? first_admissible(nc, Q.l, w, S.ez) : -1;
+    const int64_t jc = (sp & 2) ? first_candidate(plan, S, nc, Q.l, w) : -1;
     if (jc >= 0) {
       val = 0.0;
       idx = jc;
     } else {
-      const int64_t jv = (sp & 1) ? first_admissible(nv, Q.l, w, S.ez)
-                                  : first_admissible_all(Q.l, w, S.ez);
+      const int64_t jv = first_candidate(plan, S, (sp & 1) ? nv : nullptr, Q.l, w);
       val = jv >= 0 ? 0.5 : INFINITY;
       idx = jv;
     }
@@ -134,7 +176,7 @@ __global__ void __launch_bounds__(256) k_finalize(Plan plan, Work wk, const Tin 
     return;
   }
   if (sp & 2) {
-    const int64_t jc = first_admissible(nc, Q.l, w, S.ez);
+    const int64_t jc = first_candidate(plan, S, nc, Q.l, w);
     if (jc >= 0 && (0.5 < val || (0.5 == val && jc < idx))) {
       val = 0.5;
       idx = jc;
@@ -178,7 +220,7 @@ __global__ void __launch_bounds__(256) k_rescan(Plan plan, Work wk, const Tin *_
     double best = INFINITY;
     int64_t arg = -1;
     for (int64_t j = threadIdx.x; j < Q.l; j += blockDim.x) {
-      if (S.ez >= 0 && llabs(j - w) <= S.ez) continue;
+      if (!candidate(plan, S, w, j)) continue;
       const uint8_t fj = wk.flags[Q.w_off + j];
       if (!(fj & 1)) continue;
       double key;
@@ -248,6 +290,30 @@ hipError_t launch_rescan(const Plan &plan, const Work &w, const void *T, bool t_
     if (out_f64) hipLaunchKernelGGL((k_rescan<float, double>), grd, blk, 0, st, plan, w, (const float *)T, o, f);
     else hipLaunchKernelGGL((k_rescan<float, float>), grd, blk, 0, st, plan, w, (const float *)T, o, f);
   }
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------- left/right merge
+// Profile of a left/right job: out[0, l) = the better of the left profile
+// (out[l, 2l)) and the right profile (out[2l, 3l)); on equal distances the
+// left neighbour (the smaller index) wins.
+template <typename Tout>
+__global__ void __launch_bounds__(256) k_lr_combine(Outputs o, int64_t l) {
+  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= l) return;
+  Tout *P = reinterpret_cast<Tout *>(o.P[0]);
+  int64_t *I = o.I[0];
+  const Tout pl = P[l + w], pr = P[2 * l + w];
+  const int64_t il = I[l + w], ir = I[2 * l + w];
+  const bool right = il < 0 || (ir >= 0 && pr < pl);
+  P[w] = right ? pr : pl;
+  I[w] = right ? ir : il;
+}
+
+hipError_t launch_lr_combine(const Outputs &o, bool out_f64, int64_t l, hipStream_t st) {
+  const dim3 blk(256), grd((unsigned)((l + 255) / 256));
+  if (out_f64) hipLaunchKernelGGL((k_lr_combine<double>), grd, blk, 0, st, o, l);
+  else hipLaunchKernelGGL((k_lr_combine<float>), grd, blk, 0, st, o, l);
   return hipGetLastError();
 }
 

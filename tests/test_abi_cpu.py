@@ -118,3 +118,51 @@ def test_exclusion_zone_rule():
     assert B.exclusion_zone(80, Fraction(1, 2)) == 40
     assert B.exclusion_zone(50, Fraction(1, 4)) == 13
     assert B.exclusion_zone(64, 0.25) == 16
+
+
+def test_selfjoin_chunks_and_restricted_plans():
+    lib = B.lib()
+    opt = B.make_options("f32", tile_slots=8)
+    w = ctypes.c_int64()
+    # l = 4033, offsets 17 .. 4032 -> 4016 offsets in chunks of 512
+    assert lib.mp_selfjoin_chunks(4096, 64, 16, ctypes.byref(opt), ctypes.byref(w)) == 8
+    assert w.value == 512
+    assert lib.mp_selfjoin_chunks(100, 64, 40, None, None) == 0      # l = 37 <= ez + 1
+    assert lib.mp_selfjoin_chunks(10, 64, 4, None, None) == -1
+    h = ctypes.c_void_p()
+    ch = (ctypes.c_int64 * 3)(5, 0, 7)
+    assert lib.mp_selfjoin_plan_create(4096, 64, 16, B.MP_F32, ctypes.byref(opt), 0, 3, ch, ctypes.byref(h)) == 0
+    assert lib.mp_batch_plan_profile_length(h) == 4033
+    lib.mp_batch_plan_destroy(h)
+    assert lib.mp_selfjoin_plan_create(4096, 64, 16, B.MP_F32, ctypes.byref(opt), 1, 0, None, ctypes.byref(h)) == 0
+    assert lib.mp_batch_plan_profile_length(h) == 3 * 4033
+    assert lib.mp_batch_plan_cells(h) == B.selfjoin_cells(4096, 64, 16)
+    lib.mp_batch_plan_destroy(h)
+    for bad in ((8,), (2, 2), (-1,)):
+        arr = (ctypes.c_int64 * len(bad))(*bad)
+        assert lib.mp_selfjoin_plan_create(4096, 64, 16, B.MP_F32, ctypes.byref(opt), 0, len(bad), arr,
+                                           ctypes.byref(h)) == B.MP_EINVAL
+    assert lib.mp_selfjoin_plan_create(4096, 64, 16, B.MP_F32, None, 2, 0, None, ctypes.byref(h)) == B.MP_EINVAL
+
+
+def test_restricted_plan_cells_are_the_chunk_cells():
+    """Cells of a chunk plan = admissible pairs whose offset is in the chunks."""
+    lib = B.lib()
+    opt = B.make_options("f32", tile_slots=8)
+    n, m, ez, W = 4096, 64, 16, 512
+    l = n - m + 1
+    chunks = [1, 6, 3]
+    arr = (ctypes.c_int64 * 3)(*chunks)
+    h = ctypes.c_void_p()
+    assert lib.mp_selfjoin_plan_create(n, m, ez, B.MP_F32, ctypes.byref(opt), 0, 3, arr, ctypes.byref(h)) == 0
+    want = sum(l - k for c in chunks for k in range(ez + 1 + c * W, min(ez + (c + 1) * W, l - 1) + 1))
+    assert lib.mp_batch_plan_cells(h) == want
+    lib.mp_batch_plan_destroy(h)
+
+
+def test_anytime_order_is_a_seeded_permutation():
+    a = B.anytime_order(1000, 7)
+    assert sorted(a) == list(range(1000))
+    assert a == B.anytime_order(1000, 7)
+    assert a != B.anytime_order(1000, 8)
+    assert B.anytime_order(0, 1) == []

@@ -79,6 +79,17 @@ def test_selfjoin_large_planted_walk():
         assert abs(dist[q] - O.pair_distance(T64, int(i), T64, int(j), m)) < 1e-9
     # noisy planted pairs: d ~ sqrt(m * 0.05^2 * (s_a^-2 + s_b^-2)) in [0.57, 2.26]
     assert np.all(dist[:8] > 0.3) and np.all(dist[:8] < 3.0)
+    # discords: the white-noise bursts have no match anywhere, and neither
+    # do windows that straddle a planted motif copy (its pattern is white
+    # noise too, matched only at its own twin); each of the top-4 discords
+    # lands within m of a planted window, and every burst is among the top 8
+    planted = list(pw.discords) + [x for pr in pw.motif_pairs for x in pr]
+    for q, p in enumerate(idx[16:20]):
+        assert min(abs(int(p) - b) for b in planted) <= m, (p, planted)
+        assert abs(dist[8 + q] - O.pair_distance(T64, int(p), T64, int(I32[p]), m)) < 1e-9
+    top8 = O.top_discords(P32, m, 8)
+    for b in pw.discords:
+        assert min(abs(int(p) - b) for p in top8) <= m, (b, top8)
 
 
 def test_abjoin_ecg_full():
@@ -112,7 +123,7 @@ def test_abjoin_ecg_full():
 
 def test_batch_ragged_full():
     """512 float32 random walks, lengths U{2048..65536}, m in {32,64,128},
-    ez = m/4, one launch sequence; graph replay equals the eager run."""
+    ez = m/4, one launch sequence; five graph replays equal the eager run."""
     import paper_1904_12626_amd as mpx
     rb = W.batch_ragged()
     Tc, _ = rb.concat()
@@ -164,7 +175,7 @@ def test_batch_ragged_full():
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g):
         plan.run(Tg, Pg, Ig)
-    for rep in range(2):
+    for rep in range(5):
         Pg.zero_()
         torch.cuda.synchronize()
         g.replay()
