@@ -60,6 +60,10 @@ __all__ = [
     "abjoin",
     "abjoin_rows",
     "top_motifs",
+    "arc_curve",
+    "corrected_arc_curve",
+    "fluss_segments",
+    "chains",
     "top_discords",
     "reference_gradient",
     "profile_sum_loss",
@@ -345,6 +349,96 @@ def top_discords(P, m: int, k: int):
         out.append(i)
         P[max(0, i - m):i + m + 1] = np.nan
     return out
+
+
+# --------------------------------------------------------------------------
+# Data-mining passes over a profile index: semantic segmentation
+# (Section 3.4.2, FLUSS after Gharghabi et al. 2017) and time series chains
+# (Section 3.4.3, after Zhu et al. 2018)
+# --------------------------------------------------------------------------
+
+def arc_curve(I):
+    """AC[x] = number of windows i whose arc to I[i] spans x, i.e.
+    min(i, I[i]) <= x < max(i, I[i]).  Entries < 0, >= l or equal to i draw
+    no arc.  (+1 at the arc's start, -1 at its end, then a running sum.)"""
+    I = np.asarray(I, dtype=np.int64)
+    l = I.size
+    marks = np.zeros(l + 1, dtype=np.int64)
+    for i in range(l):
+        j = int(I[i])
+        if j < 0 or j >= l or j == i:
+            continue
+        marks[min(i, j)] += 1
+        marks[max(i, j)] -= 1
+    return np.cumsum(marks[:l])
+
+
+def corrected_arc_curve(I, zone: int):
+    """CAC[x] = min(AC[x] / IAC[x], 1) with IAC[x] = 2x(l - x)/l, the
+    expected arc count when every arc ends at a uniformly random position;
+    1 within `zone` of either end."""
+    ac = arc_curve(I).astype(np.float64)
+    l = ac.size
+    cac = np.ones(l)
+    for x in range(zone, l - zone):
+        ideal = 2.0 * x * (l - x) / l
+        if ideal > 0:
+            cac[x] = min(ac[x] / ideal, 1.0)
+    return cac
+
+
+def fluss_segments(cac, k: int, zone: int):
+    """k boundaries: repeatedly the smallest CAC (first index on ties)
+    outside the edge zones and farther than `zone` from earlier picks; -1
+    once nothing is left."""
+    cac = np.asarray(cac, dtype=np.float64)
+    l = cac.size
+    picks = []
+    for _ in range(k):
+        best, arg = np.inf, -1
+        for x in range(zone, l - zone):
+            if any(abs(x - c) <= zone for c in picks if c >= 0):
+                continue
+            if cac[x] < best:
+                best, arg = cac[x], x
+        picks.append(arg)
+    return picks
+
+
+def chains(IL, IR, min_len: int = 3):
+    """Chains from the left and right profile indices.  The link i -> IR[i]
+    holds when IL[IR[i]] == i; the links form disjoint increasing paths.
+    Returns (next, length, count, best): the confirmed successor of every
+    window (-1 if none), the number of windows from i to its chain's end,
+    the number of chains (counted at their first window) with at least
+    min_len windows, and the longest chain (the earliest on equal lengths)."""
+    IL = np.asarray(IL, dtype=np.int64)
+    IR = np.asarray(IR, dtype=np.int64)
+    l = IL.size
+    nxt = np.full(l, -1, dtype=np.int64)
+    for i in range(l):
+        j = int(IR[i])
+        if i < j < l and IL[j] == i:
+            nxt[i] = j
+    length = np.ones(l, dtype=np.int64)
+    for i in range(l - 1, -1, -1):
+        if nxt[i] >= 0:
+            length[i] = 1 + length[nxt[i]]
+    count, best_head, best_len = 0, -1, 0
+    for i in range(l):
+        p = int(IL[i])
+        if 0 <= p < i and nxt[p] == i:
+            continue                       # not the first window of its chain
+        if length[i] >= min_len:
+            count += 1
+        if length[i] > best_len:
+            best_head, best_len = i, int(length[i])
+    best = []
+    v = best_head
+    while v >= 0 and len(best) < best_len:
+        best.append(v)
+        v = int(nxt[v])
+    return nxt, length, count, best
 
 
 # --------------------------------------------------------------------------

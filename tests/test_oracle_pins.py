@@ -442,3 +442,79 @@ def test_one_sided_profiles_of_a_sine():
     l = T.size - m + 1
     assert np.all(PL[p:] < 1e-6) and np.all((np.arange(l) - IL)[p:] % p == 0)
     assert np.all(PR[:l - p] < 1e-6) and np.all((IR - np.arange(l))[:l - p] % p == 0)
+
+
+# ------------------------------------------- segmentation and chains
+
+def test_arc_curve_counts_spanning_arcs():
+    rng = np.random.default_rng(70)
+    l = 60
+    I = rng.integers(-3, l + 3, l)
+    I[5] = 5                                      # self arc: none
+    ac = O.arc_curve(I)
+    for x in range(l):
+        want = sum(1 for i in range(l) if 0 <= I[i] < l and I[i] != i and min(i, I[i]) <= x < max(i, I[i]))
+        assert ac[x] == want
+
+
+def test_random_arcs_follow_the_ideal_arc_curve():
+    """For arcs to uniformly random other windows, the expected count at x
+    under 'min <= x < max' is 2(x+1)(l-1-x)/(l-1) (which the corrected
+    curve's 2x(l-x)/l approximates); the mean of many draws agrees within
+    its standard error."""
+    rng = np.random.default_rng(71)
+    l, draws = 120, 3000
+    acc = np.zeros(l)
+    acc2 = np.zeros(l)
+    for _ in range(draws):
+        j = rng.integers(0, l - 1, l)
+        j = j + (j >= np.arange(l))              # uniform over the others
+        a = O.arc_curve(j)
+        acc += a
+        acc2 += a * a
+    mean = acc / draws
+    se = np.sqrt(np.maximum(acc2 / draws - mean ** 2, 1e-12) / draws)
+    x = np.arange(l)
+    want = 2.0 * (x + 1) * (l - 1 - x) / (l - 1)
+    assert np.all(np.abs(mean - want) <= 5 * se + 1e-9)
+
+
+def test_fluss_finds_regime_changes():
+    import workloads as W
+    T, (b1, b2) = W.regime_series(6000, 7)
+    m = 60
+    P, I = cimpl.selfjoin(T, m, m // 2)
+    cac = O.corrected_arc_curve(I, 5 * m)
+    assert np.all(cac[:5 * m] == 1) and np.all(cac[-5 * m:] == 1) and np.all((cac >= 0) & (cac <= 1))
+    seg = sorted(O.fluss_segments(cac, 2, 5 * m))
+    assert abs(seg[0] - b1) <= m and abs(seg[1] - b2) <= m
+
+
+def test_chains_by_hand():
+    # windows 0..9; confirmed links 1->4->7 and 2->5; 3->6 is not confirmed
+    # (IL[6] = 0); 8 -> 9 confirmed
+    IL = np.array([-1, -1, -1, -1, 1, 2, 0, 4, -1, 8])
+    IR = np.array([3, 4, 5, 6, 7, -1, 9, -1, 9, -1])
+    nxt, length, count, best = O.chains(IL, IR, min_len=2)
+    assert list(nxt) == [-1, 4, 5, -1, 7, -1, -1, -1, 9, -1]
+    assert list(length) == [1, 3, 2, 1, 2, 1, 1, 1, 2, 1]
+    assert count == 3 and best == [1, 4, 7]
+    assert O.chains(IL, IR, min_len=3)[2] == 1
+
+
+def test_chains_partition_the_windows_and_follow_an_evolving_pattern():
+    import workloads as W
+    T, pos = W.evolving_chain(8000, 64, 8, 2)
+    m, ez = 64, 16
+    rows = np.arange(T.size - m + 1)
+    _, IL = cimpl.selfjoin_rows_restricted(T, m, ez, rows, None, "left")
+    _, IR = cimpl.selfjoin_rows_restricted(T, m, ez, rows, None, "right")
+    nxt, length, count, best = O.chains(IL, IR)
+    # every window lies on exactly one chain: chain lengths at the first
+    # windows add up to l, and no window has two confirmed predecessors
+    heads = [i for i in rows if not (0 <= IL[i] < i and nxt[IL[i]] == i)]
+    assert sum(int(length[h]) for h in heads) == rows.size
+    succ = nxt[nxt >= 0]
+    assert np.unique(succ).size == succ.size
+    for p in pos:
+        assert any(abs(b - p) <= m // 8 for b in best), (p, best)

@@ -130,6 +130,50 @@ def walk_batch(nseries: int, n: int, seed, dtype=np.float32) -> np.ndarray:
     return np.cumsum(rng.standard_normal((nseries, n)), axis=1).astype(dtype)
 
 
+def regime_series(n: int, seed, dtype=np.float64):
+    """Three regimes of about n/3 samples each: a sine of period 40, a
+    sawtooth of period 55 and a two-level pulse of period 70, every cycle
+    with its own amplitude U(0.8, 1.2) and N(0, 0.05^2) noise.  Returns the
+    series and the two regime boundaries (semantic-segmentation input)."""
+    rng = np.random.default_rng(seed)
+    b1, b2 = n // 3 + int(rng.integers(-n // 20, n // 20)), 2 * n // 3 + int(rng.integers(-n // 20, n // 20))
+    out = np.empty(n)
+    t = 0
+    while t < n:
+        reg = 0 if t < b1 else (1 if t < b2 else 2)
+        p = (40, 55, 70)[reg]
+        u = np.arange(p) / p
+        cyc = (np.sin(2 * np.pi * u), 2.0 * u - 1.0, np.where(u < 0.3, 1.0, -0.4))[reg]
+        e = min(n, t + p, b1 if t < b1 else (b2 if t < b2 else n))
+        out[t:e] = rng.uniform(0.8, 1.2) * cyc[:e - t]
+        t = e
+    out += rng.normal(0.0, 0.05, n)
+    return out.astype(dtype), (b1, b2)
+
+
+def evolving_chain(n: int, m: int, k: int, seed, dtype=np.float64):
+    """A random walk with k planted windows that morph step by step from one
+    random smooth shape into another (copy t is (1 - t/(k-1)) A + t/(k-1) B
+    plus N(0, 0.01^2), scaled to the local walk), spaced evenly: each copy's
+    nearest neighbours to the left and right are the copies before and after
+    it, so they form one chain.  Returns the series and the positions."""
+    rng = np.random.default_rng(seed)
+    T = np.cumsum(rng.standard_normal(n))
+    u = np.arange(m) / m
+
+    def shape():
+        f = sum(rng.normal() * np.sin(2 * np.pi * (h * u + rng.random())) / h for h in range(1, 6))
+        return (f - f.mean()) / f.std()
+
+    A, Bs = shape(), shape()
+    gap = n // (k + 1)
+    pos = [gap * (t + 1) - m // 2 for t in range(k)]
+    for t, p in enumerate(pos):
+        w = (1 - t / (k - 1)) * A + t / (k - 1) * Bs + rng.normal(0.0, 0.01, m)
+        T[p:p + m] = T[p] + 5.0 * w
+    return T.astype(dtype), pos
+
+
 # ---- the five benchmark workloads -----------------------------------------
 
 def selfjoin_small():
