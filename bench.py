@@ -68,6 +68,12 @@ def workload(name: str, n_override=None):
         return dict(kind="self", T=pw.T, m=256, ez=64, planted=pw,
                     desc=f"self-join, float32 random walk n={n} with 8 planted motif pairs and 4 discords, "
                          f"m=256, ez=64")
+    if name == "anytime":
+        n = n_override or (1 << 20)
+        pw = W.planted_walk(n, 256, 2)
+        return dict(kind="anytime", T=pw.T, m=256, ez=64, planted=pw,
+                    desc=f"anytime self-join: a random 5% of the diagonal-offset chunks of the float32 random walk "
+                         f"n={n} with 8 planted motif pairs and 4 discords, m=256, ez=64")
     if name == "selfjoin_small":
         T, m, ez = W.selfjoin_small()
         return dict(kind="self", T=T, m=m, ez=ez, planted=None,
@@ -95,7 +101,9 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="selfjoin_large",
-                    choices=["selfjoin_large", "selfjoin_small", "abjoin_ecg", "batch_ragged", "diff_batch"])
+                    choices=["selfjoin_large", "selfjoin_small", "abjoin_ecg", "batch_ragged", "diff_batch",
+                             "anytime"])
+    ap.add_argument("--fraction", type=float, default=0.05, help="anytime workload: fraction of chunks timed")
     ap.add_argument("--n", type=int, default=None, help="override the series length")
     ap.add_argument("--slots", type=int, default=0, help="diagonals per lane (0 = automatic)")
     ap.add_argument("--reseed", type=int, default=0, help="rows per tile / reseed interval (0 = automatic)")
@@ -144,6 +152,28 @@ def main():
 
         def step(precision):
             P, I = mpx.selfjoin(Tg, m, ez, precision=precision, tile_slots=args.slots, reseed_rows=args.reseed)
+            idx, dist = mpx.recheck(Tg, m, P, I, km, kd)
+            return P, I, idx, dist
+    elif wl["kind"] == "anytime":
+        T, ez = wl["T"], wl["ez"]
+        Tg = torch.from_numpy(T).to(dev)
+        n = T.size
+        nchunk, cwidth = mpx.selfjoin_chunks(n, m, ez, tile_slots=args.slots)
+        order = mpx.anytime_order(nchunk, 0)
+        plans = {}
+
+        def anytime_plan(frac, precision="f32"):
+            k = min(nchunk, max(1, int(np.ceil(frac * nchunk))))
+            if (k, precision) not in plans:
+                plans[(k, precision)] = mpx.SelfJoinPlan(n, m, ez, dtype=torch.float32, device=dev,
+                                                         chunks=order[:k], precision=precision,
+                                                         tile_slots=args.slots, reseed_rows=args.reseed)
+            return plans[(k, precision)]
+        cells = anytime_plan(args.fraction).cells
+        km, kd = 8, 4
+
+        def step(precision):
+            P, I = anytime_plan(args.fraction, precision).run(Tg)
             idx, dist = mpx.recheck(Tg, m, P, I, km, kd)
             return P, I, idx, dist
     elif wl["kind"] == "ab":
@@ -271,6 +301,36 @@ def main():
         result["config"]["series"] = len(wl["rb"].series)
     if wl["kind"] == "diff":
         result["config"]["note"] = "value counts forward cells per second of forward+backward steps"
+    if wl["kind"] == "anytime":
+        # convergence of the best-so-far profile towards the exact one as
+        # more chunks (in one fixed random order) are included
+        l = n - m + 1
+        tol = 1e-3 * np.sqrt(m)
+        Pfull, Ifull = anytime_plan(1.0).run(Tg)
+        Pfull = Pfull.double().cpu().numpy()
+        planted = wl["planted"].motif_pairs
+        conv = []
+        for frac in (0.01, 0.02, 0.05, 0.1, 0.25, 0.5, 1.0):
+            plan = anytime_plan(frac)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            P, I = plan.run(Tg)
+            idx, _ = mpx.recheck(Tg, m, P, I, 8, 0)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3
+            Ph = P.double().cpu().numpy()
+            fin = np.isfinite(Pfull)
+            found = [tuple(sorted(p)) for p in idx.cpu().numpy()[:16].reshape(8, 2)]
+            hits = sum(any(abs(a - x) <= m // 8 and abs(b - y) <= m // 8 for x, y in found) for a, b in planted)
+            conv.append({"fraction_of_chunks": plan.cells / mpx.selfjoin_cells(n, m, ez), "chunks": len(plan.chunks),
+                         "ms": ms, "rows_within_tol_of_exact": float(np.mean(np.abs(Ph[fin] - Pfull[fin]) <= tol)),
+                         "mean_excess_over_exact": float(np.mean(Ph[fin] - Pfull[fin])),
+                         "planted_pairs_in_top8_motifs": int(hits)})
+            log(f"[bench] anytime {conv[-1]}")
+        result["convergence"] = conv
+        result["config"]["chunk_width"] = cwidth
+        result["config"]["chunks_total"] = nchunk
+        result["config"]["chunks_timed"] = len(anytime_plan(args.fraction).chunks)
 
     if not args.no_fp64 and wl["kind"] in ("self", "ab"):
         out64, ms64, sweep64, tot64 = timed("f64", max(1, min(args.steps, 3)), 1)
@@ -326,6 +386,30 @@ def main():
         if not args.no_fp64:
             P64r = out64[0].double().cpu().numpy()[rows]
             result["oracle_check"]["max_abs_dP_f64_vs_oracle"] = float(np.max(np.abs(P64r - Po)))
+    if args.cpu_rows > 0 and wl["kind"] == "anytime":
+        from oracle import cimpl
+        plan = anytime_plan(args.fraction)
+        l = n - m + 1
+        allowed = np.zeros(l, dtype=bool)
+        for c in plan.chunks:
+            allowed[ez + 1 + c * cwidth:min(ez + (c + 1) * cwidth, l - 1) + 1] = True
+        rng = np.random.default_rng(0)
+        rows = np.sort(rng.choice(l, args.cpu_rows, replace=False)).astype(np.int64)
+        T64 = T.astype(np.float64)
+        t0 = time.perf_counter()
+        Po, Io = cimpl.selfjoin_rows_restricted(T64, m, ez, rows, allowed)
+        dt = time.perf_counter() - t0
+        ks = np.nonzero(allowed)[0]
+        pairs = int(sum(np.count_nonzero(r - ks >= 0) + np.count_nonzero(r + ks < l) for r in rows))
+        result["cpu_baseline"] = {
+            "value": pairs / dt, "unit": "cells/s", "cores": cimpl.max_threads(), "kind": "oracle",
+            "sample": f"{rows.size} random rows of the same chunk-restricted self-join, {pairs} pairs, "
+                      f"each O(m) in FP64, {dt:.1f} s"}
+        result["oracle_check"] = {
+            "rows": int(rows.size),
+            "max_abs_dP_f32_vs_oracle": float(np.max(np.abs(out32[0].double().cpu().numpy()[rows] - Po))),
+            "index_agreement": float(np.mean(out32[1].cpu().numpy()[rows] == Io)),
+        }
     if args.cpu_rows > 0 and wl["kind"] == "ab":
         from oracle import cimpl
         rng = np.random.default_rng(0)

@@ -202,6 +202,54 @@ mp_status mp_backward(const mp_batch_plan *plan, const void *T_cat, const int64_
                       const void *gP_cat, void *gT_cat, void *ws, size_t ws_bytes,
                       void *stream);
 
+/* ------------------------------------------------- semantic segmentation
+ * Section 3.4.2 (FLUSS, after Gharghabi et al. 2017): every window i and its
+ * neighbour I[i] form an arc; the arc curve AC[x] counts the arcs with
+ * min(i, I[i]) <= x < max(i, I[i]).  Few arcs cross a regime change.  The
+ * corrected arc curve divides by 2x(l - x)/l, the count that arcs to
+ * uniformly random positions give, and caps at 1:
+ *   cac[x] = min(AC[x] / (2x(l - x)/l), 1),  cac[x] = 1 within `zone` of
+ *   either end (edge effect).
+ * Segment boundaries: k times the smallest cac (smallest index on ties)
+ * outside the edges and farther than `zone` from every earlier boundary;
+ * -1 once no position is left.
+ *   I         device int64[l], a profile index (entries < 0 or >= l and
+ *             I[i] == i draw no arc)
+ *   zone      >= 0 (the Python layer uses 5 m);  0 <= k <= 64
+ *   cac       device double[l], written;  segments  device int64[k]
+ *             (may be NULL when k == 0)
+ *   ws        device scratch of mp_fluss_workspace(l) bytes
+ * Arc counts are integer atomics plus a prefix sum: exact and
+ * deterministic.  Enqueues kernels only.
+ */
+size_t mp_fluss_workspace(int64_t l);
+mp_status mp_fluss(const int64_t *I, int64_t l, int64_t zone, int32_t k, double *cac,
+                   int64_t *segments, void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------ chains
+ * Section 3.4.3 (time series chains, after Zhu et al. 2018): from the left
+ * and right profile indices (mp_selfjoin_plan_create with
+ * MP_SIDES_LEFT_RIGHT), window i links forward to j = IR[i] when the link
+ * is confirmed backwards, IL[j] == i.  Confirmed links form disjoint
+ * increasing paths, the chains; every window lies on exactly one.
+ *   IL, IR   device int64[l] (-1 = none)
+ *   next     device int64[l], written: the confirmed successor or -1
+ *   length   device int64[l], written: windows from i to its chain's end
+ *   summary  device int64[3], written: number of chains (counted at their
+ *            first window) with at least min_len windows; first window of
+ *            the longest chain (the smallest one on equal lengths); its
+ *            length
+ *   best     device int64[l]: its first `length` entries receive the
+ *            longest chain's windows in order; the rest is left as is
+ *   ws       device scratch of mp_chains_workspace(l) bytes
+ * Lengths by pointer jumping (ceil(log2 l) rounds); integer work only,
+ * deterministic.  Enqueues kernels only.
+ */
+size_t mp_chains_workspace(int64_t l);
+mp_status mp_chains(const int64_t *IL, const int64_t *IR, int64_t l, int32_t min_len,
+                    int64_t *next, int64_t *length, int64_t *summary, int64_t *best, void *ws,
+                    size_t ws_bytes, void *stream);
+
 /* ----------------------------------------------------------- FP64 recheck
  * Section 2: the lowest points of P are the best motif pair, the highest
  * point is the discord.  Extracts k_motifs motif pairs (repeatedly the

@@ -12,10 +12,12 @@ package computes it with hand-written HIP kernels behind a C ABI
     P, I = mpx.matrix_profile(T_batch, m, ez)     # differentiable profile
     P, I, chunks = mpx.anytime_selfjoin(T, m, ez, fraction=0.05)  # Sections 3.3.1/3.3.3
     P, I, PL, IL, PR, IR = mpx.left_right_profiles(T, m, ez)      # left/right profiles
+    cac, boundaries = mpx.fluss(I, m, k=2)        # Section 3.4.2 segmentation
+    ch = mpx.chains(IL, IR)                       # Section 3.4.3 chains
 """
 
 from ._binding import (  # noqa: F401
-    EXPORTS, LIB_PATH, MPError, BatchPlan, SelfJoinPlan, abjoin, abjoin_cells, anytime_order,
+    EXPORTS, LIB_PATH, MPError, BatchPlan, SelfJoinPlan, abjoin, abjoin_cells, anytime_order, chains, fluss,
     anytime_selfjoin, exclusion_zone, left_right_profiles, lib, make_options, recheck, selfjoin,
     selfjoin_cells, selfjoin_chunks, timing_enable, timing_query,
 )
@@ -24,5 +26,5 @@ from .autograd import MatrixProfileFn, matrix_profile  # noqa: F401
 __all__ = [
     "selfjoin", "abjoin", "BatchPlan", "recheck", "MatrixProfileFn", "matrix_profile",
     "exclusion_zone", "selfjoin_cells", "abjoin_cells", "MPError", "lib", "SelfJoinPlan",
-    "selfjoin_chunks", "anytime_order", "anytime_selfjoin", "left_right_profiles",
+    "selfjoin_chunks", "anytime_order", "anytime_selfjoin", "left_right_profiles", "fluss", "chains",
 ]

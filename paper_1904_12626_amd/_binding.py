@@ -31,6 +31,7 @@ EXPORTS = (
     "mp_backward", "mp_recheck_workspace", "mp_recheck", "mp_strerror", "mp_abi_version",
     "mp_selfjoin_cells", "mp_abjoin_cells", "mp_timing_enable", "mp_timing_query",
     "mp_selfjoin_chunks", "mp_selfjoin_plan_create", "mp_anytime_order",
+    "mp_fluss_workspace", "mp_fluss", "mp_chains_workspace", "mp_chains",
 )
 
 
@@ -82,6 +83,10 @@ def lib():
         "mp_selfjoin_chunks": (i64, [i64, i32, i32, op, ctypes.POINTER(i64)]),
         "mp_selfjoin_plan_create": (ctypes.c_int, [i64, i32, i32, i32, op, i32, i64, vp, ctypes.POINTER(vp)]),
         "mp_anytime_order": (ctypes.c_int, [i64, ctypes.c_uint64, vp]),
+        "mp_fluss_workspace": (sz, [i64]),
+        "mp_fluss": (ctypes.c_int, [vp, i64, i64, i32, vp, vp, vp, sz, vp]),
+        "mp_chains_workspace": (sz, [i64]),
+        "mp_chains": (ctypes.c_int, [vp, vp, i64, i32, vp, vp, vp, vp, vp, sz, vp]),
         "mp_timing_enable": (ctypes.c_int, [ctypes.c_int]),
         "mp_timing_query": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                            ctypes.POINTER(ctypes.c_int64)]),
@@ -313,6 +318,7 @@ class SelfJoinPlan(BatchPlan):
         self.total_n = int(n)
         self.t_off = [0, int(n)]
         self.sides = sides
+        self.chunks = None if chunks is None else [int(c) for c in chunks]
         dt = MP_F64 if dtype == torch.float64 else MP_F32
         self._opt = make_options(precision, reseed_rows, tile_slots, fp64_finalize)
         if chunks is None:
@@ -357,6 +363,50 @@ def anytime_selfjoin(T: torch.Tensor, m: int, ez: Optional[int] = None, *, fract
     plan = SelfJoinPlan(T.numel(), m, ez, dtype=T.dtype, device=T.device, chunks=chunks, **opts)
     P, I = plan.run(T, stream=stream)
     return P, I, chunks
+
+
+def fluss(I: torch.Tensor, m: int, k: int = 2, zone: Optional[int] = None, stream=None):
+    """Corrected arc curve of a profile index and k segment boundaries
+    (mp_fluss; Section 3.4.2).  `zone` defaults to 5 m.  Returns
+    (cac float64[l], segments int64[k])."""
+    if not isinstance(I, torch.Tensor) or not I.is_cuda or I.dtype != torch.int64 or I.dim() != 1:
+        raise TypeError("I must be a 1-D int64 CUDA (HIP) tensor")
+    I = I.contiguous()
+    l = I.numel()
+    zone = 5 * int(m) if zone is None else int(zone)
+    L = lib()
+    cac = torch.empty(l, dtype=torch.float64, device=I.device)
+    seg = torch.empty(max(1, k), dtype=torch.int64, device=I.device)
+    ws_bytes = int(L.mp_fluss_workspace(l))
+    ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=I.device)
+    _check("mp_fluss", L.mp_fluss(_ptr(I), l, zone, int(k), _ptr(cac), _ptr(seg), _ptr(ws), ws_bytes,
+                                  _stream(stream)))
+    return cac, seg[:k]
+
+
+def chains(IL: torch.Tensor, IR: torch.Tensor, min_len: int = 3, stream=None):
+    """Time series chains from left/right profile indices (mp_chains;
+    Section 3.4.3).  Returns a dict: next, length (int64[l] tensors),
+    count (chains with >= min_len windows), best (the longest chain's
+    windows, a host list)."""
+    for t, name in ((IL, "IL"), (IR, "IR")):
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.int64 or t.dim() != 1:
+            raise TypeError(f"{name} must be a 1-D int64 CUDA (HIP) tensor")
+    if IL.numel() != IR.numel():
+        raise ValueError("IL and IR differ in length")
+    IL, IR = IL.contiguous(), IR.contiguous()
+    l = IL.numel()
+    L = lib()
+    nxt = torch.empty(l, dtype=torch.int64, device=IL.device)
+    length = torch.empty(l, dtype=torch.int64, device=IL.device)
+    summary = torch.empty(3, dtype=torch.int64, device=IL.device)
+    best = torch.empty(l, dtype=torch.int64, device=IL.device)
+    ws_bytes = int(L.mp_chains_workspace(l))
+    ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=IL.device)
+    _check("mp_chains", L.mp_chains(_ptr(IL), _ptr(IR), l, int(min_len), _ptr(nxt), _ptr(length), _ptr(summary),
+                                    _ptr(best), _ptr(ws), ws_bytes, _stream(stream)))
+    cnt, head, blen = (int(v) for v in summary.cpu().tolist())
+    return {"next": nxt, "length": length, "count": cnt, "best": best[:blen].cpu().tolist()}
 
 
 def recheck(T: torch.Tensor, m: int, P: torch.Tensor, I: torch.Tensor, k_motifs: int, k_discords: int,

@@ -24,6 +24,8 @@ SOURCES = {
     "mp_sweep.hip": ["-fno-honor-nans"],
     "mp_post.hip": [],
     "mp_backward.hip": [],
+    "mp_scan.hip": [],
+    "mp_mine.hip": [],
     "mp_abi.cpp": [],
 }
 

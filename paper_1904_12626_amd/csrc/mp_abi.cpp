@@ -683,6 +683,43 @@ mp_status mp_backward(const mp_batch_plan *pl, const void *T_cat, const int64_t 
   return MP_OK;
 }
 
+size_t mp_fluss_workspace(int64_t l) {
+  if (l < 1 || l >= ((int64_t)1 << 31)) return 0;
+  return align_up(8 * mpx::fluss_scratch_words(l));
+}
+
+mp_status mp_fluss(const int64_t *I, int64_t l, int64_t zone, int32_t k, double *cac, int64_t *segments,
+                   void *ws, size_t ws_bytes, void *stream) {
+  if (l < 1 || l >= ((int64_t)1 << 31) || zone < 0 || k < 0 || k > 64) return MP_EINVAL;
+  if (!I || !cac || !aligned(I, 8) || !aligned(cac, 8)) return MP_EINVAL;
+  if (k > 0 && (!segments || !aligned(segments, 8))) return MP_EINVAL;
+  mp_status s = check_ws(ws, ws_bytes, mp_fluss_workspace(l));
+  if (s != MP_OK) return s;
+  if (mpx::launch_fluss(I, l, zone, k, cac, segments, (int64_t *)ws, (hipStream_t)stream) != hipSuccess)
+    return MP_ELAUNCH;
+  return MP_OK;
+}
+
+size_t mp_chains_workspace(int64_t l) {
+  if (l < 1 || l >= ((int64_t)1 << 31)) return 0;
+  return align_up(8 * mpx::chains_scratch_words(l));
+}
+
+mp_status mp_chains(const int64_t *IL, const int64_t *IR, int64_t l, int32_t min_len, int64_t *next,
+                    int64_t *length, int64_t *summary, int64_t *best, void *ws, size_t ws_bytes,
+                    void *stream) {
+  if (l < 1 || l >= ((int64_t)1 << 31) || min_len < 1) return MP_EINVAL;
+  const void *ptrs[] = {IL, IR, next, length, summary, best};
+  for (const void *q : ptrs)
+    if (!q || !aligned(q, 8)) return MP_EINVAL;
+  mp_status s = check_ws(ws, ws_bytes, mp_chains_workspace(l));
+  if (s != MP_OK) return s;
+  if (mpx::launch_chains(IL, IR, l, min_len, next, length, summary, best, (int64_t *)ws,
+                         (hipStream_t)stream) != hipSuccess)
+    return MP_ELAUNCH;
+  return MP_OK;
+}
+
 size_t mp_recheck_workspace(int64_t n, int32_t m) {
   if (m < 2 || n < m) return 0;
   return align_up(mpx::recheck_state_bytes());

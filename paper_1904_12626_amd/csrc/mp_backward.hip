@@ -130,60 +130,6 @@ __global__ void __launch_bounds__(256) k_bwd_coef(Plan plan, BwdWork b, const Ti
   }
 }
 
-// Exclusive prefix sum of count[0..n) into off[0..n]: one workgroup per
-// chunk of 1024 entries, then a single workgroup over the chunk totals, then
-// the chunk offsets are added back.
-__global__ void __launch_bounds__(1024) k_scan_chunks(const unsigned long long *__restrict__ cnt, int64_t *off,
-                                                      int64_t *chunk_tot, int64_t n) {
-  __shared__ int64_t sh[1024];
-  const int64_t x = (int64_t)blockIdx.x * 1024 + threadIdx.x;
-  const int64_t v = x < n ? (int64_t)cnt[x] : 0;
-  sh[threadIdx.x] = v;
-  __syncthreads();
-  for (int d = 1; d < 1024; d <<= 1) {
-    const int64_t add = threadIdx.x >= (unsigned)d ? sh[threadIdx.x - d] : 0;
-    __syncthreads();
-    sh[threadIdx.x] += add;
-    __syncthreads();
-  }
-  if (x < n) off[x] = sh[threadIdx.x] - v;
-  if (threadIdx.x == 1023) chunk_tot[blockIdx.x] = sh[1023];
-}
-
-__global__ void __launch_bounds__(1024) k_scan_totals(int64_t *chunk_tot, int64_t nchunks, int64_t *off,
-                                                      int64_t n) {
-  __shared__ int64_t part[1024];
-  const int tid = threadIdx.x;
-  const int64_t per = (nchunks + 1023) / 1024;
-  const int64_t a = min(nchunks, (int64_t)tid * per), e = min(nchunks, a + per);
-  int64_t s = 0;
-  for (int64_t c = a; c < e; ++c) s += chunk_tot[c];
-  part[tid] = s;
-  __syncthreads();
-  if (tid == 0) {
-    int64_t run = 0;
-    for (int q = 0; q < 1024; ++q) {
-      const int64_t v = part[q];
-      part[q] = run;
-      run += v;
-    }
-    off[n] = run;
-  }
-  __syncthreads();
-  int64_t run = part[tid];
-  for (int64_t c = a; c < e; ++c) {
-    const int64_t v = chunk_tot[c];
-    chunk_tot[c] = run;
-    run += v;
-  }
-}
-
-__global__ void __launch_bounds__(1024) k_scan_add(int64_t *off, const int64_t *__restrict__ chunk_tot,
-                                                   int64_t n) {
-  const int64_t x = (int64_t)blockIdx.x * 1024 + threadIdx.x;
-  if (x < n) off[x] += chunk_tot[blockIdx.x];
-}
-
 // Own edge of each live row (first slot of its window) and its bucket entry
 // on the neighbour window (after that window's own edge, arbitrary order).
 __global__ void __launch_bounds__(256) k_bwd_place(BwdWork b, int64_t total_l) {
@@ -284,7 +230,6 @@ hipError_t launch_backward(const Plan &plan, const BwdWork &b, const void *T, bo
                            int64_t total_n, hipStream_t st) {
   const dim3 blk(256);
   const dim3 gl((unsigned)((total_l + 255) / 256)), gn((unsigned)((total_n + 255) / 256));
-  const int64_t nchunks = (total_l + 1023) / 1024;
   if (t_f64) {
     hipLaunchKernelGGL((k_bwd_stats<double>), gl, blk, 0, st, plan, b, (const double *)T, total_l);
     hipLaunchKernelGGL((k_bwd_coef<double, double>), gl, blk, 0, st, plan, b, (const double *)T, I,
@@ -294,11 +239,9 @@ hipError_t launch_backward(const Plan &plan, const BwdWork &b, const void *T, bo
     hipLaunchKernelGGL((k_bwd_coef<float, float>), gl, blk, 0, st, plan, b, (const float *)T, I,
                        (const float *)gP, total_l);
   }
-  hipLaunchKernelGGL(k_scan_chunks, dim3((unsigned)nchunks), dim3(1024), 0, st, (const unsigned long long *)b.count,
-                     b.off, b.chunk, total_l);
-  hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(1024), 0, st, b.chunk, nchunks, b.off, total_l);
-  hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nchunks), dim3(1024), 0, st, b.off, (const int64_t *)b.chunk,
-                     total_l);
+  const hipError_t e = launch_exclusive_scan(reinterpret_cast<const int64_t *>(b.count), b.off, b.chunk,
+                                             total_l, st);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_bwd_place, gl, blk, 0, st, b, total_l);
   hipLaunchKernelGGL(k_bwd_rank, gl, blk, 0, st, b, total_l);
   hipLaunchKernelGGL(k_bwd_window, gl, blk, 0, st, b, total_l);

@@ -142,6 +142,19 @@ hipError_t launch_backward(const Plan &plan, const BwdWork &b, const void *T, bo
                            const int64_t *I, const void *gP, void *gT, int64_t total_l,
                            int64_t total_n, hipStream_t st);
 
+// Exclusive prefix sum: out[0..n] (out[n] = total) of in[0..n); `partial`
+// holds ceil(n / 1024) + 1 entries of scratch.
+hipError_t launch_exclusive_scan(const int64_t *in, int64_t *out, int64_t *partial, int64_t n,
+                                 hipStream_t st);
+
+// Semantic segmentation and chains over a profile index (mp_mine.hip).
+size_t fluss_scratch_words(int64_t l);
+hipError_t launch_fluss(const int64_t *I, int64_t l, int64_t zone, int k, double *cac, int64_t *segments,
+                        int64_t *ws, hipStream_t st);
+size_t chains_scratch_words(int64_t l);
+hipError_t launch_chains(const int64_t *IL, const int64_t *IR, int64_t l, int64_t min_len, int64_t *next,
+                         int64_t *length, int64_t *summary, int64_t *best, int64_t *ws, hipStream_t st);
+
 // Occupancy-derived persistent grid for the sweep kernel.
 int sweep_grid(bool f64_sweep, int slots);
 

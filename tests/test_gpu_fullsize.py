@@ -231,3 +231,34 @@ def test_differentiable_batch_full():
         assert abs(fd - g[b, t]) <= 1e-3 * max(1.0, abs(fd)), (b, t, fd, g[b, t])
         checked += 1
     print(f"FD checked {checked} coordinates, redrawn {flips}")
+
+
+def test_left_right_segmentation_chains_full():
+    """The benchmark self-join (n=2^20, m=256) split into left and right
+    profiles by one sweep; sampled rows of each side against the oracle;
+    the combined profile against the plain self-join; arc curve, boundaries
+    and chains of the GPU indices against the oracle on the same indices."""
+    import paper_1904_12626_amd as mpx
+    pw, ez = W.selfjoin_large()
+    m = pw.m
+    Tg = torch.from_numpy(pw.T).to(DEV)
+    P, I, PL, IL, PR, IR = [_np(x) for x in mpx.left_right_profiles(Tg, m, ez)]
+    P1, I1 = [_np(x) for x in mpx.selfjoin(Tg, m, ez)]
+    tol = 1e-3 * math.sqrt(m)
+    assert np.max(np.abs(P - P1)) <= tol
+    T64 = pw.T.astype(np.float64)
+    rng = np.random.default_rng(6)
+    rows = np.sort(rng.choice(P.size, 24, replace=False))
+    for side, Ps, Is in (("left", PL, IL), ("right", PR, IR)):
+        Po, Io = cimpl.selfjoin_rows_restricted(T64, m, ez, rows, None, side)
+        fin = np.isfinite(Po)
+        assert np.array_equal(np.isfinite(Ps[rows]), fin)
+        assert np.max(np.abs(Ps[rows][fin] - Po[fin])) <= tol, side
+    cac, seg = mpx.fluss(torch.from_numpy(I).to(DEV), m, k=3)
+    want = O.corrected_arc_curve(I, 5 * m)
+    np.testing.assert_allclose(cac.cpu().numpy(), want, rtol=1e-15, atol=0)
+    assert list(seg.cpu().numpy()) == O.fluss_segments(want, 3, 5 * m)
+    ch = mpx.chains(torch.from_numpy(IL).to(DEV), torch.from_numpy(IR).to(DEV))
+    nxt, length, count, best = O.chains(IL, IR)
+    assert np.array_equal(ch["next"].cpu().numpy(), nxt) and np.array_equal(ch["length"].cpu().numpy(), length)
+    assert ch["count"] == count and ch["best"] == best
