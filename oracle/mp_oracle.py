@@ -67,6 +67,8 @@ __all__ = [
     "top_discords",
     "reference_gradient",
     "profile_sum_loss",
+    "reference_gradient_ab",
+    "abjoin_sum_loss",
 ]
 
 
@@ -499,4 +501,56 @@ def profile_sum_loss(T, m: int, I) -> float:
         if j < 0:
             continue
         tot += pair_distance(T, i, T, j, m)
+    return tot
+
+
+def reference_gradient_ab(A, B, m: int, Iab, gPab, Iba, gPba):
+    """(dL/dA, dL/dB) for an AB-join loss with dL/dP_ab = gPab and
+    dL/dP_ba = gPba, indices held fixed: row i of A with neighbour j = Iab[i]
+    of B adds gPab[i] * dd(A_i, B_j) -- (rho z_a - z_b)/(sigma_a d) on
+    A[i:i+m] and (rho z_b - z_a)/(sigma_b d) on B[j:j+m] -- and row j of B
+    with neighbour Iba[j] of A the same with the roles swapped.  Same
+    subgradient-0 rules as reference_gradient."""
+    A = np.asarray(A, dtype=np.float64)
+    B = np.asarray(B, dtype=np.float64)
+    gA = np.zeros_like(A)
+    gB = np.zeros_like(B)
+
+    def add(X, gX, i, Y, gY, j, g):
+        a = X[i:i + m]
+        b = Y[j:j + m]
+        if g == 0.0 or not (np.isfinite(a).all() and np.isfinite(b).all()):
+            return
+        if a.max() == a.min() or b.max() == b.min():
+            return
+        sa = np.sqrt(((a - a.mean()) ** 2).mean())
+        sb = np.sqrt(((b - b.mean()) ** 2).mean())
+        za = (a - a.mean()) / sa
+        zb = (b - b.mean()) / sb
+        d = np.sqrt(((za - zb) ** 2).sum())
+        if d == 0.0:
+            return
+        rho = (za * zb).sum() / m
+        gX[i:i + m] += g * (rho * za - zb) / (sa * d)
+        gY[j:j + m] += g * (rho * zb - za) / (sb * d)
+
+    for i in range(len(Iab)):
+        if Iab[i] >= 0:
+            add(A, gA, i, B, gB, int(Iab[i]), float(gPab[i]))
+    for j in range(len(Iba)):
+        if Iba[j] >= 0:
+            add(B, gB, j, A, gA, int(Iba[j]), float(gPba[j]))
+    return gA, gB
+
+
+def abjoin_sum_loss(A, B, m: int, Iab, wab, Iba, wba) -> float:
+    """L = sum_i wab[i] d(A_i, B_Iab[i]) + sum_j wba[j] d(B_j, A_Iba[j]),
+    indices held fixed."""
+    tot = 0.0
+    for i in range(len(Iab)):
+        if Iab[i] >= 0:
+            tot += wab[i] * pair_distance(A, i, B, int(Iab[i]), m)
+    for j in range(len(Iba)):
+        if Iba[j] >= 0:
+            tot += wba[j] * pair_distance(B, j, A, int(Iba[j]), m)
     return tot

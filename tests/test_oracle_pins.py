@@ -518,3 +518,29 @@ def test_chains_partition_the_windows_and_follow_an_evolving_pattern():
     assert np.unique(succ).size == succ.size
     for p in pos:
         assert any(abs(b - p) <= m // 8 for b in best), (p, best)
+
+
+def test_ab_reference_gradient_matches_finite_differences():
+    """Central differences (h = 1e-6) of the weighted AB loss with fixed
+    indices on every coordinate of A and B."""
+    rng = np.random.default_rng(100)
+    A = np.cumsum(rng.standard_normal(60))
+    B = np.cumsum(rng.standard_normal(45))
+    m = 8
+    Pab, Iab, Pba, Iba = O.abjoin(A, B, m)
+    wab = rng.uniform(0.5, 1.5, Iab.size)
+    wba = rng.uniform(0.5, 1.5, Iba.size)
+    gA, gB = O.reference_gradient_ab(A, B, m, Iab, wab, Iba, wba)
+    h = 1e-6
+    for X, gX, isA in ((A, gA, True), (B, gB, False)):
+        for t in range(X.size):
+            Xp, Xm = X.copy(), X.copy()
+            Xp[t] += h
+            Xm[t] -= h
+            if isA:
+                fd = (O.abjoin_sum_loss(Xp, B, m, Iab, wab, Iba, wba) - O.abjoin_sum_loss(Xm, B, m, Iab, wab, Iba, wba)) / (2 * h)
+            else:
+                fd = (O.abjoin_sum_loss(A, Xp, m, Iab, wab, Iba, wba) - O.abjoin_sum_loss(A, Xm, m, Iab, wab, Iba, wba)) / (2 * h)
+            assert abs(fd - gX[t]) <= 1e-6 * max(1.0, abs(fd)), (isA, t, fd, gX[t])
+    # each row's contribution is shift invariant: the gradients sum to zero
+    assert abs(gA.sum() + gB.sum()) < 1e-9
