@@ -141,6 +141,17 @@ mp_status mp_batch(const mp_batch_plan *plan, const void *T_cat, void *P_cat, in
                    void *ws, size_t ws_bytes, void *stream);
 void mp_batch_plan_destroy(mp_batch_plan *plan);
 
+/* -------------------------------------------------------- AB-join plans
+ * The AB-join of Section 3.2 as a batch plan, so that it can be captured
+ * and differentiated: T_cat = A (nA values) followed by B (nB values);
+ * the plan's profile (mp_batch_plan_profile_length = lA + lB entries) is
+ * P_ab (lA entries, indices into B) followed by P_ba (lB entries, indices
+ * into A).  Run with mp_batch_plan_upload / mp_batch; mp_backward then
+ * gives dL/dA followed by dL/dB from gP = [gP_ab | gP_ba].
+ */
+mp_status mp_abjoin_plan_create(int64_t nA, int64_t nB, int32_t m, mp_dtype dtype,
+                                const mp_options *opt, mp_batch_plan **out);
+
 /* ------------------------------------ partial and one-sided self-joins
  * Sections 3.3.1 and 3.3.3 (STAMP, SCRIMP): the profile can be computed in a
  * random order of its parts and read at any point as the best-so-far
@@ -184,8 +195,10 @@ mp_status mp_anytime_order(int64_t count, uint64_t seed, int64_t *order_host);
 
 /* ---------------------------------------------------------------- backward
  * Gradient of a loss L(P) with respect to T through the z-normalised
- * distance of each row's argmin pair, holding I fixed (not in the paper; the
- * derivative of d(i, j) = ||z_i - z_j|| through z = (x - mean)/sigma):
+ * distance of each row's argmin pair (j = I[i] in the same series for a
+ * self-join plan, in the other series for an AB-join plan), holding I
+ * fixed (not in the paper; the derivative of d(i, j) = ||z_i - z_j||
+ * through z = (x - mean)/sigma):
  *   dd/dT[i:i+m] = (rho z_i - z_j) / (sigma_i d),
  *   dd/dT[j:j+m] = (rho z_j - z_i) / (sigma_j d),   rho = z_i.z_j / m.
  * Rows with I < 0 (or I outside the series), a zero or non-finite gP, d == 0,

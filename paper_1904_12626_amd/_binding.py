@@ -31,7 +31,7 @@ EXPORTS = (
     "mp_backward", "mp_recheck_workspace", "mp_recheck", "mp_strerror", "mp_abi_version",
     "mp_selfjoin_cells", "mp_abjoin_cells", "mp_timing_enable", "mp_timing_query",
     "mp_selfjoin_chunks", "mp_selfjoin_plan_create", "mp_anytime_order",
-    "mp_fluss_workspace", "mp_fluss", "mp_chains_workspace", "mp_chains",
+    "mp_fluss_workspace", "mp_fluss", "mp_chains_workspace", "mp_chains", "mp_abjoin_plan_create",
 )
 
 
@@ -83,6 +83,7 @@ def lib():
         "mp_selfjoin_chunks": (i64, [i64, i32, i32, op, ctypes.POINTER(i64)]),
         "mp_selfjoin_plan_create": (ctypes.c_int, [i64, i32, i32, i32, op, i32, i64, vp, ctypes.POINTER(vp)]),
         "mp_anytime_order": (ctypes.c_int, [i64, ctypes.c_uint64, vp]),
+        "mp_abjoin_plan_create": (ctypes.c_int, [i64, i64, i32, i32, op, ctypes.POINTER(vp)]),
         "mp_fluss_workspace": (sz, [i64]),
         "mp_fluss": (ctypes.c_int, [vp, i64, i64, i32, vp, vp, vp, sz, vp]),
         "mp_chains_workspace": (sz, [i64]),
@@ -280,6 +281,29 @@ class BatchPlan:
         if h is not None and h.value and _lib is not None:
             _lib.mp_batch_plan_destroy(h)
             self._h = None
+
+
+class ABJoinPlan(BatchPlan):
+    """AB-join as a batch plan (mp_abjoin_plan_create): `run(T_cat)` with
+    T_cat = [A | B] returns (P, I) = ([P_ab | P_ba], [I_ab | I_ba]);
+    `backward` gives [dL/dA | dL/dB]."""
+
+    def __init__(self, nA, nB, m, dtype=torch.float32, device="cuda", *, precision: str = "f32",
+                 reseed_rows: int = 0, tile_slots: int = 0, fp64_finalize: bool = True):
+        L = lib()
+        self.lengths, self.windows, self.zones = [int(nA), int(nB)], [int(m), int(m)], [-1, -1]
+        self.dtype = dtype
+        self.device = torch.device(device)
+        self.total_n = int(nA) + int(nB)
+        self.t_off = [0, int(nA), int(nA) + int(nB)]
+        dt = MP_F64 if dtype == torch.float64 else MP_F32
+        self._opt = make_options(precision, reseed_rows, tile_slots, fp64_finalize)
+        h = ctypes.c_void_p()
+        _check("mp_abjoin_plan_create", L.mp_abjoin_plan_create(int(nA), int(nB), int(m), dt,
+                                                                ctypes.byref(self._opt), ctypes.byref(h)))
+        lA, lB = int(nA) - int(m) + 1, int(nB) - int(m) + 1
+        self.p_off = [0, lA, lA + lB]
+        self._setup(h)
 
 
 def selfjoin_chunks(n: int, m: int, ez: int, *, precision: str = "f32", tile_slots: int = 0):

@@ -43,3 +43,17 @@ def matrix_profile(T: torch.Tensor, m: int, ez: int, plan: BatchPlan | None = No
     if plan is None:
         plan = BatchPlan([n] * B, [m] * B, [ez] * B, dtype=T.dtype, device=T.device, **plan_kw)
     return MatrixProfileFn.apply(T, plan)
+
+
+def abjoin_profile(A: torch.Tensor, B: torch.Tensor, m: int, plan=None, **plan_kw):
+    """Differentiable AB-join: (P_ab, I_ab, P_ba, I_ba) with gradients
+    flowing to A and B through both profiles (indices held fixed)."""
+    from ._binding import ABJoinPlan
+    if A.dim() != 1 or B.dim() != 1:
+        raise ValueError("A and B must be 1-D")
+    if plan is None:
+        plan = ABJoinPlan(A.numel(), B.numel(), m, dtype=A.dtype, device=A.device, **plan_kw)
+    T = torch.cat([A, B])          # the plan's layout: A then B
+    P, I = MatrixProfileFn.apply(T, plan)
+    lA = A.numel() - m + 1
+    return P[:lA], I[:lA], P[lA:], I[lA:]

@@ -162,7 +162,7 @@ void finish_job(Job &j) {
 
 struct Layout {
   size_t mu, sig, keys, flags, nc, nv, rc, special, counters, segp, segs, rescan, sdesc, wdesc, kmask;
-  size_t b_mu, b_isig, b_coef, b_nbr, b_count, b_fill, b_off, b_tmp, b_erec, b_wrec, b_chunk;
+  size_t b_mu, b_isig, b_wpos, b_coef, b_nbr, b_count, b_fill, b_off, b_tmp, b_erec, b_wrec, b_chunk;
   size_t total;
 };
 
@@ -190,6 +190,7 @@ Layout layout_of(const Job &j, bool with_batch_tables) {
   if (with_batch_tables) {
     L.b_mu = take(8 * tl);
     L.b_isig = take(8 * tl);
+    L.b_wpos = take(8 * tl);
     L.b_coef = take(32 * tl);
     L.b_nbr = take(8 * tl);
     L.b_count = take(8 * tl);
@@ -230,6 +231,7 @@ mpx::BwdWork bwd_work_of(const Layout &L, void *ws) {
   mpx::BwdWork w{};
   w.mu = (double *)(b + L.b_mu);
   w.isig = (double *)(b + L.b_isig);
+  w.wpos = (int64_t *)(b + L.b_wpos);
   w.coef = (double *)(b + L.b_coef);
   w.nbr = (int64_t *)(b + L.b_nbr);
   w.count = (unsigned long long *)(b + L.b_count);
@@ -544,6 +546,25 @@ mp_status mp_batch_plan_create(int32_t nseries, const int64_t *t_off, const int3
     add_sweep(j, i, i, i, i, (int64_t)ez[i] + 1, j.series[i].l - 1);
   finish_job(j);
   pl->lay = layout_of(j, true);
+  *out = pl;
+  return MP_OK;
+}
+
+mp_status mp_abjoin_plan_create(int64_t nA, int64_t nB, int32_t m, mp_dtype dtype,
+                                const mp_options *opt, mp_batch_plan **out) {
+  if (!out) return MP_EINVAL;
+  *out = nullptr;
+  mp_batch_plan *pl = new (std::nothrow) mp_batch_plan();
+  if (!pl) return MP_EINVAL;
+  const mp_status s = build_abjoin(nA, nB, nA, m, dtype, opt, pl->job);
+  if (s != MP_OK) {
+    delete pl;
+    return s;
+  }
+  // one output array: P_ab at [0, lA), P_ba at [lA, lA + lB)
+  pl->job.series[1].out = 0;
+  pl->job.series[1].p_off = pl->job.series[1].w_off;
+  pl->lay = layout_of(pl->job, true);
   *out = pl;
   return MP_OK;
 }

@@ -1,5 +1,7 @@
 // Backward pass of a loss through the matrix profile, holding the index
-// fixed: for every row i with neighbour j = I[i] and upstream gradient g,
+// fixed: for every row i with neighbour j = I[i] (a window of the same
+// series for a self-join, of the other series for an AB-join) and upstream
+// gradient g,
 //   d P_i / d T[i+u] = (rho z_i[u] - z_j[u]) / (sigma_i d),
 //   d P_i / d T[j+u] = (rho z_j[u] - z_i[u]) / (sigma_j d),
 // with z the z-normalised windows, d = ||z_i - z_j|| and rho = z_i.z_j / m
@@ -81,6 +83,7 @@ __global__ void __launch_bounds__(256) k_bwd_stats(Plan plan, BwdWork b, const T
   const double sg = sqrt(q / m);
   b.mu[wi] = ok ? mu : 0.0;
   b.isig[wi] = (ok && lo != hi && sg > 0.0) ? 1.0 / sg : 0.0;
+  b.wpos[wi] = S.t_off + (wi - S.w_off);
   b.count[wi] = 0ull;
   b.fill[wi] = 0ull;
 }
@@ -95,18 +98,20 @@ __global__ void __launch_bounds__(256) k_bwd_coef(Plan plan, BwdWork b, const Ti
 #pragma clang fp contract(off)
   const int64_t wi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (wi >= total_l) return;
-  const SeriesDesc S = plan.series(find_series_by_w(plan, wi));
+  const int si = find_series_by_w(plan, wi);
+  const SeriesDesc S = plan.series(si);
+  const SeriesDesc Q = plan.series(S.partner);  // the series I indexes into
   const int64_t i = wi - S.w_off;
   const int64_t j = I[wi];
   const double g = (double)gP[wi];
   Double4 c{0.0, 0.0, 0.0, 0.0};
   int64_t jw = -1;
-  if (j >= 0 && j < S.l && j != i && g != 0.0 && isfinite(g)) {
-    jw = S.w_off + j;
+  if (j >= 0 && j < Q.l && !(S.partner == si && j == i) && g != 0.0 && isfinite(g)) {
+    jw = Q.w_off + j;
     const double isi = b.isig[wi], isj = b.isig[jw];
     if (isi > 0.0 && isj > 0.0) {
       const Tin *xi = Tb + S.t_off + i;
-      const Tin *xj = Tb + S.t_off + j;
+      const Tin *xj = Tb + Q.t_off + j;
       const double mi = b.mu[wi], mj = b.mu[jw];
       double d2 = 0.0, dot = 0.0;
       for (int u = 0; u < S.m; ++u) {
@@ -138,7 +143,7 @@ __global__ void __launch_bounds__(256) k_bwd_place(BwdWork b, int64_t total_l) {
   const int64_t jw = b.nbr[wi];
   if (jw < 0) return;
   const Double4 c = reinterpret_cast<const Double4 *>(b.coef)[wi];
-  b.erec[b.off[wi]] = BwdEdge{c.y * b.isig[jw], b.mu[jw], jw - wi, 0.0};
+  b.erec[b.off[wi]] = BwdEdge{c.y * b.isig[jw], b.mu[jw], b.wpos[jw] - b.wpos[wi], 0.0};
   const int64_t base = b.off[jw] + (b.nbr[jw] >= 0 ? 1 : 0);
   const unsigned long long pos = atomicAdd(&b.fill[jw], 1ull);
   b.tmp[base + (int64_t)pos] = wi;
@@ -155,7 +160,7 @@ __global__ void __launch_bounds__(256) k_bwd_rank(BwdWork b, int64_t total_l) {
   int64_t r = 0;
   for (int64_t p = a; p < e; ++p) r += b.tmp[p] < wi;
   const Double4 c = reinterpret_cast<const Double4 *>(b.coef)[wi];
-  b.erec[a + r] = BwdEdge{c.w * b.isig[wi], b.mu[wi], wi - jw, c.z};
+  b.erec[a + r] = BwdEdge{c.w * b.isig[wi], b.mu[wi], b.wpos[wi] - b.wpos[jw], c.z};
 }
 
 // Per window: its own alpha plus the gammas of its bucket, in edge order.

@@ -94,7 +94,7 @@ struct Work {
 struct BwdEdge {
   double c;      // coefficient on (x[t + delta] - mu)
   double mu;     // mean of the source window
-  int64_t delta; // source window start - destination window start
+  int64_t delta; // source window start - destination window start (samples)
   double gam;    // (bucket edges) the row's multiple of the destination z
 };
 struct BwdWin {
@@ -104,6 +104,7 @@ struct BwdWin {
 struct BwdWork {
   double *mu;          // [total_l] window mean
   double *isig;        // [total_l] 1/sigma, 0 for constant or non-finite windows
+  int64_t *wpos;       // [total_l] position of the window's first sample in T
   double *coef;        // [4 total_l] per row: alpha, beta (window i), gamma, delta (window j)
   int64_t *nbr;        // [total_l] neighbour window (global), -1 if the row contributes nothing
   unsigned long long *count;  // [total_l] edges per destination window

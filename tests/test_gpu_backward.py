@@ -107,3 +107,33 @@ def test_backward_hub_constant_and_nan_windows():
     assert np.all(np.isfinite(g))
     bad = np.flatnonzero(np.abs(g - ref) > 1e-9 * np.abs(ref).max() + 1e-9 * np.abs(ref))
     assert bad.size == 0, (bad[:70].tolist(), g[bad[:8]].tolist(), ref[bad[:8]].tolist())
+
+
+@pytest.mark.parametrize("precision,dtype", [("f64", np.float64), ("f32", np.float32)])
+def test_abjoin_plan_and_backward(precision, dtype):
+    """AB-join as a plan: profiles equal mp_abjoin's; the backward gives
+    [dL/dA | dL/dB] equal to the FP64 reference gradient."""
+    import paper_1904_12626_amd as mpx
+    rng = np.random.default_rng(110)
+    A = np.cumsum(rng.standard_normal(1500)).astype(dtype)
+    Bs = np.cumsum(rng.standard_normal(1100)).astype(dtype)
+    m = 32
+    Ag, Bg = torch.from_numpy(A).to(DEV), torch.from_numpy(Bs).to(DEV)
+    plan = mpx.ABJoinPlan(A.size, Bs.size, m, dtype=Ag.dtype, device=DEV, precision=precision)
+    P, I = plan.run(torch.cat([Ag, Bg]))
+    Pab, Iab, Pba, Iba = mpx.abjoin(Ag, Bg, m, precision=precision)
+    lA = A.size - m + 1
+    assert torch.equal(P[:lA], Pab) and torch.equal(I[:lA], Iab)
+    assert torch.equal(P[lA:], Pba) and torch.equal(I[lA:], Iba)
+    w = torch.from_numpy(rng.uniform(0.5, 1.5, P.numel())).to(DEV, Ag.dtype)
+    Ax = Ag.clone().requires_grad_(True)
+    Bx = Bg.clone().requires_grad_(True)
+    pab, iab, pba, iba = mpx.abjoin_profile(Ax, Bx, m, precision=precision)
+    (torch.cat([pab, pba]) * w).sum().backward()
+    wh = w.double().cpu().numpy()
+    gA, gB = O.reference_gradient_ab(A.astype(np.float64), Bs.astype(np.float64), m, iab.cpu().numpy(), wh[:lA],
+                                     iba.cpu().numpy(), wh[lA:])
+    tol = 1e-9 if precision == "f64" else 1e-4
+    for g, ref in ((Ax.grad, gA), (Bx.grad, gB)):
+        g = g.double().cpu().numpy()
+        np.testing.assert_allclose(g, ref, rtol=tol, atol=tol * np.abs(ref).max())
