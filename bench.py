@@ -74,6 +74,12 @@ def workload(name: str, n_override=None):
         return dict(kind="anytime", T=pw.T, m=256, ez=64, planted=pw,
                     desc=f"anytime self-join: a random 5% of the diagonal-offset chunks of the float32 random walk "
                          f"n={n} with 8 planted motif pairs and 4 discords, m=256, ez=64")
+    if name == "left_right":
+        n = n_override or (1 << 20)
+        pw = W.planted_walk(n, 256, 2)
+        return dict(kind="lr", T=pw.T, m=256, ez=64, planted=pw,
+                    desc=f"left/right profiles of the float32 random walk n={n} with 8 planted motif pairs and 4 "
+                         f"discords, m=256, ez=64, then the corrected arc curve with 2 boundaries and the chains")
     if name == "selfjoin_small":
         T, m, ez = W.selfjoin_small()
         return dict(kind="self", T=T, m=m, ez=ez, planted=None,
@@ -102,7 +108,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="selfjoin_large",
                     choices=["selfjoin_large", "selfjoin_small", "abjoin_ecg", "batch_ragged", "diff_batch",
-                             "anytime"])
+                             "anytime", "left_right"])
     ap.add_argument("--fraction", type=float, default=0.05, help="anytime workload: fraction of chunks timed")
     ap.add_argument("--n", type=int, default=None, help="override the series length")
     ap.add_argument("--slots", type=int, default=0, help="diagonals per lane (0 = automatic)")
@@ -176,6 +182,23 @@ def main():
             P, I = anytime_plan(args.fraction, precision).run(Tg)
             idx, dist = mpx.recheck(Tg, m, P, I, km, kd)
             return P, I, idx, dist
+    elif wl["kind"] == "lr":
+        T, ez = wl["T"], wl["ez"]
+        Tg = torch.from_numpy(T).to(dev)
+        n = T.size
+        l = n - m + 1
+        lr_plans = {}
+
+        def step(precision):
+            if precision not in lr_plans:
+                lr_plans[precision] = mpx.SelfJoinPlan(n, m, ez, dtype=torch.float32, device=dev, sides="lr",
+                                                       precision=precision, tile_slots=args.slots,
+                                                       reseed_rows=args.reseed)
+            P, I = lr_plans[precision].run(Tg)
+            cac, seg = mpx.fluss(I[:l], m, k=2)
+            ch = mpx.chains(I[l:2 * l], I[2 * l:])
+            return P, I, cac, seg, ch
+        cells = mpx.selfjoin_cells(n, m, ez)
     elif wl["kind"] == "ab":
         A, B = wl["A"], wl["B"]
         Ag, Bg = torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev)
@@ -301,6 +324,11 @@ def main():
         result["config"]["series"] = len(wl["rb"].series)
     if wl["kind"] == "diff":
         result["config"]["note"] = "value counts forward cells per second of forward+backward steps"
+    if wl["kind"] == "lr":
+        ch = out32[4]
+        result["config"]["longest_chain"] = len(ch["best"])
+        result["config"]["chains_min3"] = ch["count"]
+        result["config"]["boundaries"] = [int(v) for v in out32[3].cpu().tolist()]
     if wl["kind"] == "anytime":
         # convergence of the best-so-far profile towards the exact one as
         # more chunks (in one fixed random order) are included
