@@ -69,6 +69,8 @@ __all__ = [
     "profile_sum_loss",
     "reference_gradient_ab",
     "abjoin_sum_loss",
+    "simple_join",
+    "mstomp",
 ]
 
 
@@ -554,3 +556,73 @@ def abjoin_sum_loss(A, B, m: int, Iab, wab, Iba, wba) -> float:
         if Iba[j] >= 0:
             tot += wba[j] * pair_distance(B, j, A, int(Iba[j]), m)
     return tot
+
+
+# --------------------------------------------------------------------------
+# Non-normalised (SiMPle) and multidimensional (mSTOMP) joins, Sections
+# 3.3.4 and 3.3.5.  T has shape [D, n]: D dimensions sampled together; a
+# window is invalid when any dimension holds a non-finite value in it.
+# --------------------------------------------------------------------------
+
+def _md_windows(T, m):
+    T = np.atleast_2d(np.asarray(T, dtype=np.float64))
+    D, n = T.shape
+    l = n - m + 1
+    W = np.stack([_windows(T[d], m) for d in range(D)])      # [D, l, m]
+    valid = np.isfinite(W).all(axis=(0, 2))
+    return W, valid
+
+
+def simple_join(TA, m: int, ez=None, TB=None):
+    """SiMPle profile: P[i] = min_j sqrt(sum_d ||A_i^d - B_j^d||^2) over all
+    dimensions, no z-normalisation (Section 3.3.4).  Self-join (TB None,
+    pairs with |i - j| <= ez excluded) or AB-join (no zone).  Brute force."""
+    WA, vA = _md_windows(TA, m)
+    WB, vB = (WA, vA) if TB is None else _md_windows(TB, m)
+    lA, lB = WA.shape[1], WB.shape[1]
+    XA = np.where(vA[None, :, None], WA, 0.0).transpose(1, 0, 2).reshape(lA, -1)
+    XB = np.where(vB[None, :, None], WB, 0.0).transpose(1, 0, 2).reshape(lB, -1)
+    P = np.full(lA, np.inf)
+    I = np.full(lA, -1, dtype=np.int64)
+    jidx = np.arange(lB)
+    for i in range(lA):
+        if not vA[i]:
+            continue
+        diff = XB - XA[i]
+        d = np.sqrt((diff * diff).sum(axis=1))
+        d[~vB] = np.inf
+        if TB is None:
+            d[np.abs(jidx - i) <= ez] = np.inf
+        P[i], I[i] = _row_min(d)
+    return P, I
+
+
+def mstomp(T, m: int, ez: int):
+    """Multidimensional profiles (Section 3.3.5): for every pair the
+    z-normalised distance of each dimension (constant windows normalise to
+    zero), sorted ascending; the k-dimensional distance is the mean of the k
+    smallest; P[k-1][i] = min over |i - j| > ez of it, k = 1 .. D.
+    Returns P, I of shape [D, l]."""
+    W, valid = _md_windows(T, m)
+    D, l, _ = W.shape
+    Z = np.zeros_like(W)
+    for d in range(D):
+        mu = W[d].mean(axis=1)
+        sg = np.sqrt(((W[d] - mu[:, None]) ** 2).mean(axis=1))
+        const = W[d].max(axis=1) == W[d].min(axis=1)
+        ok = valid & ~const
+        Z[d, ok] = (W[d, ok] - mu[ok, None]) / sg[ok, None]
+    P = np.full((D, l), np.inf)
+    I = np.full((D, l), -1, dtype=np.int64)
+    jidx = np.arange(l)
+    for i in range(l):
+        if not valid[i]:
+            continue
+        dist = np.sqrt(((Z - Z[:, i:i + 1, :]) ** 2).sum(axis=2))   # [D, l]
+        dist = np.sort(dist, axis=0)
+        avg = np.cumsum(dist, axis=0) / np.arange(1, D + 1)[:, None]
+        avg[:, ~valid] = np.inf
+        avg[:, np.abs(jidx - i) <= ez] = np.inf
+        for k in range(D):
+            P[k, i], I[k, i] = _row_min(avg[k])
+    return P, I

@@ -544,3 +544,74 @@ def test_ab_reference_gradient_matches_finite_differences():
             assert abs(fd - gX[t]) <= 1e-6 * max(1.0, abs(fd)), (isA, t, fd, gX[t])
     # each row's contribution is shift invariant: the gradients sum to zero
     assert abs(gA.sum() + gB.sum()) < 1e-9
+
+
+# ------------------------------------------- SiMPle and multidimensional
+
+def test_simple_join_is_plain_euclidean():
+    """SiMPle = Euclidean distance of raw windows (all dimensions stacked):
+    scipy cdist on the concatenated windows, row minimum outside the zone;
+    and it is not shift invariant, unlike the z-normalised profile."""
+    rng = np.random.default_rng(120)
+    T = np.cumsum(rng.standard_normal((3, 150)), axis=1)
+    m, ez = 10, 3
+    l = 150 - m + 1
+    X = np.concatenate([np.lib.stride_tricks.sliding_window_view(T[d], m) for d in range(3)], axis=1)
+    Dm = cdist(X, X)
+    Dm[np.abs(np.arange(l)[:, None] - np.arange(l)[None, :]) <= ez] = np.inf
+    P, I = O.simple_join(T, m, ez)
+    np.testing.assert_allclose(P, Dm.min(axis=1), rtol=0, atol=1e-10)
+    assert np.array_equal(I, Dm.argmin(axis=1))
+    P2, _ = O.simple_join(T + 5.0, m, ez)
+    np.testing.assert_allclose(P2, P, atol=1e-9)       # a common offset cancels
+    P3, _ = O.simple_join(T * np.array([[1.0], [1.0], [3.0]]), m, ez)
+    assert not np.allclose(P3, P)
+    # AB form
+    B = np.cumsum(rng.standard_normal((3, 90)), axis=1)
+    Pab, Iab = O.simple_join(T, m, TB=B)
+    XB = np.concatenate([np.lib.stride_tricks.sliding_window_view(B[d], m) for d in range(3)], axis=1)
+    np.testing.assert_allclose(Pab, cdist(X, XB).min(axis=1), rtol=0, atol=1e-10)
+
+
+def test_mstomp_one_dimension_is_the_profile_and_loops_agree():
+    rng = np.random.default_rng(121)
+    T = np.cumsum(rng.standard_normal(200))
+    m, ez = 12, 3
+    P, I = O.mstomp(T[None, :], m, ez)
+    P1, I1 = O.selfjoin(T, m, ez)
+    np.testing.assert_allclose(P[0], P1, rtol=0, atol=1e-12)
+    assert np.array_equal(I[0], I1)
+    # pair-by-pair loops on a 3-dimensional series
+    T3 = np.cumsum(rng.standard_normal((3, 60)), axis=1)
+    m = 6
+    P, I = O.mstomp(T3, m, 2)
+    l = 60 - m + 1
+    for i in range(0, l, 7):
+        best = np.full(3, np.inf)
+        arg = np.full(3, -1)
+        for j in range(l):
+            if abs(i - j) <= 2:
+                continue
+            ds = np.sort([O.pair_distance(T3[d], i, T3[d], j, m) for d in range(3)])
+            for k in range(3):
+                v = ds[:k + 1].mean()
+                if v < best[k]:
+                    best[k], arg[k] = v, j
+        np.testing.assert_allclose(P[:, i], best, rtol=0, atol=1e-12)
+        assert np.array_equal(I[:, i], arg)
+
+
+def test_mstomp_finds_a_motif_living_in_some_dimensions():
+    """A pattern planted in dimensions 0 and 2 only: the 2-dimensional
+    profile pairs the copies; using every dimension (k = 3) does not."""
+    rng = np.random.default_rng(122)
+    n, m = 800, 32
+    T = np.cumsum(rng.standard_normal((3, n)), axis=1)
+    pat = rng.standard_normal((2, m)) * 3
+    for p in (150, 600):
+        T[0, p:p + m] = T[0, p] + pat[0] + rng.normal(0, 0.05, m)
+        T[2, p:p + m] = T[2, p] + pat[1] + rng.normal(0, 0.05, m)
+    P, I = O.mstomp(T, m, m // 4)
+    assert abs(int(I[1, 150]) - 600) <= 2 and abs(int(I[1, 600]) - 150) <= 2
+    assert P[1, 150] < 0.5 * np.median(P[1])
+    assert P[2, 150] > P[1, 150]
