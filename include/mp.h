@@ -215,6 +215,41 @@ mp_status mp_backward(const mp_batch_plan *plan, const void *T_cat, const int64_
                       const void *gP_cat, void *gT_cat, void *ws, size_t ws_bytes,
                       void *stream);
 
+/* ------------------------------------------------- multidimensional joins
+ * A series with D dimensions sampled together (1 <= D <= 8), stored
+ * dimension-major: dimension d of a series of n samples occupies
+ * [d*n, (d+1)*n) of its array.  A window is invalid (P = +inf, I = -1,
+ * never a neighbour) when any dimension holds a non-finite value in it.
+ *   MP_MD_SIMPLE  Section 3.3.4 (SiMPle): no z-normalisation, the distance
+ *                 summed over every dimension,
+ *                   d(i, j) = sqrt( sum_d ||A^d_i - B^d_j||^2 );
+ *                 self-join (B = NULL, pairs with |i - j| <= ez excluded)
+ *                 or AB-join (both directions, as mp_abjoin).
+ *   MP_MD_MULTI   Section 3.3.5 (multidimensional profiles, mSTOMP): per
+ *                 pair the z-normalised distance of each dimension, sorted
+ *                 ascending; the k-dimensional distance is the mean of the
+ *                 k smallest; P holds D profiles, k = 1 .. D, profile k at
+ *                 [(k-1)*l, k*l) (I alike).  Self-join only (the paper
+ *                 designs it for self-joins): MP_EUNSUPPORTED otherwise.
+ * Arithmetic: FP64 centred cross products and statistics; the candidate
+ * values that pick each minimum are rounded to float, and P is then
+ * recomputed in FP64 from the chosen pair (so P is exact for I; I can differ
+ * from the exact argmin only at near-ties within float resolution).
+ *   A, B   device, D*nA and D*nB values of `dtype`;  P, I, P_ba, I_ba as
+ *          above (P_ba / I_ba only for the AB-join)
+ *   ws     device scratch of mp_mdjoin_workspace(mode, D, nA, nB, m) bytes
+ *          (nB = 0 for a self-join)
+ * Enqueues kernels only.
+ */
+#define MP_MD_SIMPLE 0
+#define MP_MD_MULTI 1
+size_t mp_mdjoin_workspace(int32_t mode, int32_t D, int64_t nA, int64_t nB, int32_t m);
+mp_status mp_mdjoin(int32_t mode, int32_t D, const void *A, int64_t nA, const void *B, int64_t nB,
+                    int32_t m, int32_t ez, mp_dtype dtype, void *P, int64_t *I, void *P_ba,
+                    int64_t *I_ba, void *ws, size_t ws_bytes, void *stream);
+/* pairs a multidimensional join scores (nB = 0: self-join with zone ez) */
+int64_t mp_mdjoin_cells(int32_t D, int64_t nA, int64_t nB, int32_t m, int32_t ez);
+
 /* ------------------------------------------------- semantic segmentation
  * Section 3.4.2 (FLUSS, after Gharghabi et al. 2017): every window i and its
  * neighbour I[i] form an arc; the arc curve AC[x] counts the arcs with

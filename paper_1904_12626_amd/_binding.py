@@ -32,6 +32,7 @@ EXPORTS = (
     "mp_selfjoin_cells", "mp_abjoin_cells", "mp_timing_enable", "mp_timing_query",
     "mp_selfjoin_chunks", "mp_selfjoin_plan_create", "mp_anytime_order",
     "mp_fluss_workspace", "mp_fluss", "mp_chains_workspace", "mp_chains", "mp_abjoin_plan_create",
+    "mp_mdjoin_workspace", "mp_mdjoin", "mp_mdjoin_cells",
 )
 
 
@@ -84,6 +85,9 @@ def lib():
         "mp_selfjoin_plan_create": (ctypes.c_int, [i64, i32, i32, i32, op, i32, i64, vp, ctypes.POINTER(vp)]),
         "mp_anytime_order": (ctypes.c_int, [i64, ctypes.c_uint64, vp]),
         "mp_abjoin_plan_create": (ctypes.c_int, [i64, i64, i32, i32, op, ctypes.POINTER(vp)]),
+        "mp_mdjoin_workspace": (sz, [i32, i32, i64, i64, i32]),
+        "mp_mdjoin": (ctypes.c_int, [i32, i32, vp, i64, vp, i64, i32, i32, i32, vp, vp, vp, vp, vp, sz, vp]),
+        "mp_mdjoin_cells": (i64, [i32, i64, i64, i32, i32]),
         "mp_fluss_workspace": (sz, [i64]),
         "mp_fluss": (ctypes.c_int, [vp, i64, i64, i32, vp, vp, vp, sz, vp]),
         "mp_chains_workspace": (sz, [i64]),
@@ -387,6 +391,65 @@ def anytime_selfjoin(T: torch.Tensor, m: int, ez: Optional[int] = None, *, fract
     plan = SelfJoinPlan(T.numel(), m, ez, dtype=T.dtype, device=T.device, chunks=chunks, **opts)
     P, I = plan.run(T, stream=stream)
     return P, I, chunks
+
+
+MP_MD_SIMPLE, MP_MD_MULTI = 0, 1
+
+
+def _md_series(t: torch.Tensor, name: str) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dim() == 1:
+        t = t.unsqueeze(0)
+    if t.dim() != 2:
+        raise ValueError(f"{name} must be [D, n] (or 1-D)")
+    return t.contiguous()
+
+
+def mdjoin(A: torch.Tensor, m: int, ez: Optional[int] = None, B: Optional[torch.Tensor] = None, *,
+           mode: str = "simple", exclusion_zone_frac=Fraction(1, 2), stream=None):
+    """Multidimensional joins of [D, n] series (mp_mdjoin).
+    mode="simple": SiMPle (Section 3.3.4), raw Euclidean distance over all
+    dimensions; returns (P, I) for a self-join or (P_ab, I_ab, P_ba, I_ba)
+    with B.  mode="multi": the D multidimensional profiles of Section 3.3.5
+    (self-join), P and I of shape [D, l], row k-1 = k dimensions."""
+    A = _md_series(A, "A")
+    D, nA = A.shape
+    if mode not in ("simple", "multi"):
+        raise ValueError("mode must be 'simple' or 'multi'")
+    md = MP_MD_SIMPLE if mode == "simple" else MP_MD_MULTI
+    dt = _dtype_code(A)
+    L = lib()
+    lA = nA - m + 1
+    if B is None:
+        if ez is None:
+            ez = exclusion_zone(m, exclusion_zone_frac)
+        np_ = D if md == MP_MD_MULTI else 1
+        P = torch.empty(np_ * lA, dtype=A.dtype, device=A.device)
+        I = torch.empty(np_ * lA, dtype=torch.int64, device=A.device)
+        ws_bytes = int(L.mp_mdjoin_workspace(md, D, nA, 0, m))
+        if ws_bytes == 0:
+            raise MPError("mp_mdjoin_workspace", MP_EINVAL, "invalid arguments")
+        ws = torch.empty(ws_bytes, dtype=torch.uint8, device=A.device)
+        _check("mp_mdjoin", L.mp_mdjoin(md, D, _ptr(A), nA, None, 0, m, int(ez), dt, _ptr(P), _ptr(I), None, None,
+                                        _ptr(ws), ws_bytes, _stream(stream)))
+        if md == MP_MD_MULTI:
+            return P.view(D, lA), I.view(D, lA)
+        return P, I
+    B = _md_series(B, "B")
+    if B.shape[0] != D or B.dtype != A.dtype:
+        raise ValueError("A and B must have the same dimensions and dtype")
+    nB = B.shape[1]
+    lB = nB - m + 1
+    Pab = torch.empty(lA, dtype=A.dtype, device=A.device)
+    Iab = torch.empty(lA, dtype=torch.int64, device=A.device)
+    Pba = torch.empty(lB, dtype=A.dtype, device=A.device)
+    Iba = torch.empty(lB, dtype=torch.int64, device=A.device)
+    ws_bytes = int(L.mp_mdjoin_workspace(md, D, nA, nB, m))
+    ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=A.device)
+    _check("mp_mdjoin", L.mp_mdjoin(md, D, _ptr(A), nA, _ptr(B), nB, m, -1, dt, _ptr(Pab), _ptr(Iab), _ptr(Pba),
+                                    _ptr(Iba), _ptr(ws), ws_bytes, _stream(stream)))
+    return Pab, Iab, Pba, Iba
 
 
 def fluss(I: torch.Tensor, m: int, k: int = 2, zone: Optional[int] = None, stream=None):

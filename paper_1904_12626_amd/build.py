@@ -26,6 +26,7 @@ SOURCES = {
     "mp_backward.hip": [],
     "mp_scan.hip": [],
     "mp_mine.hip": [],
+    "mp_md.hip": [],
     "mp_abi.cpp": [],
 }
 

@@ -704,6 +704,138 @@ mp_status mp_backward(const mp_batch_plan *pl, const void *T_cat, const int64_t 
   return MP_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Multidimensional job: the self-join or AB-join descriptors of the
+// one-dimensional path with 64-diagonal strips; every dimension of a series
+// shares its windows.
+struct MdLayout {
+  size_t rec, uv, keys, segp, segs, counters, special, total;
+  int64_t stride;
+};
+
+mp_status build_md(int32_t mode, int32_t D, int64_t nA, int64_t nB, int64_t b_off, int32_t m,
+                   int32_t ez, bool self, mp_dtype dt, Job &j, MdLayout &L) {
+  if (dt != MP_F64 && dt != MP_F32) return MP_EINVAL;
+  if (mode != MP_MD_SIMPLE && mode != MP_MD_MULTI) return MP_EINVAL;
+  if (D < 1 || D > mpx::kMdMaxDims || m < 2 || nA < m) return MP_EINVAL;
+  if (self && ez < 0) return MP_EINVAL;
+  if (!self && nB < m) return MP_EINVAL;
+  if (!self && mode == MP_MD_MULTI) return MP_EUNSUPPORTED;
+  if (nA - m + 1 >= ((int64_t)1 << 31) || (!self && nB - m + 1 >= ((int64_t)1 << 31))) return MP_EINVAL;
+  j.t_f64 = dt == MP_F64;
+  if (self) {
+    add_series(j, 0, nA, m, ez, 0, 0);
+    add_sweep(j, 0, 0, 0, 0, (int64_t)ez + 1, nA - m);
+  } else {
+    add_series(j, 0, nA, m, -1, 1, 0);
+    add_series(j, b_off, nB, m, -1, 0, 1);
+    j.series[1].p_off = 0;
+    add_sweep(j, 0, 1, 0, 1, 0, nB - m);
+    add_sweep(j, 1, 0, 1, 0, 1, nA - m);
+  }
+  j.W = 64;
+  int R = 2048;
+  while (R > 64 && count_tiles(j, 64, R) < 8 * 1024) R /= 2;
+  j.R = R;
+  int64_t seg = 0;
+  j.cells = 0;
+  for (SweepDesc &d : j.sweeps) {
+    d.seg_base = seg;
+    d.nseg = (d.k_lo > d.k_hi) ? 0 : (d.k_hi - d.k_lo + 64) / 64;
+    seg += d.nseg;
+    j.cells += sweep_cells(j.series[d.rs].l, j.series[d.cs].l, d.k_lo, d.k_hi);
+  }
+  j.nseg = seg;
+  j.tiles = count_tiles(j, 64, R);
+  const int np = mode == MP_MD_MULTI ? D : 1;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align_up(o + bytes);
+    return at;
+  };
+  L.stride = j.total_rc;
+  L.rec = take(32 * (size_t)D * (size_t)j.total_rc);
+  L.uv = take(16 * (size_t)D * (size_t)j.total_rc);
+  L.keys = take(8 * (size_t)np * (size_t)j.total_l);
+  L.segp = take(8 * ((size_t)j.nseg + 1));
+  L.segs = take(4 * std::max<size_t>(1, (size_t)j.nseg));
+  L.counters = take(8 * 4);
+  L.special = take(4 * j.series.size());
+  L.total = o;
+  return MP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t mp_mdjoin_workspace(int32_t mode, int32_t D, int64_t nA, int64_t nB, int32_t m) {
+  Job j;
+  MdLayout L;
+  const bool self = nB <= 0;
+  if (build_md(mode, D, nA, nB, 0, m, 0, self, MP_F32, j, L) != MP_OK) return 0;
+  return L.total;
+}
+
+mp_status mp_mdjoin(int32_t mode, int32_t D, const void *A, int64_t nA, const void *B, int64_t nB,
+                    int32_t m, int32_t ez, mp_dtype dtype, void *P, int64_t *I, void *P_ba,
+                    int64_t *I_ba, void *ws, size_t ws_bytes, void *stream) {
+  const bool self = B == nullptr;
+  const size_t es = esize(dtype);
+  if (!A || !P || !I || !aligned(A, es) || !aligned(P, es) || !aligned(I, 8)) return MP_EINVAL;
+  int64_t b_off = 0;
+  if (!self) {
+    if (!P_ba || !I_ba || !aligned(B, es) || !aligned(P_ba, es) || !aligned(I_ba, 8)) return MP_EINVAL;
+    const int64_t diff = (int64_t)((intptr_t)B - (intptr_t)A);
+    if (diff % (int64_t)es != 0) return MP_EINVAL;
+    b_off = diff / (int64_t)es;
+  }
+  Job j;
+  MdLayout L;
+  mp_status s = build_md(mode, D, nA, nB, b_off, m, ez, self, dtype, j, L);
+  if (s != MP_OK) return s;
+  if ((s = check_ws(ws, ws_bytes, L.total)) != MP_OK) return s;
+  char *b = (char *)ws;
+  const mpx::Plan p = plan_of(j, Layout{}, ws, false);
+  mpx::Work w{};
+  w.seg_prefix = (int64_t *)(b + L.segp);
+  w.seg_sweep = (int32_t *)(b + L.segs);
+  w.counters = (unsigned long long *)(b + L.counters);
+  w.special = (int32_t *)(b + L.special);
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  if (g_timing.on) {
+    for (auto &e : ev) e = g_timing.get();
+    if (ev[0]) (void)hipEventRecord(ev[0], st);
+  }
+  if (mpx::launch_plan(p, w, 64, j.R, j.nseg, st) != hipSuccess) return MP_ELAUNCH;
+  mpx::Outputs o{};
+  o.P[0] = P;
+  o.I[0] = I;
+  o.P[1] = self ? nullptr : P_ba;
+  o.I[1] = self ? nullptr : I_ba;
+  const int grid = (int)std::min<int64_t>(std::max<int64_t>(j.tiles, 1), mpx::md_sweep_grid(mode, D));
+  if (mpx::launch_md(mode, D, p, A, dtype == MP_F64, b + L.rec, b + L.uv, L.stride, j.total_rc,
+                     (unsigned long long *)(b + L.keys), j.total_l, w.seg_prefix, w.seg_sweep, w.counters,
+                     j.R, j.tiles, j.nseg, grid, o, j.total_l, ev[1], ev[2], st) != hipSuccess)
+    return MP_ELAUNCH;
+  if (g_timing.on) {
+    if (ev[3]) (void)hipEventRecord(ev[3], st);
+    for (auto &e : ev) g_timing.rec.push_back(e);
+  }
+  return MP_OK;
+}
+
+int64_t mp_mdjoin_cells(int32_t D, int64_t nA, int64_t nB, int32_t m, int32_t ez) {
+  if (D < 1 || m < 2 || nA < m) return 0;
+  if (nB <= 0) return ez < 0 ? 0 : mp_selfjoin_cells(nA, m, ez);
+  return nB < m ? 0 : mp_abjoin_cells(nA, nB, m);
+}
+
 size_t mp_fluss_workspace(int64_t l) {
   if (l < 1 || l >= ((int64_t)1 << 31)) return 0;
   return align_up(8 * mpx::fluss_scratch_words(l));

@@ -156,6 +156,18 @@ size_t chains_scratch_words(int64_t l);
 hipError_t launch_chains(const int64_t *IL, const int64_t *IR, int64_t l, int64_t min_len, int64_t *next,
                          int64_t *length, int64_t *summary, int64_t *best, int64_t *ws, hipStream_t st);
 
+// Multidimensional joins (mp_md.hip): SiMPle (non-normalised, summed over
+// dimensions, one profile) and the multidimensional profiles (one per k).
+constexpr int kMdSimple = 0;
+constexpr int kMdMulti = 1;
+constexpr int kMdMaxDims = 8;
+hipError_t launch_md(int mode, int D, const Plan &plan, const void *T, bool t_f64, void *rec, void *uv,
+                     int64_t stride, int64_t total_rc, unsigned long long *keys, int64_t kstride,
+                     const int64_t *seg_prefix, const int32_t *seg_sweep, unsigned long long *counter, int R,
+                     int64_t total_tiles, int64_t nseg, int grid, const Outputs &o, int64_t total_l,
+                     hipEvent_t ev0, hipEvent_t ev1, hipStream_t st);
+int md_sweep_grid(int mode, int D);
+
 // Occupancy-derived persistent grid for the sweep kernel.
 int sweep_grid(bool f64_sweep, int slots);
 
