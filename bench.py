@@ -80,6 +80,15 @@ def workload(name: str, n_override=None):
         return dict(kind="lr", T=pw.T, m=256, ez=64, planted=pw,
                     desc=f"left/right profiles of the float32 random walk n={n} with 8 planted motif pairs and 4 "
                          f"discords, m=256, ez=64, then the corrected arc curve with 2 boundaries and the chains")
+    if name in ("md_simple", "md_multi"):
+        n = n_override or (1 << 18)
+        rng = np.random.default_rng(7)
+        T = np.cumsum(rng.standard_normal((3, n)), axis=1).astype(np.float32)
+        mode = "simple" if name == "md_simple" else "multi"
+        what = ("SiMPle self-join (raw Euclidean distance summed over the dimensions)" if mode == "simple"
+                else "multidimensional profiles (k = 1..3 of the sorted per-dimension z-normalised distances)")
+        return dict(kind="md", T=T, m=128, ez=32, mode=mode,
+                    desc=f"{what}, 3-dimensional float32 random walk n={n}, m=128, ez=32")
     if name == "selfjoin_small":
         T, m, ez = W.selfjoin_small()
         return dict(kind="self", T=T, m=m, ez=ez, planted=None,
@@ -108,7 +117,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="selfjoin_large",
                     choices=["selfjoin_large", "selfjoin_small", "abjoin_ecg", "batch_ragged", "diff_batch",
-                             "anytime", "left_right"])
+                             "anytime", "left_right", "md_simple", "md_multi"])
     ap.add_argument("--fraction", type=float, default=0.05, help="anytime workload: fraction of chunks timed")
     ap.add_argument("--n", type=int, default=None, help="override the series length")
     ap.add_argument("--slots", type=int, default=0, help="diagonals per lane (0 = automatic)")
@@ -199,6 +208,14 @@ def main():
             ch = mpx.chains(I[l:2 * l], I[2 * l:])
             return P, I, cac, seg, ch
         cells = mpx.selfjoin_cells(n, m, ez)
+    elif wl["kind"] == "md":
+        T, ez = wl["T"], wl["ez"]
+        Tg = torch.from_numpy(T).to(dev)
+        D, n = T.shape
+        cells = mpx.selfjoin_cells(n, m, ez)
+
+        def step(precision):
+            return mpx.mdjoin(Tg, m, ez, mode=wl["mode"])
     elif wl["kind"] == "ab":
         A, B = wl["A"], wl["B"]
         Ag, Bg = torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev)
@@ -324,6 +341,16 @@ def main():
         result["config"]["series"] = len(wl["rb"].series)
     if wl["kind"] == "diff":
         result["config"]["note"] = "value counts forward cells per second of forward+backward steps"
+    if wl["kind"] == "md":
+        # algorithmic VALU operations per cell of the multidimensional sweep
+        D = wl["T"].shape[0]
+        ops = 5 * D + 2 if wl["mode"] == "simple" else 6 * D + D * (D - 1) + 4 * D
+        ach = cells * ops / (sweep32 / 1e3) / 1e12
+        result["dtype"] = "f64"
+        result["config"]["workload"] = wl["desc"] + "; FP64 cross products, float candidate keys, FP64 recompute of P"
+        result["config"]["dims"] = D
+        result["roofline"].update({"achieved": ach, "frac": ach / (PEAK_LANE_OPS / 1e12), "kernel": "k_md_sweep",
+                                   "ops_per_cell": ops, "traffic": None})
     if wl["kind"] == "lr":
         ch = out32[4]
         result["config"]["longest_chain"] = len(ch["best"])
@@ -438,6 +465,29 @@ def main():
             "max_abs_dP_f32_vs_oracle": float(np.max(np.abs(out32[0].double().cpu().numpy()[rows] - Po))),
             "index_agreement": float(np.mean(out32[1].cpu().numpy()[rows] == Io)),
         }
+    if args.cpu_rows > 0 and wl["kind"] == "md":
+        from oracle import mp_oracle as O
+        T64 = wl["T"].astype(np.float64)
+        D, n = T64.shape
+        l = n - m + 1
+        rng = np.random.default_rng(0)
+        rows = np.sort(rng.choice(l, max(4, args.cpu_rows // 16), replace=False))
+        t0 = time.perf_counter()
+        if wl["mode"] == "simple":
+            Po, Io = O.simple_join(T64, m, ez, rows=rows)
+            Po, Io = Po[rows], Io[rows]
+            Pg = out32[0].double().cpu().numpy()[rows]
+        else:
+            Po, Io = O.mstomp(T64, m, ez, rows=rows)
+            Po, Io = Po[:, rows], Io[:, rows]
+            Pg = out32[0].double().cpu().numpy()[:, rows]
+        dt = time.perf_counter() - t0
+        pairs = int(sum(l - (min(l - 1, r + ez) - max(0, r - ez) + 1) for r in rows))
+        result["cpu_baseline"] = {
+            "value": pairs / dt, "unit": "cells/s", "cores": 1, "kind": "oracle",
+            "sample": f"{rows.size} full rows of the same join (numpy, {D} dimensions), {pairs} pairs, {dt:.1f} s"}
+        result["oracle_check"] = {"rows": int(rows.size),
+                                  "max_rel_dP_vs_oracle": float(np.max(np.abs(Pg - Po) / np.maximum(1.0, Po)))}
     if args.cpu_rows > 0 and wl["kind"] == "ab":
         from oracle import cimpl
         rng = np.random.default_rng(0)

@@ -573,10 +573,11 @@ def _md_windows(T, m):
     return W, valid
 
 
-def simple_join(TA, m: int, ez=None, TB=None):
+def simple_join(TA, m: int, ez=None, TB=None, rows=None):
     """SiMPle profile: P[i] = min_j sqrt(sum_d ||A_i^d - B_j^d||^2) over all
     dimensions, no z-normalisation (Section 3.3.4).  Self-join (TB None,
-    pairs with |i - j| <= ez excluded) or AB-join (no zone).  Brute force."""
+    pairs with |i - j| <= ez excluded) or AB-join (no zone).  Brute force;
+    `rows` limits the rows computed (entries of the others stay +inf / -1)."""
     WA, vA = _md_windows(TA, m)
     WB, vB = (WA, vA) if TB is None else _md_windows(TB, m)
     lA, lB = WA.shape[1], WB.shape[1]
@@ -585,7 +586,7 @@ def simple_join(TA, m: int, ez=None, TB=None):
     P = np.full(lA, np.inf)
     I = np.full(lA, -1, dtype=np.int64)
     jidx = np.arange(lB)
-    for i in range(lA):
+    for i in (range(lA) if rows is None else rows):
         if not vA[i]:
             continue
         diff = XB - XA[i]
@@ -597,12 +598,12 @@ def simple_join(TA, m: int, ez=None, TB=None):
     return P, I
 
 
-def mstomp(T, m: int, ez: int):
+def mstomp(T, m: int, ez: int, rows=None):
     """Multidimensional profiles (Section 3.3.5): for every pair the
     z-normalised distance of each dimension (constant windows normalise to
     zero), sorted ascending; the k-dimensional distance is the mean of the k
     smallest; P[k-1][i] = min over |i - j| > ez of it, k = 1 .. D.
-    Returns P, I of shape [D, l]."""
+    Returns P, I of shape [D, l] (`rows` limits the rows computed)."""
     W, valid = _md_windows(T, m)
     D, l, _ = W.shape
     Z = np.zeros_like(W)
@@ -615,7 +616,7 @@ def mstomp(T, m: int, ez: int):
     P = np.full((D, l), np.inf)
     I = np.full((D, l), -1, dtype=np.int64)
     jidx = np.arange(l)
-    for i in range(l):
+    for i in (range(l) if rows is None else rows):
         if not valid[i]:
             continue
         dist = np.sqrt(((Z - Z[:, i:i + 1, :]) ** 2).sum(axis=2))   # [D, l]
