@@ -250,6 +250,33 @@ mp_status mp_mdjoin(int32_t mode, int32_t D, const void *A, int64_t nA, const vo
 /* pairs a multidimensional join scores (nB = 0: self-join with zone ez) */
 int64_t mp_mdjoin_cells(int32_t D, int64_t nA, int64_t nB, int32_t m, int32_t ez);
 
+/* ---------------------------------------------------------------- streaming
+ * Section 2: once computed, the join can be updated incrementally, so an
+ * exact join can be kept on streaming data (the paper gives no algorithm).
+ * The caller keeps a growing series in T (capacity n_max samples) and the
+ * profile in P, I (capacity n_max - m + 1 entries); the library keeps FP64
+ * state in the workspace.  mp_stream_init computes the self-join of the
+ * first n samples (the FP64 sweep) and the state.  After the caller has
+ * written samples n_old .. n_new-1 into T (ordered before the call on
+ * `stream`), mp_stream_append extends P, I to the n_new - m + 1 windows so
+ * that they equal the self-join of T[0, n_new): each new window gets its
+ * nearest admissible earlier window, and every earlier window whose new
+ * candidate is strictly closer takes it (on equal distances the older,
+ * smaller index stays).  FP64: the cross products of each new window
+ * continue those of its predecessor along every diagonal (O(l) per window,
+ * re-seeded by direct dot products every 1024 windows); one small launch
+ * pair per new window.  m, ez, n_max and the workspace must stay the same
+ * for the life of the stream; nothing else may write the workspace.
+ *   ws   device scratch of mp_stream_workspace(n_max, m) bytes
+ */
+size_t mp_stream_workspace(int64_t n_max, int32_t m);
+mp_status mp_stream_init(const void *T, int64_t n, int64_t n_max, int32_t m, int32_t ez,
+                         mp_dtype dtype, void *P, int64_t *I, void *ws, size_t ws_bytes,
+                         void *stream);
+mp_status mp_stream_append(const void *T, int64_t n_old, int64_t n_new, int64_t n_max, int32_t m,
+                           int32_t ez, mp_dtype dtype, void *P, int64_t *I, void *ws,
+                           size_t ws_bytes, void *stream);
+
 /* ------------------------------------------------- semantic segmentation
  * Section 3.4.2 (FLUSS, after Gharghabi et al. 2017): every window i and its
  * neighbour I[i] form an arc; the arc curve AC[x] counts the arcs with

@@ -16,10 +16,11 @@ package computes it with hand-written HIP kernels behind a C ABI
     ch = mpx.chains(IL, IR)                       # Section 3.4.3 chains
     P, I = mpx.mdjoin(T_multi, m, ez, mode="simple")  # Section 3.3.4 SiMPle
     P, I = mpx.mdjoin(T_multi, m, ez, mode="multi")   # Section 3.3.5 k-dim profiles
+    s = mpx.SelfJoinStream(T, m, ez, n_max=N); s.append(x)  # incremental (Section 2)
 """
 
 from ._binding import (  # noqa: F401
-    EXPORTS, LIB_PATH, MPError, ABJoinPlan, BatchPlan, SelfJoinPlan, abjoin, abjoin_cells, anytime_order, chains, fluss,
+    EXPORTS, LIB_PATH, MPError, ABJoinPlan, BatchPlan, SelfJoinPlan, SelfJoinStream, abjoin, abjoin_cells, anytime_order, chains, fluss,
     anytime_selfjoin, exclusion_zone, left_right_profiles, lib, make_options, mdjoin, recheck, selfjoin,
     selfjoin_cells, selfjoin_chunks, timing_enable, timing_query,
 )
@@ -29,5 +30,5 @@ __all__ = [
     "selfjoin", "abjoin", "BatchPlan", "recheck", "MatrixProfileFn", "matrix_profile",
     "exclusion_zone", "selfjoin_cells", "abjoin_cells", "MPError", "lib", "SelfJoinPlan",
     "selfjoin_chunks", "anytime_order", "anytime_selfjoin", "left_right_profiles", "fluss", "chains",
-    "ABJoinPlan", "abjoin_profile", "mdjoin",
+    "ABJoinPlan", "abjoin_profile", "mdjoin", "SelfJoinStream",
 ]

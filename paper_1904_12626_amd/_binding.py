@@ -33,6 +33,7 @@ EXPORTS = (
     "mp_selfjoin_chunks", "mp_selfjoin_plan_create", "mp_anytime_order",
     "mp_fluss_workspace", "mp_fluss", "mp_chains_workspace", "mp_chains", "mp_abjoin_plan_create",
     "mp_mdjoin_workspace", "mp_mdjoin", "mp_mdjoin_cells",
+    "mp_stream_workspace", "mp_stream_init", "mp_stream_append",
 )
 
 
@@ -88,6 +89,9 @@ def lib():
         "mp_mdjoin_workspace": (sz, [i32, i32, i64, i64, i32]),
         "mp_mdjoin": (ctypes.c_int, [i32, i32, vp, i64, vp, i64, i32, i32, i32, vp, vp, vp, vp, vp, sz, vp]),
         "mp_mdjoin_cells": (i64, [i32, i64, i64, i32, i32]),
+        "mp_stream_workspace": (sz, [i64, i32]),
+        "mp_stream_init": (ctypes.c_int, [vp, i64, i64, i32, i32, i32, vp, vp, vp, sz, vp]),
+        "mp_stream_append": (ctypes.c_int, [vp, i64, i64, i64, i32, i32, i32, vp, vp, vp, sz, vp]),
         "mp_fluss_workspace": (sz, [i64]),
         "mp_fluss": (ctypes.c_int, [vp, i64, i64, i32, vp, vp, vp, sz, vp]),
         "mp_chains_workspace": (sz, [i64]),
@@ -391,6 +395,57 @@ def anytime_selfjoin(T: torch.Tensor, m: int, ez: Optional[int] = None, *, fract
     plan = SelfJoinPlan(T.numel(), m, ez, dtype=T.dtype, device=T.device, chunks=chunks, **opts)
     P, I = plan.run(T, stream=stream)
     return P, I, chunks
+
+
+class SelfJoinStream:
+    """Incrementally updated self-join (mp_stream_init / mp_stream_append):
+    the profile of everything appended so far, exact (FP64 state).
+    `append(x)` adds samples; `P`, `I` are views of the current profile."""
+
+    def __init__(self, T: torch.Tensor, m: int, ez: Optional[int] = None, *, n_max: int,
+                 exclusion_zone_frac=Fraction(1, 2), stream=None):
+        T = _series(T, "T")
+        self.m = int(m)
+        self.ez = exclusion_zone(m, exclusion_zone_frac) if ez is None else int(ez)
+        self.n_max = int(n_max)
+        self.dtype = T.dtype
+        self.n = T.numel()
+        if self.n > self.n_max:
+            raise ValueError("initial series longer than n_max")
+        L = lib()
+        dev = T.device
+        self.T = torch.empty(self.n_max, dtype=T.dtype, device=dev)
+        self.T[:self.n].copy_(T)
+        lmax = self.n_max - self.m + 1
+        self._P = torch.empty(lmax, dtype=T.dtype, device=dev)
+        self._I = torch.empty(lmax, dtype=torch.int64, device=dev)
+        self.ws_bytes = int(L.mp_stream_workspace(self.n_max, self.m))
+        if self.ws_bytes == 0:
+            raise MPError("mp_stream_workspace", MP_EINVAL, "invalid arguments")
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=dev)
+        _check("mp_stream_init", L.mp_stream_init(_ptr(self.T), self.n, self.n_max, self.m, self.ez,
+                                                  _dtype_code(T), _ptr(self._P), _ptr(self._I), _ptr(self.ws),
+                                                  self.ws_bytes, _stream(stream)))
+
+    def append(self, x: torch.Tensor, stream=None):
+        x = x.reshape(-1).to(self.T.device, self.dtype)
+        k = x.numel()
+        if self.n + k > self.n_max:
+            raise ValueError("stream capacity n_max exceeded")
+        self.T[self.n:self.n + k].copy_(x)
+        _check("mp_stream_append", lib().mp_stream_append(_ptr(self.T), self.n, self.n + k, self.n_max, self.m,
+                                                          self.ez, _dtype_code(self.T), _ptr(self._P),
+                                                          _ptr(self._I), _ptr(self.ws), self.ws_bytes,
+                                                          _stream(stream)))
+        self.n += k
+
+    @property
+    def P(self):
+        return self._P[:self.n - self.m + 1]
+
+    @property
+    def I(self):
+        return self._I[:self.n - self.m + 1]
 
 
 MP_MD_SIMPLE, MP_MD_MULTI = 0, 1

@@ -27,6 +27,7 @@ SOURCES = {
     "mp_scan.hip": [],
     "mp_mine.hip": [],
     "mp_md.hip": [],
+    "mp_stream.hip": [],
     "mp_abi.cpp": [],
 }
 

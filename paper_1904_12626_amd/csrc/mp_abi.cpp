@@ -830,6 +830,119 @@ mp_status mp_mdjoin(int32_t mode, int32_t D, const void *A, int64_t nA, const vo
   return MP_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Stream workspace: the FP64 state for l_max windows, then the workspace of
+// the initial FP64 self-join of up to n_max samples.
+struct StreamLayout {
+  size_t mu, isd, flags, a, g, pd, c0, c1, pdp, pjp, join, total;
+};
+
+StreamLayout stream_layout(int64_t n_max, int32_t m) {
+  StreamLayout L{};
+  const size_t lm = (size_t)(n_max - m + 1), np = (size_t)mpx::stream_partials((int64_t)lm);
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align_up(o + bytes);
+    return at;
+  };
+  L.mu = take(8 * lm);
+  L.isd = take(8 * lm);
+  L.flags = take(lm);
+  L.a = take(8 * lm);
+  L.g = take(8 * lm);
+  L.pd = take(8 * lm);
+  L.c0 = take(8 * lm);
+  L.c1 = take(8 * lm);
+  L.pdp = take(8 * np);
+  L.pjp = take(8 * np);
+  L.join = o;
+  mp_options f64opt{MP_PREC_F64, 0, 0, (int32_t)MP_FLAG_FP64_FINALIZE};
+  Job j;
+  if (build_selfjoin(n_max, m, 0, MP_F64, &f64opt, j) == MP_OK) o += layout_of(j, false).total;
+  L.total = align_up(o);
+  return L;
+}
+
+mpx::StreamWork stream_work(const StreamLayout &L, void *ws) {
+  char *b = (char *)ws;
+  mpx::StreamWork s{};
+  s.mu = (double *)(b + L.mu);
+  s.isd = (double *)(b + L.isd);
+  s.flags = (uint8_t *)(b + L.flags);
+  s.a = (double *)(b + L.a);
+  s.g = (double *)(b + L.g);
+  s.Pd = (double *)(b + L.pd);
+  s.C[0] = (double *)(b + L.c0);
+  s.C[1] = (double *)(b + L.c1);
+  s.part_d = (double *)(b + L.pdp);
+  s.part_j = (int64_t *)(b + L.pjp);
+  return s;
+}
+
+constexpr int kStreamReseed = 1024;
+
+}  // namespace
+
+extern "C" {
+
+size_t mp_stream_workspace(int64_t n_max, int32_t m) {
+  if (m < 2 || n_max < m || n_max - m + 1 >= ((int64_t)1 << 31)) return 0;
+  return stream_layout(n_max, m).total;
+}
+
+mp_status mp_stream_init(const void *T, int64_t n, int64_t n_max, int32_t m, int32_t ez, mp_dtype dtype,
+                         void *P, int64_t *I, void *ws, size_t ws_bytes, void *stream) {
+  if (dtype != MP_F64 && dtype != MP_F32) return MP_EINVAL;
+  if (m < 2 || ez < 0 || n < m || n > n_max || n_max - m + 1 >= ((int64_t)1 << 31)) return MP_EINVAL;
+  const size_t es = esize(dtype);
+  if (!T || !P || !I || !aligned(T, es) || !aligned(P, es) || !aligned(I, 8)) return MP_EINVAL;
+  const StreamLayout L = stream_layout(n_max, m);
+  mp_status s = check_ws(ws, ws_bytes, L.total);
+  if (s != MP_OK) return s;
+  // the initial profile: the FP64 self-join of the first n samples
+  mp_options f64opt{MP_PREC_F64, 0, 0, (int32_t)MP_FLAG_FP64_FINALIZE};
+  Job j;
+  if ((s = build_selfjoin(n, m, ez, dtype, &f64opt, j)) != MP_OK) return s;
+  const Layout JL = layout_of(j, false);
+  if (L.join + JL.total > L.total) return MP_EWORKSPACE;
+  void *jws = (char *)ws + L.join;
+  const mpx::Work w = work_of(JL, jws);
+  const mpx::Plan p = plan_of(j, JL, jws, false);
+  mpx::Outputs o{};
+  o.P[0] = P;
+  o.I[0] = I;
+  hipStream_t st = (hipStream_t)stream;
+  if ((s = run_job(j, p, w, T, o, dtype == MP_F64, st)) != MP_OK) return s;
+  if (mpx::launch_stream_init(stream_work(L, ws), T, dtype == MP_F64, n, m, ez, I, st) != hipSuccess)
+    return MP_ELAUNCH;
+  return MP_OK;
+}
+
+mp_status mp_stream_append(const void *T, int64_t n_old, int64_t n_new, int64_t n_max, int32_t m, int32_t ez,
+                           mp_dtype dtype, void *P, int64_t *I, void *ws, size_t ws_bytes, void *stream) {
+  if (dtype != MP_F64 && dtype != MP_F32) return MP_EINVAL;
+  if (m < 2 || ez < 0 || n_old < m || n_new < n_old || n_new > n_max ||
+      n_max - m + 1 >= ((int64_t)1 << 31))
+    return MP_EINVAL;
+  const size_t es = esize(dtype);
+  if (!T || !P || !I || !aligned(T, es) || !aligned(P, es) || !aligned(I, 8)) return MP_EINVAL;
+  const StreamLayout L = stream_layout(n_max, m);
+  mp_status s = check_ws(ws, ws_bytes, L.total);
+  if (s != MP_OK) return s;
+  if (n_new == n_old) return MP_OK;
+  hipStream_t st = (hipStream_t)stream;
+  const mpx::StreamWork sw = stream_work(L, ws);
+  if (mpx::launch_stream_append(sw, T, dtype == MP_F64, n_old, n_new, m, ez, kStreamReseed, I, st) !=
+      hipSuccess)
+    return MP_ELAUNCH;
+  if (mpx::launch_stream_out(sw, n_new - m + 1, P, dtype == MP_F64, st) != hipSuccess) return MP_ELAUNCH;
+  return MP_OK;
+}
+
 int64_t mp_mdjoin_cells(int32_t D, int64_t nA, int64_t nB, int32_t m, int32_t ez) {
   if (D < 1 || m < 2 || nA < m) return 0;
   if (nB <= 0) return ez < 0 ? 0 : mp_selfjoin_cells(nA, m, ez);

@@ -168,6 +168,24 @@ hipError_t launch_md(int mode, int D, const Plan &plan, const void *T, bool t_f6
                      hipEvent_t ev0, hipEvent_t ev1, hipStream_t st);
 int md_sweep_grid(int mode, int D);
 
+// Incremental self-join state (mp_stream.hip), sized for l_max windows.
+struct StreamWork {
+  double *mu;        // [l_max] window mean
+  double *isd;       // [l_max] 1/(sqrt(m) sigma), 0 for constant or invalid windows
+  uint8_t *flags;    // [l_max] bit0 valid, bit1 constant
+  double *a, *g;     // [l_max] recurrence terms (a needs the window's successor sample)
+  double *Pd;        // [l_max] FP64 profile
+  double *C[2];      // [l_max] cross products of the newest window (window w in C[w % 2])
+  double *part_d;    // [ceil(l_max / 256)] per-block row minima
+  int64_t *part_j;
+};
+int64_t stream_partials(int64_t l_max);
+hipError_t launch_stream_init(const StreamWork &s, const void *T, bool t_f64, int64_t n, int m, int ez,
+                              const int64_t *I, hipStream_t st);
+hipError_t launch_stream_append(const StreamWork &s, const void *T, bool t_f64, int64_t n_old, int64_t n_new,
+                                int m, int ez, int reseed, int64_t *I, hipStream_t st);
+hipError_t launch_stream_out(const StreamWork &s, int64_t l, void *P, bool out_f64, hipStream_t st);
+
 // Occupancy-derived persistent grid for the sweep kernel.
 int sweep_grid(bool f64_sweep, int slots);
 
