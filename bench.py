@@ -80,6 +80,12 @@ def workload(name: str, n_override=None):
         return dict(kind="lr", T=pw.T, m=256, ez=64, planted=pw,
                     desc=f"left/right profiles of the float32 random walk n={n} with 8 planted motif pairs and 4 "
                          f"discords, m=256, ez=64, then the corrected arc curve with 2 boundaries and the chains")
+    if name == "stream":
+        n = n_override or (1 << 20)
+        pw = W.planted_walk(n, 256, 2)
+        return dict(kind="stream", T=pw.T, m=256, ez=64,
+                    desc=f"incremental self-join: the profile of the first {n - 8192} samples of the float32 planted "
+                         f"walk (n={n}, m=256, ez=64), then the last 8192 samples appended 512 at a time")
     if name in ("md_simple", "md_multi"):
         n = n_override or (1 << 18)
         rng = np.random.default_rng(7)
@@ -117,7 +123,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="selfjoin_large",
                     choices=["selfjoin_large", "selfjoin_small", "abjoin_ecg", "batch_ragged", "diff_batch",
-                             "anytime", "left_right", "md_simple", "md_multi"])
+                             "anytime", "left_right", "md_simple", "md_multi", "stream"])
     ap.add_argument("--fraction", type=float, default=0.05, help="anytime workload: fraction of chunks timed")
     ap.add_argument("--n", type=int, default=None, help="override the series length")
     ap.add_argument("--slots", type=int, default=0, help="diagonals per lane (0 = automatic)")
@@ -208,6 +214,26 @@ def main():
             ch = mpx.chains(I[l:2 * l], I[2 * l:])
             return P, I, cac, seg, ch
         cells = mpx.selfjoin_cells(n, m, ez)
+    elif wl["kind"] == "stream":
+        T, ez = wl["T"], wl["ez"]
+        n = T.size
+        n0 = n - 8192
+        Tg = torch.from_numpy(T).to(dev)
+        l0 = n0 - m + 1
+        # pairs scored by the appends: every new window against its admissible earlier windows
+        cells = sum(max(0, w - ez) for w in range(l0, n - m + 1))
+        state = {}
+
+        def step(precision):
+            st = mpx.SelfJoinStream(Tg[:n0], m, ez, n_max=n)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for b in range(n0, n, 512):
+                st.append(Tg[b:b + 512])
+            torch.cuda.synchronize()
+            state["append_ms"] = (time.perf_counter() - t0) * 1e3
+            state["last"] = st
+            return st.P, st.I
     elif wl["kind"] == "md":
         T, ez = wl["T"], wl["ez"]
         Tg = torch.from_numpy(T).to(dev)
@@ -284,6 +310,45 @@ def main():
         return out, (t1 - t0) * 1e3 / steps, sweep_ms / max(calls, 1), total_ms / max(calls, 1)
 
     log(f"[bench] workload: {wl['desc']}; cells={cells}")
+    if wl["kind"] == "stream":
+        for _ in range(args.warmup):
+            step("f64")
+        times = []
+        for _ in range(args.steps):
+            out = step("f64")
+            times.append(state["append_ms"])
+        ms = float(np.median(times))
+        st = state["last"]
+        l = n - m + 1
+        result = {
+            "metric": METRIC, "value": cells / (ms / 1e3), "unit": "cells/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": wl["desc"] + "; FP64 state, one row update per new window",
+                       "cells": cells, "windows_appended": 8192, "appended_windows_per_s": 8192 / (ms / 1e3)},
+            # per scored pair the row kernel reads C(w-1, j-1), a, g, 1/sigma and the profile of j and
+            # writes C(w, j): 5 + 1 doubles and one flag byte = 49 bytes
+            "roofline": {"bound": "hbm", "achieved": cells * 49 / (ms / 1e3) / 1e9, "peak": 8000.0, "unit": "GB/s",
+                         "frac": cells * 49 / (ms / 1e3) / 1e9 / 8000.0, "traffic": None, "kernel": "k_stream_row",
+                         "bytes_per_cell": 49, "note": "two launches per appended window"},
+        }
+        if args.cpu_rows > 0:
+            from oracle import cimpl
+            rng = np.random.default_rng(0)
+            rows = np.sort(rng.choice(l, 64, replace=False))
+            T64 = T.astype(np.float64)
+            t0 = time.perf_counter()
+            Po, Io = cimpl.selfjoin_rows(T64, m, ez, rows)
+            dt = time.perf_counter() - t0
+            pairs = int(sum(l - (min(l - 1, r + ez) - max(0, r - ez) + 1) for r in rows))
+            Pg = st.P.double().cpu().numpy()[rows]
+            result["cpu_baseline"] = {"value": pairs / dt, "unit": "cells/s", "cores": cimpl.max_threads(),
+                                      "kind": "oracle",
+                                      "sample": f"{rows.size} full rows of the grown series' self-join, {pairs} pairs, "
+                                                f"{dt:.1f} s"}
+            result["oracle_check"] = {"rows": int(rows.size), "max_abs_dP_vs_oracle": float(np.max(np.abs(Pg - Po)))}
+        print(json.dumps(result), flush=True)
+        return
     out32, ms32, sweep32, tot32 = timed("f32", args.steps, args.warmup)
     log(f"[bench] f32: {ms32:.2f} ms/step, sweep {sweep32:.2f} ms, launch sequence {tot32:.2f} ms")
     value = cells / (ms32 / 1e3)
