@@ -49,12 +49,15 @@ def measured_traffic():
     source has changed since they were taken."""
     import hashlib
     rec = os.path.join(ROOT, "profiles", "k_sweep_f32_traffic.json")
-    src = os.path.join(ROOT, "paper_1904_12626_amd", "csrc", "mp_sweep.hip")
+    csrc = os.path.join(ROOT, "paper_1904_12626_amd", "csrc")
     try:
         with open(rec) as f:
             r = json.load(f)
-        with open(src, "rb") as f:
-            h = hashlib.sha256(f.read()).hexdigest()
+        h = hashlib.sha256()
+        for name in ("mp_sweep.hip", "mp_internal.h", "mp_types.h"):   # the kernel and what it includes
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(f.read())
+        h = h.hexdigest()
     except OSError:
         return None
     return r["traffic_bytes_per_launch"] if r.get("sweep_source_sha256") == h else None
