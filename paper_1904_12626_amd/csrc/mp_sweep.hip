@@ -406,7 +406,7 @@ int sweep_grid(bool f64_sweep, int slots) {
   int per = 0;
   hipError_t e;
   if (f64_sweep)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_sweep<double, float, 8, 16>, 64, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_sweep<double, float, 8, 32>, 64, 0);
   else if (slots == 8)
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_sweep<float, float, 8, 32>, 64, 0);
   else if (slots == 12)
@@ -427,8 +427,8 @@ hipError_t launch_sweep(const Plan &plan, const Work &w, const void *T, bool t_f
                      (const int64_t *)w.seg_prefix, (const int32_t *)w.seg_sweep, plan.s_ext,   \
                      plan.w_ext, w.keys, w.counters, (const TIN *)T, R, total_tiles, nseg)
   if (f64_sweep) {
-    if (t_f64) MPX_LAUNCH(double, double, 8, 16);
-    else MPX_LAUNCH(double, float, 8, 16);
+    if (t_f64) MPX_LAUNCH(double, double, 8, 32);
+    else MPX_LAUNCH(double, float, 8, 32);
   } else if (slots == 8) {
     if (t_f64) MPX_LAUNCH(float, double, 8, 32);
     else MPX_LAUNCH(float, float, 8, 32);
