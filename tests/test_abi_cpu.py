@@ -166,3 +166,43 @@ def test_anytime_order_is_a_seeded_permutation():
     assert a == B.anytime_order(1000, 7)
     assert a != B.anytime_order(1000, 8)
     assert B.anytime_order(0, 1) == []
+
+
+def test_new_entry_points_reject_bad_arguments():
+    lib = B.lib()
+    ok = ctypes.c_void_p(1 << 20)
+    # multidimensional joins: D out of range, window too long, AB form of the k-dim profiles
+    assert lib.mp_mdjoin_workspace(B.MP_MD_SIMPLE, 9, 1000, 0, 16) == 0
+    assert lib.mp_mdjoin_workspace(B.MP_MD_SIMPLE, 0, 1000, 0, 16) == 0
+    assert lib.mp_mdjoin_workspace(B.MP_MD_SIMPLE, 3, 10, 0, 16) == 0
+    assert lib.mp_mdjoin_workspace(B.MP_MD_MULTI, 3, 1000, 0, 16) > 0
+    assert lib.mp_mdjoin(B.MP_MD_MULTI, 3, ok, 1000, ctypes.c_void_p((1 << 20) + 4096), 1000, 16, 4, B.MP_F32,
+                         ok, ok, ok, ok, ok, 1 << 30, None) == B.MP_EUNSUPPORTED
+    assert lib.mp_mdjoin(7, 3, ok, 1000, None, 0, 16, 4, B.MP_F32, ok, ok, None, None, ok, 1 << 30,
+                         None) == B.MP_EINVAL
+    assert lib.mp_mdjoin_cells(3, 4096, 0, 64, 16) == B.selfjoin_cells(4096, 64, 16)
+    assert lib.mp_mdjoin_cells(2, 1000, 900, 32, 0) == B.abjoin_cells(1000, 900, 32)
+    # segmentation and chains
+    assert lib.mp_fluss(ok, 1000, 10, 65, ok, ok, ok, 1 << 30, None) == B.MP_EINVAL
+    assert lib.mp_fluss(ok, 1000, -1, 2, ok, ok, ok, 1 << 30, None) == B.MP_EINVAL
+    assert lib.mp_fluss(ok, 1000, 10, 2, ok, None, ok, 1 << 30, None) == B.MP_EINVAL
+    assert lib.mp_fluss(ok, 1000, 10, 2, ok, ok, ok, 8, None) == B.MP_EWORKSPACE
+    assert lib.mp_chains(ok, ok, 1000, 0, ok, ok, ok, ok, ok, 1 << 30, None) == B.MP_EINVAL
+    assert lib.mp_chains(ok, None, 1000, 3, ok, ok, ok, ok, ok, 1 << 30, None) == B.MP_EINVAL
+    # streaming: capacity, order of sizes, workspace
+    assert lib.mp_stream_workspace(100, 200) == 0
+    assert lib.mp_stream_workspace(5000, 64) > 0
+    assert lib.mp_stream_init(ok, 6000, 5000, 64, 16, B.MP_F32, ok, ok, ok, 1 << 30, None) == B.MP_EINVAL
+    assert lib.mp_stream_append(ok, 3000, 2000, 5000, 64, 16, B.MP_F32, ok, ok, ok, 1 << 30, None) == B.MP_EINVAL
+    assert lib.mp_stream_append(ok, 3000, 6000, 5000, 64, 16, B.MP_F32, ok, ok, ok, 1 << 30, None) == B.MP_EINVAL
+    assert lib.mp_stream_append(ok, 3000, 3100, 5000, 64, 16, B.MP_F32, ok, ok, ok, 64, None) == B.MP_EWORKSPACE
+    # plans: AB plan sizes, left/right plans refuse the backward
+    h = ctypes.c_void_p()
+    assert lib.mp_abjoin_plan_create(1000, 900, 32, B.MP_F32, None, ctypes.byref(h)) == 0
+    assert lib.mp_batch_plan_profile_length(h) == (1000 - 31) + (900 - 31)
+    assert lib.mp_batch_plan_cells(h) == B.abjoin_cells(1000, 900, 32)
+    lib.mp_batch_plan_destroy(h)
+    assert lib.mp_abjoin_plan_create(10, 900, 32, B.MP_F32, None, ctypes.byref(h)) == B.MP_EINVAL
+    assert lib.mp_selfjoin_plan_create(4096, 64, 16, B.MP_F32, None, 1, 0, None, ctypes.byref(h)) == 0
+    assert lib.mp_backward(h, ok, ok, ok, ok, ok, 1 << 40, None) == B.MP_EUNSUPPORTED
+    lib.mp_batch_plan_destroy(h)

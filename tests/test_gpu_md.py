@@ -101,3 +101,34 @@ def test_degenerate_windows_and_planted_motif():
     Ps, Is = [x.cpu().numpy() for x in mpx.mdjoin(torch.from_numpy(T).to(DEV), m, ez, mode="simple")]
     Po, Io = O.simple_join(T, m, ez)
     _compare(Ps, Is, Po, Io, lambda i, j: _simple_dist(T, i, T, j, m), 1e-6, ez, "simple")
+
+
+@pytest.mark.parametrize("mode", ["simple", "multi"])
+def test_eight_dimensions(mode):
+    """The largest supported dimension count."""
+    import paper_1904_12626_amd as mpx
+    rng = np.random.default_rng(180)
+    D, n, m, ez = 8, 700, 16, 4
+    T = np.cumsum(rng.standard_normal((D, n)), axis=1)
+    P, I = [x.cpu().numpy() for x in mpx.mdjoin(torch.from_numpy(T).to(DEV), m, ez, mode=mode)]
+    if mode == "simple":
+        Po, Io = O.simple_join(T, m, ez)
+        _compare(P, I, Po, Io, lambda i, j: _simple_dist(T, i, T, j, m), 1e-6, ez, "simple D=8")
+    else:
+        Po, Io = O.mstomp(T, m, ez)
+        for k in (0, 3, 7):
+            _compare(P[k], I[k], Po[k], Io[k], lambda i, j, k=k: _multi_dist(T, i, j, m, k + 1), 1e-6, ez, f"k={k + 1}")
+
+
+def test_simple_abjoin_float32_and_short_series():
+    import paper_1904_12626_amd as mpx
+    rng = np.random.default_rng(181)
+    A = np.cumsum(rng.standard_normal((2, 300)), axis=1).astype(np.float32)
+    B = np.cumsum(rng.standard_normal((2, 40)), axis=1).astype(np.float32)   # lB = 9: one partial strip
+    m = 32
+    out = [x.cpu().numpy() for x in mpx.mdjoin(torch.from_numpy(A).to(DEV), m, B=torch.from_numpy(B).to(DEV))]
+    A64, B64 = A.astype(np.float64), B.astype(np.float64)
+    Po, Io = O.simple_join(A64, m, TB=B64)
+    _compare(out[0], out[1], Po, Io, lambda i, j: _simple_dist(A64, i, B64, j, m), 1e-6, where="ab")
+    Po, Io = O.simple_join(B64, m, TB=A64)
+    _compare(out[2], out[3], Po, Io, lambda i, j: _simple_dist(B64, i, A64, j, m), 1e-6, where="ba")
