@@ -327,13 +327,15 @@ def main():
             "metric": METRIC, "value": cells / (ms / 1e3), "unit": "cells/s", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-            "config": {"workload": wl["desc"] + "; FP64 state, one row update per new window",
+            "config": {"workload": wl["desc"] + "; FP64 state, new windows in batches of up to 63",
                        "cells": cells, "windows_appended": 8192, "appended_windows_per_s": 8192 / (ms / 1e3)},
-            # per scored pair the row kernel reads C(w-1, j-1), a, g, 1/sigma and the profile of j and
-            # writes C(w, j): 5 + 1 doubles and one flag byte = 49 bytes
-            "roofline": {"bound": "hbm", "achieved": cells * 49 / (ms / 1e3) / 1e9, "peak": 8000.0, "unit": "GB/s",
-                         "frac": cells * 49 / (ms / 1e3) / 1e9 / 8000.0, "traffic": None, "kernel": "k_stream_row",
-                         "bytes_per_cell": 49, "note": "two launches per appended window"},
+            # a batch of up to 63 new windows reads each column's terms once, so the scored pairs
+            # cost FP64 arithmetic: 2 FMA (cross product), MUL + FMA + MAX (key), the column
+            # compare and the row minimum = 7 operations
+            "roofline": {"bound": "alu", "achieved": cells * 7 / (ms / 1e3) / 1e12, "peak": PEAK_LANE_OPS / 1e12,
+                         "unit": "TOP/s", "frac": cells * 7 / (ms / 1e3) / 1e12 / (PEAK_LANE_OPS / 1e12),
+                         "traffic": None, "kernel": "k_stream_batch", "ops_per_cell": 7,
+                         "note": "three launches and 63 workgroup barriers per batch of 63 windows"},
         }
         if args.cpu_rows > 0:
             from oracle import cimpl

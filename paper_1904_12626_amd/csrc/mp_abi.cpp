@@ -837,7 +837,7 @@ namespace {
 // Stream workspace: the FP64 state for l_max windows, then the workspace of
 // the initial FP64 self-join of up to n_max samples.
 struct StreamLayout {
-  size_t mu, isd, flags, a, g, pd, c0, c1, pdp, pjp, join, total;
+  size_t mu, isd, flags, a, g, pd, c0, c1, pdp, pjp, col0, join, total;
 };
 
 StreamLayout stream_layout(int64_t n_max, int32_t m) {
@@ -859,6 +859,7 @@ StreamLayout stream_layout(int64_t n_max, int32_t m) {
   L.c1 = take(8 * lm);
   L.pdp = take(8 * np);
   L.pjp = take(8 * np);
+  L.col0 = take(8 * 64);
   L.join = o;
   mp_options f64opt{MP_PREC_F64, 0, 0, (int32_t)MP_FLAG_FP64_FINALIZE};
   Job j;
@@ -880,6 +881,7 @@ mpx::StreamWork stream_work(const StreamLayout &L, void *ws) {
   s.C[1] = (double *)(b + L.c1);
   s.part_d = (double *)(b + L.pdp);
   s.part_j = (int64_t *)(b + L.pjp);
+  s.col0 = (double *)(b + L.col0);
   return s;
 }
 
@@ -939,7 +941,7 @@ mp_status mp_stream_append(const void *T, int64_t n_old, int64_t n_new, int64_t 
   if (mpx::launch_stream_append(sw, T, dtype == MP_F64, n_old, n_new, m, ez, kStreamReseed, I, st) !=
       hipSuccess)
     return MP_ELAUNCH;
-  if (mpx::launch_stream_out(sw, n_new - m + 1, P, dtype == MP_F64, st) != hipSuccess) return MP_ELAUNCH;
+  if (mpx::launch_stream_out(sw, n_new - m + 1, m, P, dtype == MP_F64, st) != hipSuccess) return MP_ELAUNCH;
   return MP_OK;
 }
 

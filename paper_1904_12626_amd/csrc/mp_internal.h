@@ -174,17 +174,18 @@ struct StreamWork {
   double *isd;       // [l_max] 1/(sqrt(m) sigma), 0 for constant or invalid windows
   uint8_t *flags;    // [l_max] bit0 valid, bit1 constant
   double *a, *g;     // [l_max] recurrence terms (a needs the window's successor sample)
-  double *Pd;        // [l_max] FP64 profile
+  double *Pd;        // [l_max] FP64 profile as keys d^2 / (2m)
   double *C[2];      // [l_max] cross products of the newest window (window w in C[w % 2])
-  double *part_d;    // [ceil(l_max / 256)] per-block row minima
+  double *part_d;    // per-wave row minima of a batch
   int64_t *part_j;
+  double *col0;      // [64] C(w, 0) of the windows of a batch
 };
 int64_t stream_partials(int64_t l_max);
 hipError_t launch_stream_init(const StreamWork &s, const void *T, bool t_f64, int64_t n, int m, int ez,
                               const int64_t *I, hipStream_t st);
 hipError_t launch_stream_append(const StreamWork &s, const void *T, bool t_f64, int64_t n_old, int64_t n_new,
                                 int m, int ez, int reseed, int64_t *I, hipStream_t st);
-hipError_t launch_stream_out(const StreamWork &s, int64_t l, void *P, bool out_f64, hipStream_t st);
+hipError_t launch_stream_out(const StreamWork &s, int64_t l, int m, void *P, bool out_f64, hipStream_t st);
 
 // Occupancy-derived persistent grid for the sweep kernel.
 int sweep_grid(bool f64_sweep, int slots);
