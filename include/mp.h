@@ -264,9 +264,10 @@ int64_t mp_mdjoin_cells(int32_t D, int64_t nA, int64_t nB, int32_t m, int32_t ez
  * candidate is strictly closer takes it (on equal distances the older,
  * smaller index stays).  FP64: the cross products of each new window
  * continue those of its predecessor along every diagonal (O(l) per window,
- * re-seeded by direct dot products every 1024 windows); one small launch
- * pair per new window.  m, ez, n_max and the workspace must stay the same
- * for the life of the stream; nothing else may write the workspace.
+ * re-seeded by direct dot products every 1024 windows); new windows are
+ * processed up to min(63, ez + 1) per launch.  m, ez, n_max and the
+ * workspace must stay the same for the life of the stream; nothing else may
+ * write the workspace.
  *   ws   device scratch of mp_stream_workspace(n_max, m) bytes
  */
 size_t mp_stream_workspace(int64_t n_max, int32_t m);
