@@ -712,7 +712,7 @@ namespace {
 // one-dimensional path with 64-diagonal strips; every dimension of a series
 // shares its windows.
 struct MdLayout {
-  size_t rec, uv, keys, segp, segs, counters, special, total;
+  size_t rec, mu2, keys, segp, segs, counters, special, total;
   int64_t stride;
 };
 
@@ -759,7 +759,7 @@ mp_status build_md(int32_t mode, int32_t D, int64_t nA, int64_t nB, int64_t b_of
   };
   L.stride = j.total_rc;
   L.rec = take(32 * (size_t)D * (size_t)j.total_rc);
-  L.uv = take(16 * (size_t)D * (size_t)j.total_rc);
+  L.mu2 = take(16 * (size_t)D * (size_t)j.total_rc);
   L.keys = take(8 * (size_t)np * (size_t)j.total_l);
   L.segp = take(8 * ((size_t)j.nseg + 1));
   L.segs = take(4 * std::max<size_t>(1, (size_t)j.nseg));
@@ -819,7 +819,7 @@ mp_status mp_mdjoin(int32_t mode, int32_t D, const void *A, int64_t nA, const vo
   o.P[1] = self ? nullptr : P_ba;
   o.I[1] = self ? nullptr : I_ba;
   const int grid = (int)std::min<int64_t>(std::max<int64_t>(j.tiles, 1), mpx::md_sweep_grid(mode, D));
-  if (mpx::launch_md(mode, D, p, A, dtype == MP_F64, b + L.rec, b + L.uv, L.stride, j.total_rc,
+  if (mpx::launch_md(mode, D, p, A, dtype == MP_F64, b + L.rec, b + L.mu2, L.stride, j.total_rc,
                      (unsigned long long *)(b + L.keys), j.total_l, w.seg_prefix, w.seg_sweep, w.counters,
                      j.R, j.tiles, j.nseg, grid, o, j.total_l, ev[1], ev[2], st) != hipSuccess)
     return MP_ELAUNCH;

@@ -161,7 +161,7 @@ hipError_t launch_chains(const int64_t *IL, const int64_t *IR, int64_t l, int64_
 constexpr int kMdSimple = 0;
 constexpr int kMdMulti = 1;
 constexpr int kMdMaxDims = 8;
-hipError_t launch_md(int mode, int D, const Plan &plan, const void *T, bool t_f64, void *rec, void *uv,
+hipError_t launch_md(int mode, int D, const Plan &plan, const void *T, bool t_f64, void *rec, void *mu2,
                      int64_t stride, int64_t total_rc, unsigned long long *keys, int64_t kstride,
                      const int64_t *seg_prefix, const int32_t *seg_sweep, unsigned long long *counter, int R,
                      int64_t total_tiles, int64_t nseg, int grid, const Outputs &o, int64_t total_l,

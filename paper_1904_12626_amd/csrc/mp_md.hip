@@ -238,7 +238,7 @@ __global__ void __launch_bounds__(64) k_md_sweep(const Plan plan, const Tin *__r
       __syncthreads();
       const int rn = __builtin_amdgcn_readfirstlane((int)min((int64_t)64, nr - rb));
       for (int r = 0; r < rn; ++r) {
-        const int64_t i = i0 + rb + r, j = i + k0 + lane;
+        const int64_t i = i0 + rb + r;
         const int64_t ri_off = uni(rrow + rb + r);
         float val[NP];
         if (MODE == kMdSimple) {
@@ -294,11 +294,13 @@ __global__ void __launch_bounds__(64) k_md_sweep(const Plan plan, const Tin *__r
       }
     }
     // columns still in flight: lane L holds column i0 + nr + k0 + L
+    const int64_t c = i0 + nr + k0 + lane;
+    unsigned long long *cdst = ckeys + c;
+    for (int p = 0; p < NP; ++p) {  // CM is read through a copy so that it stays in registers
+      unsigned long long v = CM[0];
 #pragma unroll
-    for (int p = 0; p < NP; ++p) {
-      const int64_t c = i0 + nr + k0 + lane;
-      if (c < lc && CM[p] != ~0ull && (float)__uint_as_float((unsigned)(CM[p] >> 32)) < 1.0e30f)
-        atomicMin(ckeys + p * kstride + c, CM[p]);
+      for (int q = 1; q < NP; ++q) v = q == p ? CM[q] : v;
+      if (c < lc && v != ~0ull && __uint_as_float((unsigned)(v >> 32)) < 1.0e30f) atomicMin(cdst + p * kstride, v);
     }
   }
 }
@@ -406,13 +408,13 @@ hipError_t launch_md_fin_t(int D, const Plan &plan, const Tin *T, const Double4 
   return hipGetLastError();
 }
 
-hipError_t launch_md(int mode, int D, const Plan &plan, const void *T, bool t_f64, void *rec, void *uv,
+hipError_t launch_md(int mode, int D, const Plan &plan, const void *T, bool t_f64, void *rec, void *mu2,
                      int64_t stride, int64_t total_rc, unsigned long long *keys, int64_t kstride,
                      const int64_t *seg_prefix, const int32_t *seg_sweep, unsigned long long *counter, int R,
                      int64_t total_tiles, int64_t nseg, int grid, const Outputs &o, int64_t total_l,
                      hipEvent_t ev0, hipEvent_t ev1, hipStream_t st) {
   Double4 *rc = (Double4 *)rec;
-  double2 *u2 = (double2 *)uv;
+  double2 *u2 = (double2 *)mu2;
   hipError_t e;
   if (t_f64) {
     const double *Tb = (const double *)T;
