@@ -169,8 +169,21 @@ __global__ void __launch_bounds__(256) k_bwd_window(BwdWork b, int64_t total_l) 
   if (w >= total_l) return;
   const bool own = b.nbr[w] >= 0;
   double s = own ? b.coef[4 * w] : 0.0;
-  for (int64_t p = b.off[w] + (own ? 1 : 0), e = b.off[w + 1]; p < e; ++p) s += b.erec[p].gam;
+  const int64_t e = b.off[w + 1];
+  for (int64_t p = b.off[w] + (own ? 1 : 0); p < e; ++p) s += b.erec[p].gam;
   b.wrec[w] = BwdWin{s * b.isig[w], b.mu[w]};
+  // from here on each edge carries its destination window instead of gamma
+  for (int64_t p = b.off[w]; p < e; ++p) b.erec[p].gam = __longlong_as_double((long long)w);
+}
+
+// Lane k's value, wave-uniform (k is uniform).
+__device__ __forceinline__ int64_t lane_i(int64_t v, int k) {
+  const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, k);
+  const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)((uint64_t)v >> 32), k);
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ double lane_d(double v, int k) {
+  return __longlong_as_double(lane_i(__double_as_longlong(v), k));
 }
 
 __device__ __forceinline__ int64_t uni64(int64_t v) {
@@ -210,22 +223,58 @@ __global__ void __launch_bounds__(256) k_bwd_gather(Plan plan, BwdWork b, const 
   const BwdWin *__restrict__ wrec = b.wrec;
   const BwdEdge *__restrict__ erec = b.erec;
   const int64_t *__restrict__ off = b.off;
+  const int lane = threadIdx.x & 63;
   double acc = 0.0;
-  int64_t e0 = off[lo_w];
-  for (int64_t d = lo_w; d <= hi_w; ++d) {
-    const BwdWin wr = wrec[d];
-    const int64_t e1 = off[d + 1];
-    const bool in = d >= lo_t && d <= hi_t;
-    if (in) {
+  // Records are fetched 64 at a time, one per lane (coalesced, all in
+  // flight together), and handed to the whole wave with lane reads.
+  // First the multiples of each covering window's own z ...
+  for (int64_t c = lo_w; c <= hi_w; c += 64) {
+    double sc_l = 0.0, mu_l = 0.0;
+    if (c + lane <= hi_w) {
+      const BwdWin wr = wrec[c + lane];
+      sc_l = wr.sc;
+      mu_l = wr.mu;
+    }
+    const int cnt = (int)min((int64_t)64, hi_w - c + 1);
+    for (int k = 0; k < cnt; ++k) {
+      const double sc = lane_d(sc_l, k), mu = lane_d(mu_l, k);
+      const int64_t d = c + k;
       // sc is 0 for windows without gradient, including non-finite ones
       // whose samples must not reach the sum
-      if (wr.sc != 0.0) acc = fma(wr.sc, xt - wr.mu, acc);
-      for (int64_t p = e0; p < e1; ++p) {
-        const BwdEdge q = erec[p];
-        acc = fma(q.c, (double)xp[q.delta] - q.mu, acc);
-      }
+      if (d >= lo_t && d <= hi_t && sc != 0.0) acc = fma(sc, xt - mu, acc);
     }
-    e0 = e1;
+  }
+  // ... then the edges of the covering windows, one flat run of the edge
+  // array (each edge carries its destination window).  Eight edges per
+  // step: their sample loads are issued together (a lane outside an edge's
+  // window loads its own sample instead, so every load stays in bounds) and
+  // summed afterwards in edge order.  Fetch slots past the run read as
+  // window -1, which no lane covers.
+  const int64_t eb = uni64(off[lo_w]), ee = uni64(off[hi_w + 1]);
+  for (int64_t c = eb; c < ee; c += 64) {
+    double qc = 0.0, qmu = 0.0;
+    int64_t qdelta = 0, qdst = -1;
+    if (c + lane < ee) {
+      const BwdEdge q = erec[c + lane];
+      qc = q.c;
+      qmu = q.mu;
+      qdelta = q.delta;
+      qdst = __double_as_longlong(q.gam);
+    }
+    const int cnt = ((int)min((int64_t)64, ee - c) + 7) & ~7;
+    for (int k = 0; k < cnt; k += 8) {
+      double v[8];
+      bool in[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int64_t d = lane_i(qdst, k + u);
+        in[u] = d >= lo_t && d <= hi_t;
+        v[u] = (double)xp[in[u] ? lane_i(qdelta, k + u) : 0];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (in[u]) acc = fma(lane_d(qc, k + u), v[u] - lane_d(qmu, k + u), acc);
+    }
   }
   if (act) gT[x] = (Tg)acc;
 }

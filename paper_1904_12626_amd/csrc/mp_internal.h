@@ -95,7 +95,8 @@ struct BwdEdge {
   double c;      // coefficient on (x[t + delta] - mu)
   double mu;     // mean of the source window
   int64_t delta; // source window start - destination window start (samples)
-  double gam;    // (bucket edges) the row's multiple of the destination z
+  double gam;    // (bucket edges) the row's multiple of the destination z; after
+                 // the per-window sums, the destination window (int64 bits)
 };
 struct BwdWin {
   double sc;     // summed multiple of this window's z, times 1/sigma
