@@ -736,20 +736,21 @@ mp_status build_md(int32_t mode, int32_t D, int64_t nA, int64_t nB, int64_t b_of
     add_sweep(j, 0, 1, 0, 1, 0, nB - m);
     add_sweep(j, 1, 0, 1, 0, 1, nA - m);
   }
-  j.W = 64;
+  const int W = mpx::md_strip_width(mode, D);
+  j.W = W;
   int R = 2048;
-  while (R > 64 && count_tiles(j, 64, R) < 8 * 1024) R /= 2;
+  while (R > 64 && count_tiles(j, W, R) < 8 * 1024) R /= 2;
   j.R = R;
   int64_t seg = 0;
   j.cells = 0;
   for (SweepDesc &d : j.sweeps) {
     d.seg_base = seg;
-    d.nseg = (d.k_lo > d.k_hi) ? 0 : (d.k_hi - d.k_lo + 64) / 64;
+    d.nseg = (d.k_lo > d.k_hi) ? 0 : (d.k_hi - d.k_lo + W) / W;
     seg += d.nseg;
     j.cells += sweep_cells(j.series[d.rs].l, j.series[d.cs].l, d.k_lo, d.k_hi);
   }
   j.nseg = seg;
-  j.tiles = count_tiles(j, 64, R);
+  j.tiles = count_tiles(j, W, R);
   const int np = mode == MP_MD_MULTI ? D : 1;
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -812,7 +813,7 @@ mp_status mp_mdjoin(int32_t mode, int32_t D, const void *A, int64_t nA, const vo
     for (auto &e : ev) e = g_timing.get();
     if (ev[0]) (void)hipEventRecord(ev[0], st);
   }
-  if (mpx::launch_plan(p, w, 64, j.R, j.nseg, st) != hipSuccess) return MP_ELAUNCH;
+  if (mpx::launch_plan(p, w, j.W, j.R, j.nseg, st) != hipSuccess) return MP_ELAUNCH;
   mpx::Outputs o{};
   o.P[0] = P;
   o.I[0] = I;

@@ -168,6 +168,8 @@ hipError_t launch_md(int mode, int D, const Plan &plan, const void *T, bool t_f6
                      int64_t total_tiles, int64_t nseg, int grid, const Outputs &o, int64_t total_l,
                      hipEvent_t ev0, hipEvent_t ev1, hipStream_t st);
 int md_sweep_grid(int mode, int D);
+// Diagonals per strip of the multidimensional sweep (64 times its slots).
+int md_strip_width(int mode, int D);
 
 // Incremental self-join state (mp_stream.hip), sized for l_max windows.
 struct StreamWork {

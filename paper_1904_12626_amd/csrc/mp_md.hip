@@ -5,18 +5,24 @@
 // dimensions sampled together, stored dimension-major: dimension d of a
 // series of n samples starts d*n values after its first sample.
 //
-// Same diagonal order as the one-dimensional sweep (tiles of R rows of a
-// strip of 64 diagonals, one wave per tile, persistent grid), with a simpler
-// register layout: lane L owns diagonal k0 + L, so at row i it scores the
-// cell (i, i + k0 + L).  Per dimension the centred cross product C advances
-// with C += a_j g_i + a_i g_j in FP64 (seeded in FP64 at the tile's first
-// row); column records are loaded per lane (consecutive lanes, consecutive
-// columns), row records are wave-uniform.  Every cell yields one value per
-// output profile, packed as (float value bits << 32 | partner index); row
-// minima are wave reductions, column minima travel one lane down per row
-// and leave through lane 0, and both merge into global words with a 64-bit
-// atomic minimum (order independent: deterministic).
+// Same diagonal order as the one-dimensional sweep: tiles of R rows of a
+// strip of W = 64*DT diagonals, one wave per tile, persistent grid; lane L
+// owns the DT diagonals k0 + L*DT + t, so at row i it scores the cells
+// (i, i + k0 + L*DT + t).  Per dimension the centred cross product C
+// advances with C += a_j g_i + a_i g_j in FP64 (seeded in FP64 at the tile's
+// first row).  Row records are wave-uniform scalar loads; column records
+// live in registers and rotate: slot t at row i+1 holds the column slot t+1
+// held at row i, the last slot takes lane L+1's first through a DPP wave
+// shift, and lane 63 takes the one new column of the row.  Every cell yields
+// one FP64 key per output profile with the cell's diagonal in its low bits,
+// so one FP64 minimum gives both the row's and the column's partner.  Column
+// minima travel with their column and leave the strip through lane 0; row
+// minima pass through LDS; both merge into global (float value << 32 |
+// partner) words with a 64-bit atomic minimum (order independent:
+// deterministic).
 #include <cmath>
+#include <type_traits>
+#include <utility>
 
 #include "mp_internal.h"
 #include "mp_types.h"
@@ -88,14 +94,14 @@ __device__ __forceinline__ int find_series_md(const Plan &plan, int64_t wi) {
 
 // Per window and dimension two records.  rec = {a, g, c, e} with
 // a = x[w+m] - x[w], g = x[w] - mu + a (m-1)/(2m) (the cross-product
-// recurrence) and, for SiMPle, c = mu and e = Q = sum_d m sigma_d^2 (kept in
-// dimension 0); for the multidimensional profiles c = s = 1/(sqrt(m) sigma)
-// (0 for a constant dimension) and e = v, the column term of
-// key = u_i + v_j - C s_i s_j, which is d^2/(2m) for every mix of constant
-// and varying windows (u = 1 - c/2, v = -c/2, c = 1 for a constant
-// dimension).  mu = {mean, u}.  A window with a non-finite sample in any
-// dimension gets Q = u = v = huge; so do the 64 padding records after each
-// series (and a = g = 0 there).
+// recurrence) and, for SiMPle, c = sqrt(m) mu and e = Q = sum_d m sigma_d^2
+// (kept in dimension 0); for the multidimensional profiles c = s =
+// sqrt(2)/sigma (0 for a constant dimension) and e = v, the column term of
+// key = u_i + v_j - C s_i s_j, which is the squared z-normalised distance for
+// every mix of constant and varying windows (u = 2m and v = 0 for a varying
+// dimension, u = m and v = -m for a constant one).  mu = {mean, u}.  A window with a non-finite sample in any dimension
+// gets Q = u = v = huge; so do the padding records after each series (and
+// a = g = 0 there).
 template <typename Tin, int MODE>
 __global__ void __launch_bounds__(256) k_md_stats(Plan plan, int D, const Tin *__restrict__ Tb, Double4 *rec,
                                                   double2 *mu2, int64_t stride, int64_t total_rc) {
@@ -138,11 +144,11 @@ __global__ void __launch_bounds__(256) k_md_stats(Plan plan, int D, const Tin *_
     const double sg = sqrt(q / m);
     Q += q;
     if (MODE == kMdSimple) {
-      rec[d * stride + r] = Double4{a, g, mu, 0.0};
+      rec[d * stride + r] = Double4{a, g, sqrt((double)m) * mu, 0.0};
       mu2[d * stride + r] = make_double2(mu, 0.0);
     } else {
-      rec[d * stride + r] = Double4{a, g, cst ? 0.0 : 1.0 / (sqrt((double)m) * sg), cst ? -0.5 : 0.0};
-      mu2[d * stride + r] = make_double2(mu, cst ? 0.5 : 1.0);
+      rec[d * stride + r] = Double4{a, g, cst ? 0.0 : sqrt(2.0) / sg, cst ? -(double)m : 0.0};
+      mu2[d * stride + r] = make_double2(mu, cst ? (double)m : 2.0 * m);
     }
   }
   if (MODE == kMdSimple) rec[r].w = ok ? Q : kHuge;
@@ -158,19 +164,118 @@ __global__ void __launch_bounds__(256) k_md_clear(unsigned long long *keys, int6
     keys[x] = ~0ull;
 }
 
-// Sorting network (odd-even transposition) on N floats, ascending.
+// Sorting network (odd-even transposition), ascending, on the bit patterns
+// of non-negative floats (+inf included), whose integer order is their order
+// as floats.
 template <int N>
-__device__ __forceinline__ void sort_net(float (&v)[N]) {
+__device__ __forceinline__ void sort_net(unsigned (&v)[N]) {
 #pragma unroll
   for (int p = 0; p < N; ++p) {
 #pragma unroll
     for (int i = (p & 1); i + 1 < N; i += 2) {
-      const float a = v[i], b = v[i + 1];
-      v[i] = fminf(a, b);
-      v[i + 1] = fmaxf(a, b);
+      const unsigned a = v[i], b = v[i + 1];
+      v[i] = min(a, b);
+      v[i + 1] = max(a, b);
     }
   }
 }
+
+// FP64 minimum of two keys.  Keys are never NaN, so the plain instruction is
+// exact; written out so that no NaN-quieting step is added to the integer-built
+// operands.
+__device__ __forceinline__ double kmin_f64(double a, double b) {
+  double r;
+  asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+
+// Wave shift with lane 63 keeping `in63` (the DPP source of lane 63 is out of
+// range, so that lane is not written): one DPP move per dword.
+__device__ __forceinline__ double md_shl_in(double in63, double v) {
+  const long long b = __double_as_longlong(v), f = __double_as_longlong(in63);
+  const int lo = __builtin_amdgcn_update_dpp((int)(f & 0xffffffffll), (int)(b & 0xffffffffll), 0x130, 0xF, 0xF,
+                                             false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(f >> 32), (int)(b >> 32), 0x130, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Tile shape of the multidimensional sweep for a mode and dimension count.
+// Per slot a lane keeps its column's records (SiMPle: a, g, sqrt(m) mu per
+// dimension and Q; k-dimensional: a, g, s, v per dimension), the cross
+// product of every dimension and one running column minimum per output; DT
+// (a power of two) is the largest slot count whose state fits about 176
+// registers.  TP rows pass between two LDS reductions of the row minima.
+template <int D, int MODE>
+struct MdShape {
+  static constexpr int NP = MODE == kMdMulti ? D : 1;
+  static constexpr int kSlotRegs = MODE == kMdSimple ? 8 * D + 4 : 12 * D;
+  static constexpr int kFit = 176 / kSlotRegs;
+  static constexpr int DT = kFit >= 8 ? 8 : (kFit >= 4 ? 4 : (kFit >= 2 ? 2 : 1));
+  static constexpr int TP = NP == 1 ? 16 : (NP <= 3 ? 8 : 4);
+  static constexpr int W = 64 * DT;
+  // doubles of one column record set: SiMPle a, g, z per dimension and Q;
+  // k-dimensional a, g, s, v per dimension
+  static constexpr int NF = MODE == kMdSimple ? 3 * D + 1 : 4 * D;
+  // entering-column doubles each lane prefetches for the next row block
+  static constexpr int NPF = (TP * NF + 63) / 64;
+  static_assert(TP % DT == 0 && 64 % TP == 0, "row blocks");
+};
+
+constexpr int md_code_bits(int w) { return w <= 1 ? 1 : 1 + md_code_bits((w + 1) / 2); }
+
+// In-place wave shift of a double: lane L takes lane L+1's value, lane 63
+// takes `fill` (wave-uniform).
+__device__ __forceinline__ int md_shl1(int v, int fill) {
+  int x = __builtin_amdgcn_update_dpp(v, v, 0x130 /* wave_shl:1 */, 0xF, 0xF, false);
+  fill = __builtin_amdgcn_readfirstlane(fill);
+  asm volatile("v_writelane_b32 %0, %1, 63" : "+v"(x) : "s"(fill));
+  return x;
+}
+__device__ __forceinline__ double md_shl1d(double v, double fill) {
+  const long long b = __double_as_longlong(v), f = __double_as_longlong(fill);
+  const int lo = md_shl1((int)(b & 0xffffffffll), (int)(f & 0xffffffffll));
+  const int hi = md_shl1((int)(b >> 32), (int)(f >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <typename Fn, int... Ts>
+__device__ __forceinline__ void md_for_impl(Fn &&f, std::integer_sequence<int, Ts...>) {
+  (f(std::integral_constant<int, Ts>{}), ...);
+}
+template <int N, typename Fn>
+__device__ __forceinline__ void md_for(Fn &&f) {
+  md_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// Keys are doubles whose low bits carry the cell's diagonal inside the strip
+// (its code), so one FP64 minimum serves the row (partner i + k0 + code) and
+// the column (partner j - k0 - code).  SiMPle keys are the squared distance
+// with its lowest mantissa bits replaced; k-dimensional keys are the bit
+// pattern (float value << 32 | code), whose order as doubles is the order of
+// the float values (+inf included: its pattern is a finite double).  Every
+// value is kept at or above a small normal number so that no key is a
+// denormal.
+template <int CB>
+struct MdKey {
+  static constexpr unsigned kMask = (1u << CB) - 1u;
+  static __device__ __forceinline__ double from_f64(double v, unsigned code) {
+    const long long b = __double_as_longlong(v);
+    const unsigned lo = ((unsigned)(b & 0xffffffffll) & ~kMask) | code;
+    return __longlong_as_double((b & ~0xffffffffll) | lo);
+  }
+  static __device__ __forceinline__ double from_f32(float v, unsigned code) {
+    return __longlong_as_double((long long)(((unsigned long long)__float_as_uint(v) << 32) | code));
+  }
+  static __device__ __forceinline__ unsigned code(double k) {
+    return (unsigned)(__double_as_longlong(k) & 0xffffffffll) & kMask;
+  }
+  // the value as the float that goes into the global packed minimum
+  static __device__ __forceinline__ float value(double k, bool f32) {
+    const long long b = __double_as_longlong(k);
+    if (f32) return __uint_as_float((unsigned)((unsigned long long)b >> 32));
+    return (float)__longlong_as_double(b & ~(long long)kMask);
+  }
+};
 
 template <typename Tin, int D, int MODE>
 __global__ void __launch_bounds__(64) k_md_sweep(const Plan plan, const Tin *__restrict__ Tb,
@@ -181,10 +286,23 @@ __global__ void __launch_bounds__(64) k_md_sweep(const Plan plan, const Tin *__r
                                                  unsigned long long *__restrict__ keys, int64_t kstride,
                                                  unsigned long long *__restrict__ counter, int R,
                                                  int64_t total_tiles, int64_t nseg) {
-  constexpr int NP = (MODE == kMdMulti) ? D : 1;
-  // column records of the 127 columns that 64 rows x 64 diagonals touch
-  __shared__ Double4 lcol[D][128];
+  using Sh = MdShape<D, MODE>;
+  constexpr int NP = Sh::NP, DT = Sh::DT, TP = Sh::TP, W = Sh::W, NF = Sh::NF, NPF = Sh::NPF;
+  constexpr int CB = md_code_bits(W);
+  constexpr bool kSimple = MODE == kMdSimple;
+  using K = MdKey<CB>;
+  const double kBig = 1.0e300;  // above every key: an empty minimum
+
+  __shared__ double lrow[NP][TP][65];  // per row, each lane's minimum over its slots
+  __shared__ double lcol[NP][TP];      // column minima leaving the strip through lane 0
+  __shared__ double lpart[NP][64];     // partial row minima of the reduction
+  __shared__ double lfresh[TP][NF];    // records of the columns entering at lane 63
+
   const int lane = threadIdx.x;
+  unsigned codes[DT];
+#pragma unroll
+  for (int t = 0; t < DT; ++t) codes[t] = (unsigned)(lane * DT + t);
+
   for (;;) {
     int64_t tile = 0;
     if (lane == 0) tile = (int64_t)atomicAdd(counter, 1ull);
@@ -198,110 +316,244 @@ __global__ void __launch_bounds__(64) k_md_sweep(const Plan plan, const Tin *__r
     const int64_t g = uni(lo);
     const SweepDesc sd = plan.sweep(seg_sweep[g]);
     const SeriesDesc RS = plan.series(sd.rs), CS = plan.series(sd.cs);
-    const int64_t k0 = uni(sd.k_lo + (g - sd.seg_base) * 64);
+    const int64_t k0 = uni(sd.k_lo + (g - sd.seg_base) * (int64_t)W);
     const int64_t L = min(RS.l, CS.l - k0);
     const int64_t i0 = uni((tile - seg_prefix[g]) * (int64_t)R);
     const int64_t nr = uni(min((int64_t)R, L - i0));
+    // rows past nr up to a multiple of TP are scored too: they are rows of
+    // the next tile (scored twice, harmless for a minimum) or padding
+    // records, whose keys are huge
+    const int64_t nsteps = uni(((nr + TP - 1) / TP) * TP);
     const int64_t lc = CS.l;
     const int m = RS.m;
-    const int64_t rrow = uni(RS.rc_off + i0);  // record of the tile's first row
+    const int64_t rrow = uni(RS.rc_off + i0);        // record of the tile's first row
+    const int64_t newc = uni(CS.rc_off + i0 + k0 + W);  // column entering lane 63 after that row
     unsigned long long *rkeys = keys + plan.series(sd.rk).w_off;
     unsigned long long *ckeys = keys + plan.series(sd.ck).w_off;
-    const int64_t j0 = i0 + k0 + lane;  // this lane's column at the tile's first row
+    const int64_t c0 = i0 + k0 + (int64_t)lane * DT;  // slot 0's column at row i0
 
-    // FP64 seeds: C_d = sum_u (x_r - mu_r)(x_c - mu_c)
-    double C[D];
-    for (int d = 0; d < D; ++d) {
-      double acc = 0.0;
-      if (j0 < lc) {
-        const Tin *xr = Tb + RS.t_off + (int64_t)d * RS.n + i0;
-        const Tin *xc = Tb + CS.t_off + (int64_t)d * CS.n + j0;
-        const double mr = mu2[d * stride + RS.rc_off + i0].x, mc = mu2[d * stride + CS.rc_off + j0].x;
-        for (int u = 0; u < m; ++u)
-          acc = fma(clean_md((double)xr[u]) - mr, clean_md((double)xc[u]) - mc, acc);
-      }
-      C[d] = acc;
-    }
-    unsigned long long CM[NP];
+    // ---- FP64 seeds at row i0, per dimension a sliding product: column
+    // sample c0+v meets row sample v-t in slot t;
+    // C = sum (x_r - mu_r) x_c - mu_c sum (x_r - mu_r)
+    double C[DT][D];
 #pragma unroll
-    for (int p = 0; p < NP; ++p) CM[p] = ~0ull;
+    for (int d = 0; d < D; ++d) {
+      const Tin *__restrict__ Tr = Tb + RS.t_off + (int64_t)d * RS.n + i0;
+      const Tin *__restrict__ Tc = Tb + CS.t_off + (int64_t)d * CS.n;
+      const double mur = ldu_md(&mu2[d * stride + rrow].x);
+      double acc[DT], xr[DT];
+#pragma unroll
+      for (int t = 0; t < DT; ++t) { acc[t] = 0.0; xr[t] = 0.0; }
+      double Sx = 0.0;
+      const int vend = m + DT - 1;
+      for (int vb = 0; vb < vend; vb += DT) {
+#pragma unroll
+        for (int u = 0; u < DT; ++u) {
+          const int v = vb + u;
+          double xn = 0.0;
+          if (v < m) xn = clean_md((double)Tr[v]) - mur;
+          Sx += xn;
+          xr[u] = xn;
+          const int64_t ci = c0 + v;
+          const double y = ci < CS.n ? clean_md((double)Tc[ci]) : 0.0;
+#pragma unroll
+          for (int t = 0; t < DT; ++t) acc[t] = fma(xr[(u - t + DT) % DT], y, acc[t]);
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < DT; ++t) {
+        const int64_t cw = min(c0 + t, lc - 1);
+        C[t][d] = acc[t] - mu2[d * stride + CS.rc_off + cw].x * Sx;
+      }
+    }
 
-    for (int64_t rb = 0; rb < nr; rb += 64) {
-      // stage the columns of rows i0+rb .. i0+rb+63 (coalesced, two per lane)
-      const int64_t cb = CS.rc_off + i0 + rb + k0;
-      __syncthreads();
+    // ---- column records of every slot (register set t holds slot t at i0)
+    double A[DT][D], G[DT][D], Z[DT][D], V[DT][D], X[DT], CM[DT][NP];
+#pragma unroll
+    for (int t = 0; t < DT; ++t) {
 #pragma unroll
       for (int d = 0; d < D; ++d) {
-        lcol[d][lane] = rec[d * stride + cb + lane];
-        lcol[d][64 + lane] = rec[d * stride + cb + 64 + lane];
+        const Double4 r = rec[d * stride + CS.rc_off + c0 + t];
+        A[t][d] = r.x;
+        G[t][d] = r.y;
+        Z[t][d] = r.z;
+        V[t][d] = r.w;
+        if (d == 0) X[t] = r.w;
+      }
+#pragma unroll
+      for (int q = 0; q < NP; ++q) CM[t][q] = kBig;
+    }
+
+    // Records of the columns entering at lane 63 during the rows of a block
+    // (column newc + row offset), spread over the lanes: element e is
+    // double f = e % NF of the block's column e / NF.
+    double pf[NPF];
+    auto prefetch = [&](int64_t sb) {
+#pragma unroll
+      for (int k = 0; k < NPF; ++k) {
+        const int e = lane + 64 * k;
+        pf[k] = 0.0;
+        if (e < TP * NF && sb < nsteps) {
+          const int u = e / NF, f = e % NF;
+          int d, comp;
+          if constexpr (kSimple) {
+            d = f < 3 * D ? f / 3 : 0;
+            comp = f < 3 * D ? f % 3 : 3;
+          } else {
+            d = f / 4;
+            comp = f % 4;
+          }
+          pf[k] = reinterpret_cast<const double *>(rec + d * stride + newc + sb + u)[comp];
+        }
+      }
+    };
+    auto stage = [&]() {
+#pragma unroll
+      for (int k = 0; k < NPF; ++k) {
+        const int e = lane + 64 * k;
+        if (e < TP * NF) lfresh[e / NF][e % NF] = pf[k];
+      }
+    };
+    prefetch(0);
+    __syncthreads();  // the previous tile's last block is done with lfresh
+    stage();
+    prefetch(TP);
+    __syncthreads();
+
+    auto emit_row = [&](int q, int64_t i, double kb) {
+      const float val = K::value(kb, !kSimple);
+      if (val < 1.0e30f) {
+        const int64_t j = i + k0 + (int64_t)K::code(kb);
+        if (j < lc) atomicMin(rkeys + q * kstride + i, pack_md(val, j));
+      }
+    };
+    auto emit_col = [&](int q, int64_t c, double kb) {
+      const float val = K::value(kb, !kSimple);
+      if (c < lc && val < 1.0e30f) {
+        const int64_t i = c - k0 - (int64_t)K::code(kb);
+        atomicMin(ckeys + q * kstride + c, pack_md(val, i));
+      }
+    };
+
+    for (int64_t sb = 0; sb < nsteps; sb += TP) {
+      md_for<TP>([&](auto uc) {
+        constexpr int u = decltype(uc)::value, r0 = u % DT;  // set of slot 0
+        const int64_t ri = rrow + sb + u;
+        double ai[D], gi[D], zi[D], ui[D], qi = 0.0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          const Double4 rr = ldu_md(rec + d * stride + ri);
+          ai[d] = rr.x;
+          gi[d] = rr.y;
+          zi[d] = rr.z;
+          if (d == 0) qi = rr.w;
+          if constexpr (!kSimple) ui[d] = ldu_md(&mu2[d * stride + ri].y);
+        }
+        double rmin[NP];
+        md_for<DT>([&](auto tc) {
+          constexpr int t = decltype(tc)::value, p = (t + r0) % DT;
+          double key[NP];
+          if constexpr (kSimple) {
+            // d^2 = Q_i + Q_j + sum_d [m (mu_i - mu_j)^2 - 2 C_d]
+            double d2 = qi + X[p];
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+              const double dz = zi[d] - Z[p][d];
+              d2 = fma(dz, dz, d2);
+              d2 = fma(-2.0, C[t][d], d2);
+              C[t][d] = fma(A[p][d], gi[d], C[t][d]);
+              C[t][d] = fma(ai[d], G[p][d], C[t][d]);
+            }
+            key[0] = K::from_f64(fmax(d2, 0x1p-1000), codes[t]);
+          } else {
+            // per dimension 2m (u_i + v_j - C s_i s_j) = d^2, with u, v
+            // scaled by 2m and s by sqrt(2m) in the records
+            unsigned db[D];
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+              const double k2 = fma(-(C[t][d] * zi[d]), Z[p][d], ui[d] + V[p][d]);
+              // at least a small normal (the integer max also lifts negative
+              // values); huge (invalid or padding) keys become +inf, which
+              // the sort, the means and the key order all keep last
+              const int kb = max((int)__float_as_uint((float)k2), (int)__float_as_uint(0x1p-100f));
+              db[d] = __float_as_uint(__builtin_amdgcn_sqrtf(__int_as_float(kb)));
+              C[t][d] = fma(A[p][d], gi[d], C[t][d]);
+              C[t][d] = fma(ai[d], G[p][d], C[t][d]);
+            }
+            sort_net<D>(db);
+            float run = 0.0f;
+#pragma unroll
+            for (int q = 0; q < NP; ++q) {
+              run += __uint_as_float(db[q]);
+              key[q] = K::from_f32(q == 0 ? run : run * (1.0f / (float)(q + 1)), codes[t]);
+            }
+          }
+#pragma unroll
+          for (int q = 0; q < NP; ++q) {
+            CM[p][q] = kmin_f64(CM[p][q], key[q]);
+            rmin[q] = t == 0 ? key[q] : kmin_f64(rmin[q], key[q]);
+          }
+        });
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+          lrow[q][u][lane] = rmin[q];
+          if (lane == 0) lcol[q][u] = CM[r0][q];
+        }
+        // set r0 moves one lane down; lane 63 takes the entering column,
+        // read from LDS at a wave-uniform address
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          if constexpr (kSimple) {
+            A[r0][d] = md_shl_in(lfresh[u][3 * d], A[r0][d]);
+            G[r0][d] = md_shl_in(lfresh[u][3 * d + 1], G[r0][d]);
+            Z[r0][d] = md_shl_in(lfresh[u][3 * d + 2], Z[r0][d]);
+          } else {
+            A[r0][d] = md_shl_in(lfresh[u][4 * d], A[r0][d]);
+            G[r0][d] = md_shl_in(lfresh[u][4 * d + 1], G[r0][d]);
+            Z[r0][d] = md_shl_in(lfresh[u][4 * d + 2], Z[r0][d]);
+            V[r0][d] = md_shl_in(lfresh[u][4 * d + 3], V[r0][d]);
+          }
+        }
+        if constexpr (kSimple) X[r0] = md_shl_in(lfresh[u][3 * D], X[r0]);
+#pragma unroll
+        for (int q = 0; q < NP; ++q) CM[r0][q] = md_shl1d(CM[r0][q], kBig);
+      });
+      // ---- rows sb .. sb+TP-1: the 64 lane minima of each row in two
+      // passes (TP per lane, then 64/TP per row), then the merges
+      __syncthreads();
+      {
+        const int r = lane % TP, g0 = (lane / TP) * TP;
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+          double best = lrow[q][r][g0];
+#pragma unroll
+          for (int e = 1; e < TP; ++e) best = kmin_f64(best, lrow[q][r][g0 + e]);
+          lpart[q][lane] = best;
+        }
+      }
+      // the next block's entering columns (every read of this block's is done)
+      stage();
+      prefetch(sb + 2 * TP);
+      __syncthreads();
+      if (lane < TP) {
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+          double best = lpart[q][lane];
+#pragma unroll
+          for (int e = 1; e < 64 / TP; ++e) best = kmin_f64(best, lpart[q][lane + e * TP]);
+          const int64_t s = sb + lane;
+          if (s < nr) emit_row(q, i0 + s, best);
+          emit_col(q, i0 + s + k0, lcol[q][lane]);
+        }
       }
       __syncthreads();
-      const int rn = __builtin_amdgcn_readfirstlane((int)min((int64_t)64, nr - rb));
-      for (int r = 0; r < rn; ++r) {
-        const int64_t i = i0 + rb + r;
-        const int64_t ri_off = uni(rrow + rb + r);
-        float val[NP];
-        if (MODE == kMdSimple) {
-          double d2 = ldu_md(&rec[ri_off].w) + lcol[0][r + lane].w;
-#pragma unroll
-          for (int d = 0; d < D; ++d) {
-            const Double4 ri = ldu_md(rec + d * stride + ri_off), cj = lcol[d][r + lane];
-            const double dm = ri.z - cj.z;
-            d2 = fma((double)m * dm, dm, d2);
-            d2 = fma(-2.0, C[d], d2);
-            C[d] = fma(cj.x, ri.y, C[d]);
-            C[d] = fma(ri.x, cj.y, C[d]);
-          }
-          val[0] = (float)d2;
-        } else {
-          float dist[D];
-#pragma unroll
-          for (int d = 0; d < D; ++d) {
-            const Double4 ri = ldu_md(rec + d * stride + ri_off), cj = lcol[d][r + lane];
-            const double key = ldu_md(&mu2[d * stride + ri_off].y) + cj.w - C[d] * ri.z * cj.z;
-            dist[d] = sqrtf((float)(2.0 * m * fmax(key, 0.0)));
-            C[d] = fma(cj.x, ri.y, C[d]);
-            C[d] = fma(ri.x, cj.y, C[d]);
-          }
-          sort_net<D>(dist);
-          float run = 0.0f;
-#pragma unroll
-          for (int p = 0; p < NP; ++p) {
-            run += dist[p];
-            val[p] = run / (float)(p + 1);
-          }
-        }
-#pragma unroll
-        for (int p = 0; p < NP; ++p) {
-          // row minimum: the smallest value, at its first lane (the smallest
-          // column on equal values)
-          const float vp = val[p] > 0.0f ? val[p] : 0.0f;
-          const unsigned vb = __float_as_uint(vp);
-          const unsigned mn = wave_min_u32(vb);
-          const unsigned long long hit = __ballot(vb == mn);
-          if (lane == 0 && __uint_as_float(mn) < 1.0e30f)
-            atomicMin(rkeys + p * kstride + i,
-                      ((unsigned long long)mn << 32) | (unsigned long long)(uint32_t)(i + k0 + __ffsll((long long)hit) - 1));
-          const unsigned long long ck = pack_md(val[p], i);
-          CM[p] = ck < CM[p] ? ck : CM[p];
-          // lane 0's column (i + k0) has met every row of this tile it meets
-          if (lane == 0 && i + k0 < lc && (float)__uint_as_float((unsigned)(CM[p] >> 32)) < 1.0e30f)
-            atomicMin(ckeys + p * kstride + i + k0, CM[p]);
-          const unsigned hi = shift_down1((unsigned)(CM[p] >> 32), 0xFFFFFFFFu);
-          const unsigned lo = shift_down1((unsigned)CM[p], 0xFFFFFFFFu);
-          CM[p] = ((unsigned long long)hi << 32) | lo;
-        }
-      }
     }
-    // columns still in flight: lane L holds column i0 + nr + k0 + L
-    const int64_t c = i0 + nr + k0 + lane;
-    unsigned long long *cdst = ckeys + c;
-    for (int p = 0; p < NP; ++p) {  // CM is read through a copy so that it stays in registers
-      unsigned long long v = CM[0];
+    // columns still in flight: set t of lane L holds column
+    // i0 + nsteps + k0 + L*DT + t
 #pragma unroll
-      for (int q = 1; q < NP; ++q) v = q == p ? CM[q] : v;
-      if (c < lc && v != ~0ull && __uint_as_float((unsigned)(v >> 32)) < 1.0e30f) atomicMin(cdst + p * kstride, v);
-    }
+    for (int t = 0; t < DT; ++t)
+#pragma unroll
+      for (int q = 0; q < NP; ++q) emit_col(q, i0 + nsteps + k0 + (int64_t)lane * DT + t, CM[t][q]);
   }
 }
 
@@ -344,7 +596,7 @@ __global__ void __launch_bounds__(256) k_md_finalize(Plan plan, int D, const Tin
           const double ma = mu2[d * stride + S.rc_off + w].x, mb = mu2[d * stride + Q.rc_off + idx].x;
           const Tin *a = Tb + S.t_off + (int64_t)d * S.n + w;
           const Tin *b = Tb + Q.t_off + (int64_t)d * Q.n + idx;
-          const double ia = ra.z * sqrt((double)m), ib = rb.z * sqrt((double)m);  // 1/sigma or 0
+          const double ia = ra.z / sqrt(2.0), ib = rb.z / sqrt(2.0);  // 1/sigma or 0
           double s = 0.0;
           for (int u = 0; u < m; ++u) {
             const double e = ((double)a[u] - ma) * ia - ((double)b[u] - mb) * ib;
@@ -442,14 +694,50 @@ hipError_t launch_md(int mode, int D, const Plan &plan, const void *T, bool t_f6
   return e;
 }
 
+namespace {
+template <int MODE>
+int md_width_t(int D) {
+  switch (D) {
+    case 1: return MdShape<1, MODE>::W;
+    case 2: return MdShape<2, MODE>::W;
+    case 3: return MdShape<3, MODE>::W;
+    case 4: return MdShape<4, MODE>::W;
+    case 5: return MdShape<5, MODE>::W;
+    case 6: return MdShape<6, MODE>::W;
+    case 7: return MdShape<7, MODE>::W;
+    case 8: return MdShape<8, MODE>::W;
+    default: return 64;
+  }
+}
+template <int MODE>
+hipError_t md_occupancy_t(int D, int *per) {
+  switch (D) {
+    case 1: return hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_md_sweep<float, 1, MODE>, 64, 0);
+    case 2: return hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_md_sweep<float, 2, MODE>, 64, 0);
+    case 3: return hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_md_sweep<float, 3, MODE>, 64, 0);
+    case 4: return hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_md_sweep<float, 4, MODE>, 64, 0);
+    case 5: return hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_md_sweep<float, 5, MODE>, 64, 0);
+    case 6: return hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_md_sweep<float, 6, MODE>, 64, 0);
+    case 7: return hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_md_sweep<float, 7, MODE>, 64, 0);
+    case 8: return hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_md_sweep<float, 8, MODE>, 64, 0);
+    default: return hipErrorInvalidValue;
+  }
+}
+}  // namespace
+
+int md_strip_width(int mode, int D) {
+  return mode == kMdSimple ? md_width_t<kMdSimple>(D) : md_width_t<kMdMulti>(D);
+}
+
 int md_sweep_grid(int mode, int D) {
   int dev = 0, cus = 256;
   hipDeviceProp_t prop;
   if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
     cus = prop.multiProcessorCount;
-  (void)mode;
-  (void)D;
-  return cus * 16;
+  int per = 0;
+  const hipError_t e = mode == kMdSimple ? md_occupancy_t<kMdSimple>(D, &per) : md_occupancy_t<kMdMulti>(D, &per);
+  if (e != hipSuccess || per <= 0) per = 8;
+  return cus * per;
 }
 
 }  // namespace mpx
