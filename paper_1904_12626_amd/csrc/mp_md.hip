@@ -203,13 +203,16 @@ __device__ __forceinline__ double md_shl_in(double in63, double v) {
 // Per slot a lane keeps its column's records (SiMPle: a, g, sqrt(m) mu per
 // dimension and Q; k-dimensional: a, g, s, v per dimension), the cross
 // product of every dimension and one running column minimum per output; DT
-// (a power of two) is the largest slot count whose state fits about 176
-// registers.  TP rows pass between two LDS reductions of the row minima.
+// (a power of two) is the largest slot count whose state fits the register
+// budget (176 for SiMPle, 100 for the k-dimensional profiles, whose per-cell
+// temporaries are larger; measured on 3 dimensions: 2 slots 101 ms, 4 slots
+// 129 ms, 1 slot 171 ms).  TP rows pass between two LDS reductions of the
+// row minima.
 template <int D, int MODE>
 struct MdShape {
   static constexpr int NP = MODE == kMdMulti ? D : 1;
   static constexpr int kSlotRegs = MODE == kMdSimple ? 8 * D + 4 : 12 * D;
-  static constexpr int kFit = 176 / kSlotRegs;
+  static constexpr int kFit = (MODE == kMdSimple ? 176 : 100) / kSlotRegs;
   static constexpr int DT = kFit >= 8 ? 8 : (kFit >= 4 ? 4 : (kFit >= 2 ? 2 : 1));
   static constexpr int TP = NP == 1 ? 16 : (NP <= 3 ? 8 : 4);
   static constexpr int W = 64 * DT;
