@@ -9,14 +9,16 @@
 // its own neighbour and offers itself to every one of them.
 //
 // New windows are processed B at a time (B <= ez + 1, so no new window is a
-// candidate of another in the same batch): a workgroup owns 256 - (B-1)
-// consecutive columns and also recomputes the B-1 columns to their left,
-// whose cross products it needs (a trapezoid: after step b the leftmost b
-// threads hold stale values, and none of them is owned).  Each thread
-// keeps its column's terms in registers for all B rows and passes its cross
-// product to the right neighbour through LDS, so a column's data is read
-// once per batch instead of once per row.
+// candidate of another in the same batch): a one-wave workgroup owns
+// 64*8 - (B-1) consecutive columns and also recomputes the B-1 columns to
+// their left, whose cross products it needs (a trapezoid: after step b the
+// leftmost b columns hold stale values, and none of them is owned).  Each
+// lane keeps its eight columns' terms in registers for all B rows and the
+// cross products move right through registers and one DPP shift per step,
+// so a column's data is read once per batch and no step needs a barrier.
 #include <cmath>
+#include <type_traits>
+#include <utility>
 
 #include "mp_internal.h"
 #include "mp_types.h"
@@ -25,46 +27,12 @@ namespace mpx {
 
 namespace {
 
-constexpr int kStreamBlock = 256;
-
-// Minimum of a double over the wave, returned wave-uniform: DPP row shifts
-// of both halves inside each row of 16 lanes, then the four row minima.
-template <int CTRL>
-__device__ __forceinline__ double dpp_shr(double x) {
-  const long long b = __double_as_longlong(x);
-  const int lo = __builtin_amdgcn_update_dpp((int)b, (int)b, CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp((int)(b >> 32), (int)(b >> 32), CTRL, 0xF, 0xF, false);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
+// Lane `lane`'s value of x (lane index wave-uniform).
 __device__ __forceinline__ double lane_value(double x, int lane) {
   const long long b = __double_as_longlong(x);
   const int lo = __builtin_amdgcn_readlane((int)b, lane);
   const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-__device__ __forceinline__ double wave_min_f64(double v) {
-  v = fmin(v, dpp_shr<0x111>(v));  // row_shr:1
-  v = fmin(v, dpp_shr<0x112>(v));  // row_shr:2
-  v = fmin(v, dpp_shr<0x114>(v));  // row_shr:4
-  v = fmin(v, dpp_shr<0x118>(v));  // row_shr:8
-  return fmin(fmin(lane_value(v, 15), lane_value(v, 31)), fmin(lane_value(v, 47), lane_value(v, 63)));
-}
-
-// Scalar load of a wave-uniform address (constant address space): the
-// per-row terms are read-only in the batch kernel.
-template <typename T>
-__device__ __forceinline__ T ldu_s(const T *p) {
-#if defined(__HIP_DEVICE_COMPILE__)
-  typedef const uint32_t __attribute__((address_space(4))) *cptr;
-  const cptr q = (cptr)(p);
-  T out;
-  uint32_t *o = reinterpret_cast<uint32_t *>(&out);
-#pragma unroll
-  for (int i = 0; i < (int)(sizeof(T) / 4); ++i) o[i] = q[i];
-  return out;
-#else
-  return *p;
-#endif
 }
 
 template <typename Tin>
@@ -150,87 +118,231 @@ __global__ void __launch_bounds__(64) k_stream_col0(StreamWork s, const Tin *__r
   if (threadIdx.x == 0) s.col0[blockIdx.x] = acc;
 }
 
-// One batch of B new windows w0 .. w0+B-1 (see the file comment).  Row
-// minima of each step go to per-wave partials (reduced by
-// k_stream_rowfin); owned columns update their own profile entries.  One
-// barrier per step: the cross products move right through LDS.
+// One batch of B new windows w0 .. w0+B-1 (see the file comment), one wave
+// per workgroup.  Lane L holds the DT consecutive columns
+// cbase + L*DT + t; at each step every column continues its left
+// neighbour's cross product, kept in place in a register ring (slot t at
+// step b works in register (t - b) mod DT, which holds slot t-1's value of
+// step b-1; slot 0 takes lane L-1's through one DPP shift).  Keys carry a
+// code in their low mantissa bits: the column (lane*DT + t) in the row key,
+// the step b in the column key, so each minimum is one FP64 min.  Row
+// minima of every step go to LDS and are reduced every 16 steps into one
+// partial per wave and row; each column's minimum over the batch stays in a
+// register and is merged into the profile at the end.
+constexpr int kStreamSlots = 8;
+constexpr int kStreamWidth = 64 * kStreamSlots;
+
+// The low bits `mask` of v replaced by code (< mask + 1): one bitfield
+// insert, (mask & code) | (~mask & low word); a per-lane code with the mask
+// in a scalar register, or a wave-uniform code under the mask 63.
+__device__ __forceinline__ double key_code(double v, unsigned code, unsigned mask) {
+  const long long b = __double_as_longlong(v);
+  unsigned lo;
+  asm("v_bfi_b32 %0, %1, %2, %3" : "=v"(lo) : "s"(mask), "v"(code), "v"((unsigned)(b & 0xffffffffll)));
+  return __longlong_as_double((b & ~0xffffffffll) | lo);
+}
+__device__ __forceinline__ double key_code63(double v, unsigned code) {
+  const long long b = __double_as_longlong(v);
+  unsigned lo;
+  asm("v_bfi_b32 %0, 63, %1, %2" : "=v"(lo) : "s"(code), "v"((unsigned)(b & 0xffffffffll)));
+  return __longlong_as_double((b & ~0xffffffffll) | lo);
+}
+__device__ __forceinline__ double key_value(double k, unsigned mask) {
+  return __longlong_as_double(__double_as_longlong(k) & ~(long long)mask);
+}
+__device__ __forceinline__ unsigned key_code_of(double k, unsigned mask) {
+  return (unsigned)(__double_as_longlong(k) & 0xffffffffll) & mask;
+}
+// keys are never NaN: the plain instruction, without NaN quieting
+__device__ __forceinline__ double kmin(double a, double b) {
+  double r;
+  asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+// maximum with a wave-uniform bound (a plain instruction: no NaN arrives)
+__device__ __forceinline__ double kmax_s(double a, double b) {
+  double r;
+  asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "s"(b));
+  return r;
+}
+// lane L takes lane L-1's value; lane 0 keeps `old0`
+__device__ __forceinline__ double shr1_keep(double old0, double v) {
+  const long long b = __double_as_longlong(v), f = __double_as_longlong(old0);
+  const int lo = __builtin_amdgcn_update_dpp((int)(f & 0xffffffffll), (int)(b & 0xffffffffll),
+                                             0x138 /* wave_shr:1 */, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(f >> 32), (int)(b >> 32), 0x138, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <typename Fn, int... Ts>
+__device__ __forceinline__ void sfor_impl(Fn &&f, std::integer_sequence<int, Ts...>) {
+  (f(std::integral_constant<int, Ts>{}), ...);
+}
+template <int N, typename Fn>
+__device__ __forceinline__ void sfor(Fn &&f) {
+  sfor_impl(f, std::make_integer_sequence<int, N>{});
+}
+
 template <typename Tin>
-__global__ void __launch_bounds__(kStreamBlock) k_stream_batch(StreamWork s, const Tin *__restrict__ T, int m,
-                                                               int ez, int64_t w0, int B, int seed_step,
-                                                               const double *__restrict__ Cprev, double *Cnew,
-                                                               int64_t *I, int64_t nparts) {
-  __shared__ double xfer[2][kStreamBlock];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int H = B - 1;
-  const int64_t c0 = (int64_t)blockIdx.x * (kStreamBlock - H);
-  const int64_t j = c0 - H + tid;
-  const bool owned = tid >= H;
-  const int64_t jlast = w0 + B - 1 - ez - 1;  // last column any row of the batch scores
-  double aj1 = 0.0, gj1 = 0.0, isdj = 0.0, Pdj = INFINITY;
-  uint8_t fj = 0;
-  int64_t Ij = -1;
-  bool changed = false;
-  if (j >= 0 && j <= jlast) {
-    if (j >= 1) {
-      aj1 = s.a[j - 1];
-      gj1 = s.g[j - 1];
+__global__ void __launch_bounds__(64) k_stream_batch(StreamWork s, const Tin *__restrict__ T, int m, int ez,
+                                                     int64_t w0, int B, bool seed,
+                                                     const double *__restrict__ Cprev, double *Cnew, int64_t *I,
+                                                     int64_t nparts) {
+  constexpr int DT = kStreamSlots, W = kStreamWidth;
+  constexpr unsigned kRowMask = W - 1;  // column code: 9 bits
+  constexpr unsigned kColMask = 63;     // step code: B <= 63 (key_code63)
+  constexpr double kHuge = 1.0e300;
+  __shared__ double lrow[16][65];
+  __shared__ double lpart[64];
+  const int lane = threadIdx.x;
+  const bool first = blockIdx.x == 0;
+  // Workgroup 0 owns columns 0 .. W-1 (column 0 sits in lane 0, slot 0 and
+  // takes its precomputed products as the DPP fallback value); workgroup
+  // k >= 1 owns W - H columns after a halo of H = B - 1.
+  const int H = first ? 0 : B - 1;
+  const int64_t cbase = first ? 0 : (int64_t)W + (int64_t)(blockIdx.x - 1) * (W - (B - 1)) - (B - 1);
+  const int64_t jlast = w0 + B - 1 - ez - 1;  // last column any row scores
+  const int64_t jprev = w0 - ez - 2;           // last column of C(w0 - 1, .)
+  // the last columns of this wave become admissible during the batch
+  const bool ramp = cbase + W - 1 > w0 - ez - 1;
+
+  unsigned code[DT];
+  double aj1[DT], gj1[DT], sj[DT], vj[DT], R[DT], cm[DT];
+#pragma unroll
+  for (int t = 0; t < DT; ++t) {
+    code[t] = (unsigned)(lane * DT + t);
+    const int64_t j = cbase + code[t];
+    aj1[t] = 0.0;
+    gj1[t] = 0.0;
+    sj[t] = 0.0;
+    vj[t] = kHuge;  // no candidate: halo, outside the columns, invalid
+    cm[t] = kHuge;
+    if (j >= 0 && j <= jlast) {
+      if (j >= 1) {
+        aj1[t] = s.a[j - 1];
+        gj1[t] = s.g[j - 1];
+      }
+      const uint8_t f = s.flags[j];
+      sj[t] = s.isd[j];
+      if ((int)code[t] >= H && (f & 1)) vj[t] = (f & 2) ? -0.5 : 0.0;
     }
-    fj = s.flags[j];
-    isdj = s.isd[j];
-    if (owned) {
-      Pdj = s.Pd[j];
-      Ij = I[j];
+    // register t feeds slot t at step 0 with C(w0 - 1, j - 1); register 0
+    // is shifted one lane right first, so it holds this lane's last column.
+    // A re-seeded batch instead finds C(w0, j) itself (direct products) in
+    // the same buffer, for every column up to w0 - ez - 1.
+    if (seed) {
+      R[t] = (j >= 0 && j <= w0 - ez - 1) ? Cprev[j] : 0.0;
+    } else {
+      const int64_t src = t == 0 ? cbase + lane * DT + DT - 1 : j - 1;
+      R[t] = (src >= 0 && src <= jprev) ? Cprev[src] : 0.0;
     }
   }
-  // C(w0 - 1, j - 1), available for j - 1 <= w0 - 1 - ez - 1
-  double Cin = (j >= 1 && j - 1 <= w0 - ez - 2) ? Cprev[j - 1] : 0.0;
-  double C = 0.0;
-  const int64_t part = (int64_t)blockIdx.x * (kStreamBlock / 64) + wave;
-  for (int b = 0; b < B; ++b) {
-    const int64_t w = w0 + b, jmax = w - ez - 1;
-    if (b > 0) Cin = tid > 0 ? xfer[(b - 1) & 1][tid - 1] : 0.0;
-    double best = INFINITY;
-    bool cand = false;
-    if (j >= 0 && j <= jmax) {
-      if (j == 0) C = s.col0[b];
-      else if (b == seed_step) C = direct_c(T, w, j, s, m);
-      else C = Cin + aj1 * ldu_s(s.g + w - 1) + ldu_s(s.a + w - 1) * gj1;
-      const uint8_t fw = (uint8_t)(ldu_s(reinterpret_cast<const uint32_t *>(s.flags + (w & ~3ll))) >> (8 * (w & 3)));
-      if ((fw & 1) && (fj & 1) && owned) {
-        double key;
-        if ((fw & 2) && (fj & 2)) key = 0.0;
-        else if ((fw & 2) || (fj & 2)) key = 0.5;
-        else key = fmax(1.0 - C * ldu_s(s.isd + w) * isdj, 0.0);
-        const double d = key;
-        best = d;
-        cand = true;
-        if (d < Pdj) {
-          Pdj = d;
-          Ij = w;
-          changed = true;
+  // lane 0's left neighbour at step 0 (later its first columns are stale,
+  // and none of them is owned)
+  const double c_left = (cbase - 1 >= 0 && cbase - 1 <= jprev) ? Cprev[cbase - 1] : 0.0;
+  // The window terms of every step, lane b holding step b's (read by the
+  // steps with lane reads, so that no step waits on memory): g and a of
+  // window w - 1, s and the row term u of window w, and (workgroup 0)
+  // C(w, 0).
+  double tg = 0.0, ta = 0.0, ts = 0.0, tu = kHuge, tc0 = 0.0;
+  if (lane < B) {
+    const int64_t w = w0 + lane;
+    tg = s.g[w - 1];
+    ta = s.a[w - 1];
+    ts = s.isd[w];
+    const uint8_t fw = s.flags[w];
+    tu = (fw & 1) ? ((fw & 2) ? 0.5 : 1.0) : kHuge;
+    if (first) tc0 = s.col0[lane];
+  }
+
+  int fb = 0;  // first step not yet flushed
+  auto flush = [&](int nb) {
+    __syncthreads();
+    {
+      const int r = lane & 15, g0 = (lane >> 4) * 16;
+      double best = lrow[r][g0];
+#pragma unroll
+      for (int e = 1; e < 16; ++e) best = kmin(best, lrow[r][g0 + e]);
+      lpart[lane] = best;
+    }
+    __syncthreads();
+    if (lane < nb) {
+      double best = kmin(kmin(lpart[lane], lpart[lane + 16]), kmin(lpart[lane + 32], lpart[lane + 48]));
+      const double v = key_value(best, kRowMask);
+      const bool hit = v < 1.0e299;
+      const int64_t at = (int64_t)(fb + lane) * nparts + blockIdx.x;
+      s.part_d[at] = hit ? v : INFINITY;
+      s.part_j[at] = hit ? cbase + key_code_of(best, kRowMask) : -1;
+    }
+    __syncthreads();
+  };
+
+  // The B steps; RAMP (a uniform choice per workgroup, taken outside the
+  // loop) masks the columns that are not yet admissible.
+  auto run = [&](auto ramp_c) {
+    constexpr bool RAMP = decltype(ramp_c)::value;
+    for (int bb = 0; bb < B; bb += DT) {
+      sfor<DT>([&](auto uc) {
+        constexpr int u = decltype(uc)::value;
+        const int b = bb + u;
+        if (b < B) {
+          const int64_t w = w0 + b;
+          const double gw1 = lane_value(tg, b), aw1 = lane_value(ta, b), sw = lane_value(ts, b);
+          const double uw = lane_value(tu, b);
+          constexpr int r0 = (DT - u) % DT;  // register of slot 0
+          bool direct = false;
+          if constexpr (u == 0) direct = seed && b == 0;
+          if (!direct) {
+            const double keep = first ? lane_value(tc0, b) : (b == 0 ? c_left : R[r0]);
+            R[r0] = shr1_keep(keep, R[r0]);
+          }
+          int lim = W;
+          if constexpr (RAMP) lim = (int)min(max(w - ez - 1 - cbase, (int64_t)-1), (int64_t)W);
+          double rmin = kHuge;
+#pragma unroll
+          for (int t = 0; t < DT; ++t) {
+            double &C = R[(t + r0) % DT];
+            if (!direct) C = fma(aj1[t], gw1, fma(aw1, gj1[t], C));
+            double key = kmax_s(fma(-(C * sw), sj[t], uw + vj[t]), 0x1p-1000);
+            if constexpr (RAMP) {
+              if ((int)code[t] > lim) key = kHuge;  // not yet admissible
+            }
+            rmin = kmin(rmin, key_code(key, code[t], kRowMask));
+            cm[t] = kmin(cm[t], key_code63(key, (unsigned)b));
+          }
+          lrow[b & 15][lane] = rmin;
+          if ((b & 15) == 15) {
+            flush(16);
+            fb = b + 1;
+          }
+        }
+      });
+    }
+  };
+  if (ramp) run(std::true_type{});
+  else run(std::false_type{});
+  if (fb < B) flush(B - fb);
+
+  // C(w0 + B - 1, j) for the next batch and the column merges (owned only)
+  const int last = (B - 1) % DT;  // phase of the last step
+  sfor<DT>([&](auto pc) {
+    constexpr int p = decltype(pc)::value;
+    if (p == last) {
+      constexpr int r0 = (DT - p) % DT;
+#pragma unroll
+      for (int t = 0; t < DT; ++t) {
+        const int64_t j = cbase + code[t];
+        if ((int)code[t] >= H && j >= 0 && j <= jlast) {
+          Cnew[j] = R[(t + r0) % DT];
+          const double v = key_value(cm[t], kColMask);
+          if (v < 1.0e299 && v < s.Pd[j]) {
+            s.Pd[j] = v;
+            I[j] = w0 + (int64_t)key_code_of(cm[t], kColMask);
+          }
         }
       }
     }
-    xfer[b & 1][tid] = C;
-    // this wave's best candidate for row w: the smallest distance, at its
-    // first lane (lanes hold increasing columns)
-    const double mn = wave_min_f64(best);
-    const unsigned long long hit = __ballot(cand && best == mn);
-    if (lane == 0) {
-      int64_t jj = -1;
-      if (hit) jj = c0 - H + wave * 64 + (__ffsll((long long)hit) - 1);
-      s.part_d[(int64_t)b * nparts + part] = hit ? mn : INFINITY;
-      s.part_j[(int64_t)b * nparts + part] = jj;
-    }
-    __syncthreads();
-  }
-  if (owned && j >= 0 && j <= jlast) {
-    Cnew[j] = C;  // C(w0 + B - 1, j)
-    if (changed) {
-      s.Pd[j] = Pdj;
-      I[j] = Ij;
-    }
-  }
+  });
 }
 
 // Row w0 + blockIdx.x: its own neighbour from the per-wave partials (strict
@@ -294,11 +406,11 @@ __global__ void __launch_bounds__(256) k_stream_out(StreamWork s, int64_t l, int
 }
 
 constexpr int kStreamMaxBatch = 63;
-// partial row minima: up to kStreamMaxBatch rows x 4 waves per workgroup of
-// >= 194 owned columns
+// partial row minima: up to kStreamMaxBatch rows x one per workgroup of
+// >= kStreamWidth - (kStreamMaxBatch - 1) owned columns
 int64_t stream_partials(int64_t l_max) {
-  return (int64_t)kStreamMaxBatch * (kStreamBlock / 64) *
-         ((l_max + (kStreamBlock - kStreamMaxBatch + 1) - 1) / (kStreamBlock - kStreamMaxBatch + 1) + 1);
+  constexpr int64_t owned = kStreamWidth - (kStreamMaxBatch - 1);
+  return (int64_t)kStreamMaxBatch * ((l_max + owned - 1) / owned + 1);
 }
 
 template <typename Tin>
@@ -330,22 +442,27 @@ hipError_t stream_append_t(const StreamWork &s, const Tin *T, int64_t n_old, int
   const int bmax = (int)std::min<int64_t>(kStreamMaxBatch, (int64_t)ez + 1);
   for (int64_t w0 = l_old; w0 < l_new;) {
     int B = (int)std::min<int64_t>(bmax, l_new - w0);
+    // a re-seeded window (a multiple of `reseed`) always opens a batch
+    const int64_t next_seed = (w0 / reseed + 1) * reseed;
+    if (next_seed < w0 + B) B = (int)(next_seed - w0);
     if ((B & 1) == 0) --B;
+    const bool seed = w0 % reseed == 0;
     const int64_t jlast = w0 + B - 1 - ez - 1;
     if (jlast < 0) {  // no candidates yet: one window at a time
       hipLaunchKernelGGL(k_stream_rowfin, dim3(1), dim3(256), 0, st, s, w0, (int64_t)0, I);
       ++w0;
       continue;
     }
-    const int owned = kStreamBlock - (B - 1);
-    const int64_t nblocks = (jlast + 1 + owned - 1) / owned;
-    const int64_t nparts = nblocks * (kStreamBlock / 64);
-    int seed_step = -1;  // the step of this batch (if any) whose window is re-seeded
-    for (int b2 = 0; b2 < B; ++b2)
-      if ((w0 + b2) % reseed == 0) seed_step = b2;
+    // workgroup 0: columns 0 .. W-1; then W - (B-1) columns each
+    const int owned = kStreamWidth - (B - 1);
+    const int64_t nblocks = 1 + std::max<int64_t>(0, (jlast + 1 - kStreamWidth + owned - 1) / owned);
+    const int64_t nparts = nblocks;
     hipLaunchKernelGGL((k_stream_col0<Tin>), dim3((unsigned)B), dim3(64), 0, st, s, T, m, w0);
-    hipLaunchKernelGGL((k_stream_batch<Tin>), dim3((unsigned)nblocks), dim3(kStreamBlock), 0, st, s, T, m, ez, w0,
-                       B, seed_step, (const double *)s.C[(w0 - 1) & 1], s.C[(w0 + B - 1) & 1], I, nparts);
+    if (seed && w0 - ez - 1 >= 0)  // C(w0, j) by direct products into the buffer the batch reads
+      hipLaunchKernelGGL((k_stream_seed<Tin>), dim3((unsigned)((w0 - ez - 1 + 256) / 256)), b, 0, st, s, T, m,
+                         w0, w0 - ez - 1, s.C[(w0 - 1) & 1]);
+    hipLaunchKernelGGL((k_stream_batch<Tin>), dim3((unsigned)nblocks), dim3(64), 0, st, s, T, m, ez, w0,
+                       B, seed, (const double *)s.C[(w0 - 1) & 1], s.C[(w0 + B - 1) & 1], I, nparts);
     hipLaunchKernelGGL(k_stream_rowfin, dim3((unsigned)B), dim3(256), 0, st, s, w0, nparts, I);
     w0 += B;
   }
