@@ -335,8 +335,8 @@ def main():
             "roofline": {"bound": "alu", "achieved": cells * 7 / (ms / 1e3) / 1e12, "peak": PEAK_LANE_OPS / 1e12,
                          "unit": "TOP/s", "frac": cells * 7 / (ms / 1e3) / 1e12 / (PEAK_LANE_OPS / 1e12),
                          "traffic": None, "kernel": "k_stream_batch", "ops_per_cell": 7,
-                         "note": "per batch of up to 63 windows: ~25 us reading and writing the state of every "
-                                 "earlier window, then ~0.74 us per window"},
+                         "note": "per batch of up to 63 windows: ~13 us reading and writing the state of every "
+                                 "earlier window, then ~0.66 us per window"},
         }
         if args.cpu_rows > 0:
             from oracle import cimpl

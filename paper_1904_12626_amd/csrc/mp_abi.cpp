@@ -860,7 +860,7 @@ StreamLayout stream_layout(int64_t n_max, int32_t m) {
   L.c1 = take(8 * lm);
   L.pdp = take(8 * np);
   L.pjp = take(8 * np);
-  L.col0 = take(8 * 64);
+  L.col0 = take(8 * lm);
   L.join = o;
   mp_options f64opt{MP_PREC_F64, 0, 0, (int32_t)MP_FLAG_FP64_FINALIZE};
   Job j;

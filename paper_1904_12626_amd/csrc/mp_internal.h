@@ -181,7 +181,7 @@ struct StreamWork {
   double *C[2];      // [l_max] cross products of the newest window (window w in C[w % 2])
   double *part_d;    // per-wave row minima of a batch
   int64_t *part_j;
-  double *col0;      // [64] C(w, 0) of the windows of a batch
+  double *col0;      // [l_max] C(w, 0) of the appended windows
 };
 int64_t stream_partials(int64_t l_max);
 hipError_t launch_stream_init(const StreamWork &s, const void *T, bool t_f64, int64_t n, int m, int ez,

@@ -77,6 +77,68 @@ __global__ void __launch_bounds__(256) k_stream_stats(StreamWork s, const Tin *_
   s.g[w] = smp(x) - mu + a * (double)(m - 1) / (2.0 * m);
 }
 
+// The same for a few windows, one wave per window (lanes split the
+// samples; FP64 sums by butterfly), plus C(w, 0): column 0 has no left
+// neighbour to continue from, so its cross products are direct.
+__device__ __forceinline__ double wsum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+// Window w_lo - 1 (an old window whose successor sample has just arrived)
+// only gets its a and g terms.
+template <typename Tin>
+__global__ void __launch_bounds__(64) k_stream_stats_wave(StreamWork s, const Tin *__restrict__ T, int64_t n,
+                                                          int m, int64_t w_lo) {
+  const int64_t w = w_lo - 1 + blockIdx.x;
+  const int lane = threadIdx.x;
+  const Tin *x = T + w;
+  if (blockIdx.x == 0) {
+    if (lane == 0 && w >= 0) {
+      const double a = (w + m < n) ? smp(x + m) - smp(x) : 0.0;
+      s.a[w] = a;
+      s.g[w] = smp(x) - s.mu[w] + a * (double)(m - 1) / (2.0 * m);
+    }
+    return;
+  }
+  bool ok = true;
+  double sum = 0.0, lo = INFINITY, hi = -INFINITY;
+  for (int u = lane; u < m; u += 64) {
+    const double v = (double)x[u];
+    if (!isfinite(v)) ok = false;
+    const double c = isfinite(v) ? v : 0.0;
+    lo = fmin(lo, c);
+    hi = fmax(hi, c);
+    sum += c;
+  }
+  ok = __all(ok);
+  sum = wsum(sum);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, o, 64));
+    hi = fmax(hi, __shfl_xor(hi, o, 64));
+  }
+  const double mu = sum / m, mu0 = s.mu[0];
+  double q = 0.0, c0 = 0.0;
+  for (int u = lane; u < m; u += 64) {
+    const double dv = smp(x + u) - mu;
+    q = fma(dv, dv, q);
+    c0 = fma(dv, smp(T + u) - mu0, c0);
+  }
+  q = wsum(q);
+  c0 = wsum(c0);
+  if (lane == 0) {
+    const bool cst = ok && (lo == hi || !(q > 0.0));
+    s.mu[w] = mu;
+    s.isd[w] = (ok && !cst) ? 1.0 / (sqrt((double)m) * sqrt(q / m)) : 0.0;
+    s.flags[w] = (uint8_t)((ok ? 1 : 0) | (cst ? 2 : 0));
+    const double a = (w + m < n) ? smp(x + m) - smp(x) : 0.0;
+    s.a[w] = a;
+    s.g[w] = smp(x) - mu + a * (double)(m - 1) / (2.0 * m);
+    s.col0[w] = c0;
+  }
+}
+
 // Key d^2 / (2m) (= 1 - Pearson rho for varying windows) from two windows'
 // statistics and their centred cross product; constant windows normalise to
 // zero.  The state holds keys; distances are taken at the output.
@@ -95,27 +157,38 @@ __device__ double direct_c(const Tin *T, int64_t i, int64_t j, const StreamWork 
   return acc;
 }
 
-// Cross products C(w, j) of window w with every j <= w - ez - 1, directly.
+// Cross products C(w, j) of window w with every j <= jmax, directly; eight
+// consecutive columns per thread share their sample loads (column sample
+// j0 + v meets window sample v - t in column j0 + t):
+// C = sum (x_w - mu_w) x_j - mu_j sum (x_w - mu_w).
 template <typename Tin>
 __global__ void __launch_bounds__(256) k_stream_seed(StreamWork s, const Tin *__restrict__ T, int m,
                                                      int64_t w, int64_t jmax, double *C) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j > jmax) return;
-  C[j] = direct_c(T, w, j, s, m);
-}
-
-// C(w0 + b, 0) for the B windows of a batch: column 0 has no left
-// neighbour to continue from, so its cross products are direct dot
-// products, one wave per window.
-template <typename Tin>
-__global__ void __launch_bounds__(64) k_stream_col0(StreamWork s, const Tin *__restrict__ T, int m, int64_t w0) {
-  const int64_t w = w0 + blockIdx.x;
-  const double mw = s.mu[w], m0 = s.mu[0];
-  double acc = 0.0;
-  for (int u = threadIdx.x; u < m; u += 64) acc = fma(smp(T + w + u) - mw, smp(T + u) - m0, acc);
+  constexpr int K = 8;
+  const int64_t j0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * K;
+  if (j0 > jmax) return;
+  const double mw = s.mu[w];
+  double acc[K], xr[K];
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-  if (threadIdx.x == 0) s.col0[blockIdx.x] = acc;
+  for (int t = 0; t < K; ++t) { acc[t] = 0.0; xr[t] = 0.0; }
+  double Sx = 0.0;
+  for (int vb = 0; vb < m + K - 1; vb += K) {
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+      const int v = vb + q;
+      double xn = 0.0;
+      if (v < m) xn = smp(T + w + v) - mw;
+      Sx += xn;
+      xr[q] = xn;
+      const int64_t ci = j0 + v;
+      const double y = ci <= jmax + m - 1 ? smp(T + ci) : 0.0;
+#pragma unroll
+      for (int t = 0; t < K; ++t) acc[t] = fma(xr[(q - t + K) % K], y, acc[t]);
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < K; ++t)
+    if (j0 + t <= jmax) C[j0 + t] = acc[t] - s.mu[j0 + t] * Sx;
 }
 
 // One batch of B new windows w0 .. w0+B-1 (see the file comment), one wave
@@ -194,6 +267,7 @@ __global__ void __launch_bounds__(64) k_stream_batch(StreamWork s, const Tin *__
   constexpr double kHuge = 1.0e300;
   __shared__ double lrow[16][65];
   __shared__ double lpart[64];
+  __shared__ double lpd[kStreamWidth];  // profile of the owned columns
   const int lane = threadIdx.x;
   const bool first = blockIdx.x == 0;
   // Workgroup 0 owns columns 0 .. W-1 (column 0 sits in lane 0, slot 0 and
@@ -206,36 +280,78 @@ __global__ void __launch_bounds__(64) k_stream_batch(StreamWork s, const Tin *__
   // the last columns of this wave become admissible during the batch
   const bool ramp = cbase + W - 1 > w0 - ez - 1;
 
+  // Column state is read with contiguous loads (position e = lane + 64q of
+  // the workgroup's columns) and handed to the lane owning it (positions
+  // lane*DT .. lane*DT + DT-1) through LDS; the staging buffer is the row
+  // minima buffer, unused until the first step.
+  double *const lst = &lrow[0][0];
+  auto pos = [](int e) { return e + (e >> 3); };  // one pad per 8 columns
+  auto to_lanes = [&](const double (&v)[DT], double (&out)[DT]) {
+#pragma unroll
+    for (int q = 0; q < DT; ++q) lst[pos(lane + 64 * q)] = v[q];
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < DT; ++t) out[t] = lst[pos(lane * DT + t)];
+    __syncthreads();
+  };
   unsigned code[DT];
   double aj1[DT], gj1[DT], sj[DT], vj[DT], R[DT], cm[DT];
+  {
+    // contiguous loads of every array first (all in flight together)
+    double va[DT], vg[DT], vs[DT], vv[DT], vc[DT], vpd[DT];
+    const int64_t cfirst = seed ? cbase : cbase - 1;  // C(w0, j) or C(w0 - 1, j - 1)
+    const int64_t clast = seed ? w0 - ez - 1 : jprev;
+#pragma unroll
+    for (int q = 0; q < DT; ++q) {
+      const int e = lane + 64 * q;
+      const int64_t j = cbase + e;
+      va[q] = 0.0;
+      vg[q] = 0.0;
+      vs[q] = 0.0;
+      vv[q] = kHuge;  // no candidate: halo, outside the columns, invalid
+      vpd[q] = INFINITY;
+      if (j >= 0 && j <= jlast) {
+        if (j >= 1) {
+          va[q] = s.a[j - 1];
+          vg[q] = s.g[j - 1];
+        }
+        const uint8_t f = s.flags[j];
+        vs[q] = s.isd[j];
+        if (e >= H && (f & 1)) vv[q] = (f & 2) ? -0.5 : 0.0;
+        if (e >= H) vpd[q] = s.Pd[j];
+      }
+      const int64_t c = cfirst + e;
+      vc[q] = (c >= 0 && c <= clast) ? Cprev[c] : 0.0;
+    }
+    // the profile of the owned columns waits in LDS for the final merges
+#pragma unroll
+    for (int q = 0; q < DT; ++q) lpd[lane + 64 * q] = vpd[q];
+    to_lanes(va, aj1);
+    to_lanes(vg, gj1);
+    to_lanes(vs, sj);
+    to_lanes(vv, vj);
+    // register t feeds slot t at step 0 with C(w0 - 1, j - 1) (staged from
+    // column cbase - 1, so slot t reads position lane*DT + t); register 0
+    // is shifted one lane right first, so it holds this lane's last column
+    // (position lane*DT + DT).  A re-seeded batch instead finds C(w0, j)
+    // itself (direct products) in the same buffer, staged from cbase.
+    {
+#pragma unroll
+      for (int q = 0; q < DT; ++q) lst[pos(lane + 64 * q)] = vc[q];
+      if (lane == 0) {
+        const int64_t c = cfirst + W;
+        lst[pos(W)] = (c >= 0 && c <= clast) ? Cprev[c] : 0.0;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int t = 0; t < DT; ++t) R[t] = lst[pos(lane * DT + (seed ? t : (t == 0 ? DT : t)))];
+      __syncthreads();
+    }
+  }
 #pragma unroll
   for (int t = 0; t < DT; ++t) {
     code[t] = (unsigned)(lane * DT + t);
-    const int64_t j = cbase + code[t];
-    aj1[t] = 0.0;
-    gj1[t] = 0.0;
-    sj[t] = 0.0;
-    vj[t] = kHuge;  // no candidate: halo, outside the columns, invalid
     cm[t] = kHuge;
-    if (j >= 0 && j <= jlast) {
-      if (j >= 1) {
-        aj1[t] = s.a[j - 1];
-        gj1[t] = s.g[j - 1];
-      }
-      const uint8_t f = s.flags[j];
-      sj[t] = s.isd[j];
-      if ((int)code[t] >= H && (f & 1)) vj[t] = (f & 2) ? -0.5 : 0.0;
-    }
-    // register t feeds slot t at step 0 with C(w0 - 1, j - 1); register 0
-    // is shifted one lane right first, so it holds this lane's last column.
-    // A re-seeded batch instead finds C(w0, j) itself (direct products) in
-    // the same buffer, for every column up to w0 - ez - 1.
-    if (seed) {
-      R[t] = (j >= 0 && j <= w0 - ez - 1) ? Cprev[j] : 0.0;
-    } else {
-      const int64_t src = t == 0 ? cbase + lane * DT + DT - 1 : j - 1;
-      R[t] = (src >= 0 && src <= jprev) ? Cprev[src] : 0.0;
-    }
   }
   // lane 0's left neighbour at step 0 (later its first columns are stale,
   // and none of them is owned)
@@ -252,7 +368,7 @@ __global__ void __launch_bounds__(64) k_stream_batch(StreamWork s, const Tin *__
     ts = s.isd[w];
     const uint8_t fw = s.flags[w];
     tu = (fw & 1) ? ((fw & 2) ? 0.5 : 1.0) : kHuge;
-    if (first) tc0 = s.col0[lane];
+    if (first) tc0 = s.col0[w];
   }
 
   int fb = 0;  // first step not yet flushed
@@ -323,7 +439,12 @@ __global__ void __launch_bounds__(64) k_stream_batch(StreamWork s, const Tin *__
   else run(std::false_type{});
   if (fb < B) flush(B - fb);
 
-  // C(w0 + B - 1, j) for the next batch and the column merges (owned only)
+  // C(w0 + B - 1, j) for the next batch (staged through LDS for contiguous
+  // stores) and the column merges (owned columns only).  The lane index is
+  // passed through an empty asm so that the staging addresses are computed
+  // afresh here instead of being kept in registers through the steps.
+  int lane_e = lane;
+  asm volatile("" : "+v"(lane_e));
   const int last = (B - 1) % DT;  // phase of the last step
   sfor<DT>([&](auto pc) {
     constexpr int p = decltype(pc)::value;
@@ -331,11 +452,12 @@ __global__ void __launch_bounds__(64) k_stream_batch(StreamWork s, const Tin *__
       constexpr int r0 = (DT - p) % DT;
 #pragma unroll
       for (int t = 0; t < DT; ++t) {
-        const int64_t j = cbase + code[t];
-        if ((int)code[t] >= H && j >= 0 && j <= jlast) {
-          Cnew[j] = R[(t + r0) % DT];
+        const int e = lane_e * DT + t;
+        const int64_t j = cbase + e;
+        lst[pos(e)] = R[(t + r0) % DT];
+        if (e >= H && j >= 0 && j <= jlast) {
           const double v = key_value(cm[t], kColMask);
-          if (v < 1.0e299 && v < s.Pd[j]) {
+          if (v < 1.0e299 && v < lpd[e]) {
             s.Pd[j] = v;
             I[j] = w0 + (int64_t)key_code_of(cm[t], kColMask);
           }
@@ -343,6 +465,13 @@ __global__ void __launch_bounds__(64) k_stream_batch(StreamWork s, const Tin *__
       }
     }
   });
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < DT; ++q) {
+    const int e = lane_e + 64 * q;
+    const int64_t j = cbase + e;
+    if (e >= H && j >= 0 && j <= jlast) Cnew[j] = lst[pos(e)];
+  }
 }
 
 // Row w0 + blockIdx.x: its own neighbour from the per-wave partials (strict
@@ -423,7 +552,7 @@ hipError_t stream_init_t(const StreamWork &s, const Tin *T, int64_t n, int m, in
   // cross products of the newest window with its admissible partners
   const int64_t w = l - 1, jmax = w - ez - 1;
   if (jmax >= 0)
-    hipLaunchKernelGGL((k_stream_seed<Tin>), dim3((unsigned)((jmax + 256) / 256)), b, 0, st, s, T, m, w, jmax,
+    hipLaunchKernelGGL((k_stream_seed<Tin>), dim3((unsigned)((jmax / 8 + 256) / 256)), b, 0, st, s, T, m, w, jmax,
                        s.C[w & 1]);
   return hipGetLastError();
 }
@@ -437,8 +566,8 @@ hipError_t stream_append_t(const StreamWork &s, const Tin *T, int64_t n_old, int
   const dim3 b(256);
   // statistics of the new windows, and the a/g terms of the last old window
   // (its successor sample has arrived)
-  hipLaunchKernelGGL((k_stream_stats<Tin>), dim3((unsigned)((l_new - l_old + 1 + 255) / 256)), b, 0, st, s, T,
-                     n_new, m, l_old - 1, l_new);
+  hipLaunchKernelGGL((k_stream_stats_wave<Tin>), dim3((unsigned)(l_new - l_old + 1)), dim3(64), 0, st, s, T, n_new,
+                     m, l_old);
   const int bmax = (int)std::min<int64_t>(kStreamMaxBatch, (int64_t)ez + 1);
   for (int64_t w0 = l_old; w0 < l_new;) {
     int B = (int)std::min<int64_t>(bmax, l_new - w0);
@@ -457,9 +586,8 @@ hipError_t stream_append_t(const StreamWork &s, const Tin *T, int64_t n_old, int
     const int owned = kStreamWidth - (B - 1);
     const int64_t nblocks = 1 + std::max<int64_t>(0, (jlast + 1 - kStreamWidth + owned - 1) / owned);
     const int64_t nparts = nblocks;
-    hipLaunchKernelGGL((k_stream_col0<Tin>), dim3((unsigned)B), dim3(64), 0, st, s, T, m, w0);
     if (seed && w0 - ez - 1 >= 0)  // C(w0, j) by direct products into the buffer the batch reads
-      hipLaunchKernelGGL((k_stream_seed<Tin>), dim3((unsigned)((w0 - ez - 1 + 256) / 256)), b, 0, st, s, T, m,
+      hipLaunchKernelGGL((k_stream_seed<Tin>), dim3((unsigned)(((w0 - ez - 1) / 8 + 256) / 256)), b, 0, st, s, T, m,
                          w0, w0 - ez - 1, s.C[(w0 - 1) & 1]);
     hipLaunchKernelGGL((k_stream_batch<Tin>), dim3((unsigned)nblocks), dim3(64), 0, st, s, T, m, ez, w0,
                        B, seed, (const double *)s.C[(w0 - 1) & 1], s.C[(w0 + B - 1) & 1], I, nparts);
