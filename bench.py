@@ -45,22 +45,20 @@ def log(msg):
 
 def measured_traffic():
     """HBM bytes per sweep launch from the committed rocprofv3 counter runs
-    (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the sweep
-    source has changed since they were taken."""
-    import hashlib
+    (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the sweep kernel
+    built here is not the one the counters were taken on (compared by the
+    SHA-256 of its gfx950 assembly, which the build writes next to the
+    library)."""
     rec = os.path.join(ROOT, "profiles", "k_sweep_f32_traffic.json")
-    csrc = os.path.join(ROOT, "paper_1904_12626_amd", "csrc")
+    built = os.path.join(ROOT, "paper_1904_12626_amd", "libmpx.sweep.sha256")
     try:
         with open(rec) as f:
             r = json.load(f)
-        h = hashlib.sha256()
-        for name in ("mp_sweep.hip", "mp_internal.h", "mp_types.h"):   # the kernel and what it includes
-            with open(os.path.join(csrc, name), "rb") as f:
-                h.update(f.read())
-        h = h.hexdigest()
+        with open(built) as f:
+            h = f.read().strip()
     except OSError:
         return None
-    return r["traffic_bytes_per_launch"] if r.get("sweep_source_sha256") == h else None
+    return r["traffic_bytes_per_launch"] if h and r.get("sweep_isa_sha256") == h else None
 
 
 def workload(name: str, n_override=None):

@@ -8,6 +8,7 @@ plain v_min instructions without canonicalising their inputs).
 
 from __future__ import annotations
 
+import hashlib
 import os
 import subprocess
 import sys
@@ -18,6 +19,10 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libmpx.so")
 OBJ = os.path.join(HERE, "_build")
+# SHA-256 of the sweep kernel's gfx950 assembly as built (compilation-unit
+# ids and file names left out), which ties recorded hardware counters to the
+# code they were taken on
+SWEEP_ISA = os.path.join(HERE, "libmpx.sweep.sha256")
 
 SOURCES = {
     "mp_prep.hip": [],
@@ -62,14 +67,33 @@ def build(verbose: bool = False) -> str:
             print(r.stderr, file=sys.stderr)
         return obj
 
-    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
+    def sweep_isa():
+        out = os.path.join(OBJ, "mp_sweep.gfx950.s")
+        cmd = [hipcc, *COMMON, *SOURCES["mp_sweep.hip"], "--cuda-device-only", "-S",
+               os.path.join(CSRC, "mp_sweep.hip"), "-o", out]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"hipcc -S failed for mp_sweep.hip:\n{r.stdout}\n{r.stderr}")
+        h = hashlib.sha256()
+        with open(out, "rb") as f:
+            for line in f:
+                if b"__hip_cuid" in line or line.lstrip().startswith((b".file", b".ident")):
+                    continue
+                h.update(line)
+        return h.hexdigest()
+
+    with ThreadPoolExecutor(max_workers=len(SOURCES) + 1) as ex:
+        isa = ex.submit(sweep_isa)
         objs = list(ex.map(compile_one, SOURCES.items()))
+        isa_hash = isa.result()
     tmp = LIB + ".tmp"
     cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LIB)
+    with open(SWEEP_ISA, "w") as f:
+        f.write(isa_hash + "\n")
     return LIB
 
 
