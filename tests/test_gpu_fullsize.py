@@ -262,3 +262,34 @@ def test_left_right_segmentation_chains_full():
     nxt, length, count, best = O.chains(IL, IR)
     assert np.array_equal(ch["next"].cpu().numpy(), nxt) and np.array_equal(ch["length"].cpu().numpy(), length)
     assert ch["count"] == count and ch["best"] == best
+
+
+def test_stream_append_full():
+    """The streaming benchmark: the FP64 stream of the first n - 8192 samples
+    of the n=2^20 planted walk (m=256, ez=64), then the last 8192 samples
+    appended 512 at a time (batches of up to 63 windows across ~2300
+    workgroups, re-seeds included).  Sampled appended rows, random old rows
+    and old rows whose neighbour is now an appended window, against the
+    oracle on the grown series."""
+    import paper_1904_12626_amd as mpx
+    pw, ez = W.selfjoin_large()
+    m = pw.m
+    T = pw.T
+    n = T.size
+    n0 = n - 8192
+    s = mpx.SelfJoinStream(torch.from_numpy(T[:n0]).to(DEV), m, ez, n_max=n)
+    for a in range(n0, n, 512):
+        s.append(torch.from_numpy(T[a:a + 512]).to(DEV))
+    P, I = _np(s.P), _np(s.I)
+    l, l0 = n - m + 1, n0 - m + 1
+    assert P.size == l
+    rng = np.random.default_rng(8)
+    moved = np.nonzero(I[:l0] >= l0)[0]         # old rows that took an appended window
+    rows = np.unique(np.concatenate([rng.choice(np.arange(l0, l), 24, replace=False),
+                                     rng.choice(l0, 24, replace=False),
+                                     rng.permutation(moved)[:16]]))
+    T64 = T.astype(np.float64)
+    Po, Io = cimpl.selfjoin_rows(T64, m, ez, rows)
+    compare_profile(T64, m, P[rows], I[rows], Po, Io, 1e-6, ez=None, where="stream")
+    assert np.all(np.abs(I[rows] - rows) > ez)
+    assert moved.size > 0
