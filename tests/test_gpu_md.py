@@ -132,3 +132,29 @@ def test_simple_abjoin_float32_and_short_series():
     _compare(out[0], out[1], Po, Io, lambda i, j: _simple_dist(A64, i, B64, j, m), 1e-6, where="ab")
     Po, Io = O.simple_join(B64, m, TB=A64)
     _compare(out[2], out[3], Po, Io, lambda i, j: _simple_dist(B64, i, A64, j, m), 1e-6, where="ba")
+
+
+@pytest.mark.parametrize("mode", ["simple", "multi"])
+def test_benchmark_size_sampled_rows(mode):
+    """The benchmark's multidimensional join (3-dimensional float32 walk,
+    n=2^18, m=128, ez=32: thousands of strips of several diagonals per lane)
+    on sampled rows against the oracle, plus invariants on every row."""
+    import paper_1904_12626_amd as mpx
+    n, m, ez = 1 << 18, 128, 32
+    T = np.cumsum(np.random.default_rng(7).standard_normal((3, n)), axis=1).astype(np.float32)
+    P, I = [x.cpu().numpy() for x in mpx.mdjoin(torch.from_numpy(T).to(DEV), m, ez, mode=mode)]
+    T64 = T.astype(np.float64)
+    l = n - m + 1
+    rows = np.sort(np.random.default_rng(9).choice(l, 8, replace=False))
+    if mode == "simple":
+        assert np.all(np.isfinite(P)) and np.all(np.abs(I - np.arange(l)) > ez)
+        Po, Io = O.simple_join(T64, m, ez, rows=rows)
+        _compare(P[rows], I[rows], Po[rows], Io[rows], lambda i, j: _simple_dist(T64, i, T64, j, m), 1e-6, ez,
+                 "simple")
+    else:
+        assert np.all(np.isfinite(P)) and np.all(np.abs(I - np.arange(l)[None, :]) > ez)
+        assert np.all(np.diff(P, axis=0) >= -1e-3)   # mean of the k smallest grows with k
+        Po, Io = O.mstomp(T64, m, ez, rows=rows)
+        for k in range(3):
+            _compare(P[k][rows], I[k][rows], Po[k][rows], Io[k][rows],
+                     lambda i, j, k=k: _multi_dist(T64, i, j, m, k + 1), 1e-6, ez, f"k={k + 1}")
