@@ -45,9 +45,9 @@ def log(msg):
 
 def measured_traffic():
     """HBM bytes per sweep launch from the committed rocprofv3 counter runs
-    (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the sweep kernel
-    built here is not the one the counters were taken on (compared by the
-    SHA-256 of its gfx950 assembly, which the build writes next to the
+    (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the FP32 sweep
+    kernel built here is not the one the counters were taken on (compared by
+    the SHA-256 of its gfx950 assembly, which the build writes next to the
     library)."""
     rec = os.path.join(ROOT, "profiles", "k_sweep_f32_traffic.json")
     built = os.path.join(ROOT, "paper_1904_12626_amd", "libmpx.sweep.sha256")

@@ -10,6 +10,7 @@ from __future__ import annotations
 
 import hashlib
 import os
+import re
 import subprocess
 import sys
 from concurrent.futures import ThreadPoolExecutor
@@ -19,9 +20,9 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libmpx.so")
 OBJ = os.path.join(HERE, "_build")
-# SHA-256 of the sweep kernel's gfx950 assembly as built (compilation-unit
-# ids and file names left out), which ties recorded hardware counters to the
-# code they were taken on
+# SHA-256 of the FP32 sweep kernels' gfx950 assembly as built (the function
+# bodies of every k_sweep<float, ...> instantiation, compilation-unit ids left
+# out), which ties recorded hardware counters to the code they were taken on
 SWEEP_ISA = os.path.join(HERE, "libmpx.sweep.sha256")
 
 SOURCES = {
@@ -75,11 +76,16 @@ def build(verbose: bool = False) -> str:
         if r.returncode != 0:
             raise RuntimeError(f"hipcc -S failed for mp_sweep.hip:\n{r.stdout}\n{r.stderr}")
         h = hashlib.sha256()
+        inside = False
         with open(out, "rb") as f:
-            for line in f:
-                if b"__hip_cuid" in line or line.lstrip().startswith((b".file", b".ident")):
-                    continue
-                h.update(line)
+            for line in f.read().split(b"\n"):
+                if re.match(rb"^_ZN3mpx7k_sweepIf\w*:", line):
+                    inside = True
+                if inside:
+                    if not (b"__hip_cuid" in line or line.lstrip().startswith((b".file", b".ident"))):
+                        h.update(line + b"\n")
+                    if line.startswith(b".Lfunc_end"):
+                        inside = False
         return h.hexdigest()
 
     with ThreadPoolExecutor(max_workers=len(SOURCES) + 1) as ex:

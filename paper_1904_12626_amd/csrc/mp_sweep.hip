@@ -60,6 +60,16 @@ __device__ __forceinline__ double shl1d(double v, double fill) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// Wave shift of a double with lane 63 keeping `in63` (its DPP source is out
+// of range, so that lane is not written): one DPP move per dword.
+__device__ __forceinline__ double shl_keep63(double in63, double v) {
+  const long long b = __double_as_longlong(v), f = __double_as_longlong(in63);
+  const int lo = __builtin_amdgcn_update_dpp((int)(f & 0xffffffffll), (int)(b & 0xffffffffll), 0x130, 0xF, 0xF,
+                                             false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(f >> 32), (int)(b >> 32), 0x130, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 __device__ __forceinline__ int64_t rfl64(int64_t v) {
   const int lo = __builtin_amdgcn_readfirstlane((int)(v & 0xffffffff));
   const int hi = __builtin_amdgcn_readfirstlane((int)(v >> 32));
@@ -319,6 +329,79 @@ __global__ void __launch_bounds__(64, (SweepMinWaves<F, DT>::value))
       __syncthreads();
     };
 
+    if constexpr (std::is_same_v<F, double>) {
+      // FP64: one row at a time (there is no 3-input FP64 minimum, so row
+      // pairs would only hold a second key array), and the column entering
+      // at lane 63 is read from LDS as the DPP fallback operand instead of
+      // being written into the lane from a scalar register.  Each block's
+      // entering columns are prefetched one block ahead (lane u holds row
+      // u's) and staged into LDS between the two barriers of the flush.
+      __shared__ double lnew[TP][3];
+      double pa = 0.0, pg = 0.0, ps = 0.0;
+      auto prefetch = [&](int64_t sb2) {
+        if (lane < TP && sb2 + lane < nsteps) {
+          const V4 v = newcol[sb2 + lane];
+          pa = v.x;
+          pg = v.y;
+          ps = v.z;
+        }
+      };
+      auto stage = [&]() {
+        if (lane < TP) {
+          lnew[lane][0] = pa;
+          lnew[lane][1] = pg;
+          lnew[lane][2] = ps;
+        }
+      };
+      prefetch(0);
+      stage();
+      prefetch(TP);
+      __syncthreads();
+      for (int64_t sb = 0; sb < nsteps; sb += TP) {
+        const int nb = (int)min((int64_t)TP, nsteps - sb);  // a multiple of DT
+        static_for<TP>([&](auto uc) {
+          constexpr int u = decltype(uc)::value;
+          constexpr int r0 = u % DT;  // register of slot 0
+          if (u < nb) {
+            K k[DT];
+            const V4 rd = ldu(rowd + i0 + sb + u);
+            const F ai = rd.x, gi = rd.y, si = rd.z, ui = rd.w;
+            static_for<DT>([&](auto tc) {
+              constexpr int t = decltype(tc)::value;
+              constexpr int p = (t + r0) % DT;
+              k[t] = IK::make(fma(-(C[t] * si), S[p], ui), (unsigned)(lane * DT + t));
+              C[t] = fma(A[p], gi, C[t]);
+              C[t] = fma(G[p], ai, C[t]);
+            });
+            lrow[u][lane] = IK::rowmin(k);
+            // register p met slot p - r0
+            static_for<DT>([&](auto pc) {
+              constexpr int q = decltype(pc)::value;
+              CP[q] = IK::kmin(CP[q], k[(q - r0 + DT) % DT]);
+            });
+            if (lane == 0) lcol[u] = CP[r0];
+            CP[r0] = IK::shl(CP[r0]);
+            A[r0] = shl_keep63(lnew[u][0], A[r0]);
+            G[r0] = shl_keep63(lnew[u][1], G[r0]);
+            S[r0] = shl_keep63(lnew[u][2], S[r0]);
+          }
+        });
+        // flush, with the next block's entering columns staged between the
+        // barriers (every read of this block's is done)
+        __syncthreads();
+        if (lane < nb) {
+          K best = lrow[lane][0];
+#pragma unroll 8
+          for (int q = 1; q < 64; ++q) best = IK::kmin(best, lrow[lane][q]);
+          const int64_t s = sb + lane;
+          if (s < nr) emit_row(i0 + s, best);
+          emit_col(i0 + s + k0, lcol[lane]);
+        }
+        stage();
+        prefetch(sb + 2 * TP);
+        __syncthreads();
+      }
+    } else {
     // Rows are processed in pairs: a column register receives one cell from
     // each row of the pair, so its minimum is a single 3-input min, and each
     // row's own minimum is a chain of 3-input mins.
@@ -383,6 +466,7 @@ __global__ void __launch_bounds__(64, (SweepMinWaves<F, DT>::value))
         }
       });
       flush(sb, nb);
+    }
     }
 
     // columns still in flight after the last row: slot t of lane L holds the
