@@ -161,7 +161,7 @@ void finish_job(Job &j) {
 }
 
 struct Layout {
-  size_t mu, sig, keys, flags, nc, nv, rc, special, counters, segp, segs, rescan, sdesc, wdesc, kmask;
+  size_t mu, sig, keys, flags, nc, nv, rc, special, counters, segp, segs, segq, rescan, sdesc, wdesc, kmask;
   size_t b_mu, b_isig, b_wpos, b_coef, b_nbr, b_count, b_fill, b_off, b_tmp, b_erec, b_wrec, b_chunk;
   size_t total;
 };
@@ -186,6 +186,7 @@ Layout layout_of(const Job &j, bool with_batch_tables) {
   L.counters = take(8 * 4);
   L.segp = take(8 * ((size_t)j.nseg + 1));
   L.segs = take(4 * std::max<size_t>(1, (size_t)j.nseg));
+  L.segq = take(8 * ((size_t)j.nseg + 1));
   L.rescan = take(8 * tl);
   if (with_batch_tables) {
     L.b_mu = take(8 * tl);
@@ -222,6 +223,7 @@ mpx::Work work_of(const Layout &L, void *ws) {
   w.counters = (unsigned long long *)(b + L.counters);
   w.seg_prefix = (int64_t *)(b + L.segp);
   w.seg_sweep = (int32_t *)(b + L.segs);
+  w.seg_part = (int64_t *)(b + L.segq);
   w.rescan = (int64_t *)(b + L.rescan);
   return w;
 }

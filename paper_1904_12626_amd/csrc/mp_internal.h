@@ -79,8 +79,12 @@ struct Work {
   void *rc;            // [total_rc] row/column data {a, g, s, u} (F4)
   int32_t *special;    // [nseries] bit0 has invalid windows, bit1 has constant
   unsigned long long *counters;  // [4]: 0 tile counter, 1 rescan count
-  int64_t *seg_prefix; // [nseg + 1] first tile of each strip
+  int64_t *seg_prefix; // [nseg + 1] first tile of each strip; with seg_part,
+                       // the full-height tiles before each strip
   int32_t *seg_sweep;  // [nseg] sweep of each strip
+  int64_t *seg_part;   // [nseg + 1] strips with a shorter last tile before each
+                       // strip (those tiles are numbered after every full
+                       // one), or null: all tiles in strip order
   int64_t *rescan;     // [total_l] windows needing an exact row scan
 };
 

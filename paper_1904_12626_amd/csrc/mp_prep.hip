@@ -11,46 +11,67 @@ namespace mpx {
 // ------------------------------------------------------------------ plan
 // Strip g of sweep s covers diagonals [k_lo + (g - seg_base) * W, +W); its
 // longest diagonal has min(l_rows, l_cols - k0) cells, cut into tiles of R
-// rows.  One workgroup writes the first tile of every strip (an exclusive
-// prefix sum) and clears the per-call counters.
+// rows.  One workgroup writes the tile table (exclusive prefix sums) and
+// clears the per-call counters.  Without seg_part the tiles are numbered
+// strip by strip; with it, every full-height tile comes first (strip by
+// strip) and the shorter last tiles of the strips after them, so that the
+// persistent grid ends on short tiles (longest first).
 __global__ void __launch_bounds__(1024) k_plan(Plan plan, Work w, int W, int R, int64_t nseg) {
-  __shared__ int64_t part[1024];
+  __shared__ int64_t part[1024], part2[1024];
   const int tid = threadIdx.x;
   if (tid < 4) w.counters[tid] = 0;
   for (int s = tid; s < plan.nseries; s += blockDim.x) w.special[s] = 0;
+  const bool lpt = w.seg_part != nullptr;
 
   const int64_t per = (nseg + blockDim.x - 1) / blockDim.x;
   const int64_t a = min(nseg, (int64_t)tid * per), b = min(nseg, a + per);
   int sw = 0;
-  auto tiles_of = [&](int64_t g, int &swi) -> int64_t {
+  // (full-height tiles, shorter last tile) of strip g, or (all tiles, 0)
+  auto tiles_of = [&](int64_t g, int &swi, int64_t &t2) -> int64_t {
     while (swi + 1 < plan.nsweeps && plan.sweep(swi + 1).seg_base <= g) ++swi;
     const SweepDesc d = plan.sweep(swi);
     const SeriesDesc rs = plan.series(d.rs), cs = plan.series(d.cs);
     const int64_t k0 = d.k_lo + (g - d.seg_base) * (int64_t)W;
     const int64_t L = min(rs.l, cs.l - k0);
-    return (L + R - 1) / R;
+    if (!lpt) {
+      t2 = 0;
+      return (L + R - 1) / R;
+    }
+    t2 = (L % R) != 0 ? 1 : 0;
+    return L / R;
   };
-  int64_t sum = 0;
-  for (int64_t g = a; g < b; ++g) sum += tiles_of(g, sw);
+  int64_t sum = 0, sum2 = 0;
+  for (int64_t g = a; g < b; ++g) {
+    int64_t t2;
+    sum += tiles_of(g, sw, t2);
+    sum2 += t2;
+  }
   part[tid] = sum;
+  part2[tid] = sum2;
   __syncthreads();
   if (tid == 0) {
-    int64_t run = 0;
+    int64_t run = 0, run2 = 0;
     for (int q = 0; q < (int)blockDim.x; ++q) {
-      const int64_t v = part[q];
+      const int64_t v = part[q], v2 = part2[q];
       part[q] = run;
+      part2[q] = run2;
       run += v;
+      run2 += v2;
     }
     w.seg_prefix[nseg] = run;
+    if (lpt) w.seg_part[nseg] = run2;
   }
   __syncthreads();
-  int64_t run = part[tid];
+  int64_t run = part[tid], run2 = part2[tid];
   sw = 0;
   for (int64_t g = a; g < b; ++g) {
-    const int64_t t = tiles_of(g, sw);
+    int64_t t2;
+    const int64_t t = tiles_of(g, sw, t2);
     w.seg_prefix[g] = run;
     w.seg_sweep[g] = sw;
+    if (lpt) w.seg_part[g] = run2;
     run += t;
+    run2 += t2;
   }
 }
 

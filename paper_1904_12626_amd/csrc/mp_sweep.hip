@@ -195,7 +195,8 @@ template <typename F, typename Tin, int DT, int TP>
 __global__ void __launch_bounds__(64, (SweepMinWaves<F, DT>::value))
     k_sweep(const Plan plan, const typename FTraits<F>::V4 *__restrict__ rcb,
             const double *__restrict__ mu, const int64_t *__restrict__ seg_prefix,
-            const int32_t *__restrict__ seg_sweep, const SeriesDesc *__restrict__ s_ext,
+            const int32_t *__restrict__ seg_sweep, const int64_t *__restrict__ seg_part,
+            const SeriesDesc *__restrict__ s_ext,
             const SweepDesc *__restrict__ w_ext, uint64_t *__restrict__ keys,
             unsigned long long *__restrict__ counter, const Tin *__restrict__ Tb, const int R,
             const int64_t total_tiles, const int64_t nseg) {
@@ -218,18 +219,23 @@ __global__ void __launch_bounds__(64, (SweepMinWaves<F, DT>::value))
     tile = rfl64(tile);
     if (tile >= total_tiles) break;
 
-    // ---- decode the tile: strip g (binary search of the tile table)
+    // ---- decode the tile: strip g (binary search of the tile table; the
+    // full-height tiles of all strips first, then their shorter last tiles)
+    const int64_t nfull = ldu(seg_prefix + nseg);
+    const bool tail = tile >= nfull;
+    const int64_t *const table = tail ? seg_part : seg_prefix;
+    const int64_t key = tail ? tile - nfull : tile;
     int64_t lo = 0, hi = nseg - 1;
     while (lo < hi) {
       const int64_t mid = (lo + hi + 1) >> 1;
-      if (ldu(seg_prefix + mid) <= tile) lo = mid; else hi = mid - 1;
+      if (ldu(table + mid) <= key) lo = mid; else hi = mid - 1;
     }
     const int64_t g = lo;
     const SweepDesc d = sweep(ldu(seg_sweep + g));
     const SeriesDesc RS = series(d.rs), CS = series(d.cs);
     const int64_t k0 = rfl64(d.k_lo + (g - d.seg_base) * (int64_t)W);
     const int64_t L = min(RS.l, CS.l - k0);
-    const int64_t i0 = rfl64((tile - ldu(seg_prefix + g)) * (int64_t)R);
+    const int64_t i0 = rfl64(tail ? (L / R) * (int64_t)R : (tile - ldu(seg_prefix + g)) * (int64_t)R);
     const int64_t nr = min((int64_t)R, L - i0);
     const int64_t lc = CS.l;
     // Cells outside the join read padding records: rows >= l_r give huge
@@ -508,7 +514,8 @@ hipError_t launch_sweep(const Plan &plan, const Work &w, const void *T, bool t_f
 #define MPX_LAUNCH(F, TIN, DT, TP)                                                              \
   hipLaunchKernelGGL((k_sweep<F, TIN, DT, TP>), grd, blk, 0, st, plan,                         \
                      (const typename FTraits<F>::V4 *)w.rc, (const double *)w.mu,              \
-                     (const int64_t *)w.seg_prefix, (const int32_t *)w.seg_sweep, plan.s_ext,   \
+                     (const int64_t *)w.seg_prefix, (const int32_t *)w.seg_sweep,               \
+                     (const int64_t *)w.seg_part, plan.s_ext,                                  \
                      plan.w_ext, w.keys, w.counters, (const TIN *)T, R, total_tiles, nseg)
   if (f64_sweep) {
     if (t_f64) MPX_LAUNCH(double, double, 8, 32);
