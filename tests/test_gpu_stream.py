@@ -49,3 +49,22 @@ def test_stream_degenerate_windows():
         n += k
         Po, Io = O.selfjoin(T[:n], m, ez)
         compare_profile(T[:n], m, s.P.cpu().numpy(), s.I.cpu().numpy(), Po, Io, 1e-9, ez=ez, where=f"n={n}")
+
+
+@pytest.mark.parametrize("ez,chunks", [(0, (1, 5, 3, 64, 2)), (2, (9, 1, 40)), (70, (200, 333))])
+def test_stream_batch_shapes(ez, chunks):
+    """Batch sizes from one window (ez = 0: no halo) to several workgroups
+    with a halo, and a window longer than the first strip."""
+    import paper_1904_12626_amd as mpx
+    rng = np.random.default_rng(172 + ez)
+    m = 8 if ez < 70 else 96
+    n0 = 700
+    n_total = n0 + sum(chunks)
+    T = np.cumsum(rng.standard_normal(n_total))
+    s = mpx.SelfJoinStream(torch.from_numpy(T[:n0]).to(DEV), m, ez, n_max=n_total)
+    n = n0
+    for k in chunks:
+        s.append(torch.from_numpy(T[n:n + k]).to(DEV))
+        n += k
+        Po, Io = cimpl.selfjoin(T[:n], m, ez)
+        compare_profile(T[:n], m, s.P.cpu().numpy(), s.I.cpu().numpy(), Po, Io, 1e-9, ez=ez, where=f"n={n}")
