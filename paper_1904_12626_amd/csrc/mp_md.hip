@@ -60,27 +60,6 @@ __device__ __forceinline__ T ldu_md(const T *p) {
 #endif
 }
 
-// Minimum over the wave of a 32-bit value, returned wave-uniform: a
-// reduction inside each row of 16 lanes by DPP row shifts (lane 15 of a row
-// ends with the row's minimum), then the four row minima on the scalar unit.
-__device__ __forceinline__ unsigned wave_min_u32(unsigned v) {
-  v = min(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x111 /* row_shr:1 */, 0xF, 0xF, false));
-  v = min(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x112 /* row_shr:2 */, 0xF, 0xF, false));
-  v = min(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x114 /* row_shr:4 */, 0xF, 0xF, false));
-  v = min(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x118 /* row_shr:8 */, 0xF, 0xF, false));
-  const unsigned r0 = __builtin_amdgcn_readlane(v, 15), r1 = __builtin_amdgcn_readlane(v, 31);
-  const unsigned r2 = __builtin_amdgcn_readlane(v, 47), r3 = __builtin_amdgcn_readlane(v, 63);
-  return min(min(r0, r1), min(r2, r3));
-}
-
-// Lane L takes lane L+1's value; lane 63 takes `fill` (wave-uniform).
-__device__ __forceinline__ unsigned shift_down1(unsigned v, unsigned fill) {
-  int x = __builtin_amdgcn_update_dpp((int)v, (int)v, 0x130 /* wave_shl:1 */, 0xF, 0xF, false);
-  const int f = __builtin_amdgcn_readfirstlane((int)fill);
-  asm volatile("v_writelane_b32 %0, %1, 63" : "+v"(x) : "s"(f));
-  return (unsigned)x;
-}
-
 __device__ __forceinline__ unsigned long long pack_md(float v, int64_t idx) {
   v = v > 0.0f ? v : 0.0f;
   return ((unsigned long long)__float_as_uint(v) << 32) | (unsigned long long)(uint32_t)idx;

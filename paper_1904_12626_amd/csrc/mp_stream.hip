@@ -414,7 +414,7 @@ __global__ void __launch_bounds__(64) k_stream_batch(StreamWork s, const Tin *__
           }
           int lim = W;
           if constexpr (RAMP) lim = (int)min(max(w - ez - 1 - cbase, (int64_t)-1), (int64_t)W);
-          double rmin = kHuge;
+          double rk[DT];
 #pragma unroll
           for (int t = 0; t < DT; ++t) {
             double &C = R[(t + r0) % DT];
@@ -423,9 +423,13 @@ __global__ void __launch_bounds__(64) k_stream_batch(StreamWork s, const Tin *__
             if constexpr (RAMP) {
               if ((int)code[t] > lim) key = kHuge;  // not yet admissible
             }
-            rmin = kmin(rmin, key_code(key, code[t], kRowMask));
+            rk[t] = key_code(key, code[t], kRowMask);
             cm[t] = kmin(cm[t], key_code63(key, (unsigned)b));
           }
+          // the lane's row minimum as a tree (depth 3, not a chain of 8)
+          static_assert(DT == 8, "tree below");
+          const double rmin = kmin(kmin(kmin(rk[0], rk[1]), kmin(rk[2], rk[3])),
+                                   kmin(kmin(rk[4], rk[5]), kmin(rk[6], rk[7])));
           lrow[b & 15][lane] = rmin;
           if ((b & 15) == 15) {
             flush(16);
