@@ -12,7 +12,8 @@
 // candidate of another in the same batch): a one-wave workgroup owns
 // 64*8 - (B-1) consecutive columns and also recomputes the B-1 columns to
 // their left, whose cross products it needs (a trapezoid: after step b the
-// leftmost b columns hold stale values, and none of them is owned).  Each
+// leftmost b columns hold stale values, and none of them is owned); the
+// first workgroup, which starts at column 0, owns all 64*8 of its columns.  Each
 // lane keeps its eight columns' terms in registers for all B rows and the
 // cross products move right through registers and one DPP shift per step,
 // so a column's data is read once per batch and no step needs a barrier.
