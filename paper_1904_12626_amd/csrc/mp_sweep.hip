@@ -16,7 +16,8 @@
 // move one lane down per row: slot t at row i+1 reads the column slot t+1
 // held at row i, so slots rotate through registers (full unroll by DT) and
 // the last slot receives lane L+1's first slot through a DPP wave shift;
-// lane 63 receives the one new column from a scalar load.  Column minima
+// lane 63 receives the one new column from a scalar load (the FP64 sweep
+// reads it from LDS as the DPP fallback value instead).  Column minima
 // travel the same way and leave the strip through lane 0.
 //
 // Per cell: key = u_i - (C s_i) s_j  (= 1 - Pearson rho for valid windows),
