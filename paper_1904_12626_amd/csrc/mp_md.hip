@@ -277,7 +277,6 @@ __global__ void __launch_bounds__(64) k_md_sweep(const Plan plan, const Tin *__r
 
   __shared__ double lrow[NP][TP][65];  // per row, each lane's minimum over its slots
   __shared__ double lcol[NP][TP];      // column minima leaving the strip through lane 0
-  __shared__ double lpart[NP][64];     // partial row minima of the reduction
   __shared__ double lfresh[TP][NF];    // records of the columns entering at lane 63
 
   const int lane = threadIdx.x;
@@ -501,8 +500,10 @@ __global__ void __launch_bounds__(64) k_md_sweep(const Plan plan, const Tin *__r
         for (int q = 0; q < NP; ++q) CM[r0][q] = md_shl1d(CM[r0][q], kBig);
       });
       // ---- rows sb .. sb+TP-1: the 64 lane minima of each row in two
-      // passes (TP per lane, then 64/TP per row), then the merges
+      // passes (TP per lane, then 64/TP per row; the partials go back into
+      // the row buffer, which keeps the LDS per wave small), then the merges
       __syncthreads();
+      double part[NP];
       {
         const int r = lane % TP, g0 = (lane / TP) * TP;
 #pragma unroll
@@ -510,9 +511,13 @@ __global__ void __launch_bounds__(64) k_md_sweep(const Plan plan, const Tin *__r
           double best = lrow[q][r][g0];
 #pragma unroll
           for (int e = 1; e < TP; ++e) best = kmin_f64(best, lrow[q][r][g0 + e]);
-          lpart[q][lane] = best;
+          part[q] = best;
         }
       }
+      __syncthreads();
+      double *const lpart = &lrow[0][0][0];  // [NP][64] partials
+#pragma unroll
+      for (int q = 0; q < NP; ++q) lpart[q * 64 + lane] = part[q];
       // the next block's entering columns (every read of this block's is done)
       stage();
       prefetch(sb + 2 * TP);
@@ -520,9 +525,9 @@ __global__ void __launch_bounds__(64) k_md_sweep(const Plan plan, const Tin *__r
       if (lane < TP) {
 #pragma unroll
         for (int q = 0; q < NP; ++q) {
-          double best = lpart[q][lane];
+          double best = lpart[q * 64 + lane];
 #pragma unroll
-          for (int e = 1; e < 64 / TP; ++e) best = kmin_f64(best, lpart[q][lane + e * TP]);
+          for (int e = 1; e < 64 / TP; ++e) best = kmin_f64(best, lpart[q * 64 + lane + e * TP]);
           const int64_t s = sb + lane;
           if (s < nr) emit_row(q, i0 + s, best);
           emit_col(q, i0 + s + k0, lcol[q][lane]);
