@@ -399,36 +399,60 @@ __global__ void __launch_bounds__(256)
     if (i >= 0 && (arg < 0 || v < best || (v == best && i < arg))) { best = v; arg = i; }
   }
   reduce();
+  // The chosen pair, re-measured in FP64 by the whole workgroup (each sum,
+  // minimum and maximum over the m samples is a tree over the threads).
+  const int64_t i = bi[0];
+  const int64_t j = (i >= 0) ? I[i] : -1;
+  __syncthreads();
+  auto bred = [&](double v, int op) -> double {  // 0 sum, 1 min, 2 max
+    bv[tid] = v;
+    __syncthreads();
+    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+      if (tid < h) {
+        const double a = bv[tid], b = bv[tid + h];
+        bv[tid] = op == 0 ? a + b : (op == 1 ? fmin(a, b) : fmax(a, b));
+      }
+      __syncthreads();
+    }
+    const double r = bv[0];
+    __syncthreads();
+    return r;
+  };
+  double d = INFINITY;
+  if (i >= 0 && j >= 0) {
+    auto stats = [&](int64_t w, double &mu, double &sg, bool &cst) {
+      double s = 0.0, lo = INFINITY, hi = -INFINITY;
+      for (int u = tid; u < m; u += blockDim.x) {
+        const double v = sample(T + w + u);
+        lo = fmin(lo, v);
+        hi = fmax(hi, v);
+        s += v;
+      }
+      mu = bred(s, 0) / m;
+      lo = bred(lo, 1);
+      hi = bred(hi, 2);
+      double qq = 0.0;
+      for (int u = tid; u < m; u += blockDim.x) {
+        const double dv = sample(T + w + u) - mu;
+        qq = fma(dv, dv, qq);
+      }
+      sg = sqrt(bred(qq, 0) / m);
+      cst = (lo == hi);
+    };
+    double mi, si, mj, sj;
+    bool ci, cj;
+    stats(i, mi, si, ci);
+    stats(j, mj, sj, cj);
+    const double ia = ci ? 0.0 : 1.0 / si, ib = cj ? 0.0 : 1.0 / sj;
+    double acc = 0.0;
+    for (int u = tid; u < m; u += blockDim.x) {
+      const double e = (sample(T + i + u) - mi) * ia - (sample(T + j + u) - mj) * ib;
+      acc = fma(e, e, acc);
+    }
+    d = sqrt(bred(acc, 0));
+  }
   if (tid == 0) {
     st->ticket = 0;
-    const int64_t i = bi[0];
-    const int64_t j = (i >= 0) ? I[i] : -1;
-    double d = INFINITY;
-    if (i >= 0 && j >= 0) {
-      auto stats = [&](int64_t w, double &mu, double &sg, bool &cst) {
-        double s = 0.0, lo = 0.0, hi = 0.0;
-        for (int u = 0; u < m; ++u) {
-          const double v = sample(T + w + u);
-          if (u == 0) { lo = v; hi = v; }
-          lo = fmin(lo, v);
-          hi = fmax(hi, v);
-          s += v;
-        }
-        mu = s / m;
-        double qq = 0.0;
-        for (int u = 0; u < m; ++u) {
-          const double dv = sample(T + w + u) - mu;
-          qq = fma(dv, dv, qq);
-        }
-        sg = sqrt(qq / m);
-        cst = (lo == hi);
-      };
-      double mi, si, mj, sj;
-      bool ci, cj;
-      stats(i, mi, si, ci);
-      stats(j, mj, sj, cj);
-      d = pair_dist64(T + i, mi, si, ci, T + j, mj, sj, cj, m);
-    }
     if (!discord) {
       const bool ok = (i >= 0 && j >= 0);
       out_idx[2 * q] = ok ? i : -1;
