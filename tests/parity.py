@@ -11,7 +11,7 @@ import numpy as np
 from oracle import mp_oracle as O
 
 
-def compare_profile(TA, m, P, I, Po, Io, tol, TB=None, ez=None, where=""):
+def compare_profile(TA, m, P, I, Po, Io, tol, TB=None, ez=None, where="", rows=None):
     P = np.asarray(P, dtype=np.float64)
     I = np.asarray(I)
     Po = np.asarray(Po, dtype=np.float64)
@@ -25,10 +25,11 @@ def compare_profile(TA, m, P, I, Po, Io, tol, TB=None, ez=None, where=""):
     assert maxd <= tol, f"{where}: max |dP| = {maxd} > {tol} at {np.nonzero(fin_o)[0][np.argmax(d)]}"
     diff = np.nonzero(fin_o & (I != Io))[0]
     for i in diff:
+        row = int(rows[i]) if rows is not None else int(i)
         j = int(I[i])
-        assert j >= 0, f"{where}: row {i} has no index"
+        assert j >= 0, f"{where}: row {row} has no index"
         if ez is not None:
-            assert abs(int(i) - j) > ez, f"{where}: row {i} index {j} inside the exclusion zone"
-        dj = O.pair_distance(TA, int(i), TB, j, m)
-        assert dj <= Po[i] + tol, f"{where}: row {i}: GPU index {j} at {dj} vs oracle {Io[i]} at {Po[i]}"
+            assert abs(row - j) > ez, f"{where}: row {row} index {j} inside the exclusion zone"
+        dj = O.pair_distance(TA, row, TB, j, m)
+        assert dj <= Po[i] + tol, f"{where}: row {row}: GPU index {j} at {dj} vs oracle {Io[i]} at {Po[i]}"
     return maxd, int(diff.size)

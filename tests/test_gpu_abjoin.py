@@ -51,7 +51,7 @@ def test_abjoin_ecg_like():
     A64, B64 = A.astype(np.float64), B.astype(np.float64)
     rows = np.random.default_rng(0).choice(A.size - m + 1, 300, replace=False)
     Po, Io = cimpl.abjoin_rows(A64, B64, m, rows)
-    compare_profile(A64, m, Pab[rows], Iab[rows], Po, Io, tol, TB=B64)
+    compare_profile(A64, m, Pab[rows], Iab[rows], Po, Io, tol, TB=B64, rows=rows)
     # compare_profile works row by row on the listed rows only
     cols = np.random.default_rng(1).choice(B.size - m + 1, 300, replace=False)
     Po, Io = cimpl.abjoin_rows(B64, A64, m, cols)

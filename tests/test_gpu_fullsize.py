@@ -290,6 +290,6 @@ def test_stream_append_full():
                                      rng.permutation(moved)[:16]]))
     T64 = T.astype(np.float64)
     Po, Io = cimpl.selfjoin_rows(T64, m, ez, rows)
-    compare_profile(T64, m, P[rows], I[rows], Po, Io, 1e-6, ez=None, where="stream")
+    compare_profile(T64, m, P[rows], I[rows], Po, Io, 1e-6, ez=None, where="stream", rows=rows)
     assert np.all(np.abs(I[rows] - rows) > ez)
     assert moved.size > 0

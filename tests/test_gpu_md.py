@@ -20,10 +20,11 @@ def _multi_dist(T, i, j, m, k):
     return float(ds[:k].mean())
 
 
-def _compare(P, I, Po, Io, dist, rtol, ez=None, where=""):
+def _compare(P, I, Po, Io, dist, rtol, ez=None, where="", rows=None):
     """P within rtol (relative, 1e-12 absolute floor); a different index is
     accepted when admissible and its exact distance is within the tolerance
-    of the oracle's minimum (near-ties)."""
+    of the oracle's minimum (near-ties).  With `rows`, entry e of the arrays
+    belongs to window rows[e]."""
     P, I = np.asarray(P, dtype=np.float64), np.asarray(I)
     fin = np.isfinite(Po)
     assert np.array_equal(np.isfinite(P), fin), where
@@ -31,10 +32,11 @@ def _compare(P, I, Po, Io, dist, rtol, ez=None, where=""):
     tol = rtol * np.maximum(1.0, np.abs(Po[fin]))
     assert np.all(np.abs(P[fin] - Po[fin]) <= tol), (where, np.max(np.abs(P[fin] - Po[fin])))
     for i in np.nonzero(fin & (I != Io))[0]:
+        row = int(rows[i]) if rows is not None else int(i)
         j = int(I[i])
         if ez is not None:
-            assert abs(int(i) - j) > ez, where
-        assert dist(int(i), j) <= Po[i] * (1 + rtol) + 1e-12, (where, i, j, Io[i])
+            assert abs(row - j) > ez, where
+        assert dist(row, j) <= Po[i] * (1 + rtol) + 1e-12, (where, row, j, Io[i])
 
 
 @pytest.mark.parametrize("D,dtype", [(1, np.float64), (3, np.float64), (2, np.float32), (5, np.float64)])
@@ -150,11 +152,11 @@ def test_benchmark_size_sampled_rows(mode):
         assert np.all(np.isfinite(P)) and np.all(np.abs(I - np.arange(l)) > ez)
         Po, Io = O.simple_join(T64, m, ez, rows=rows)
         _compare(P[rows], I[rows], Po[rows], Io[rows], lambda i, j: _simple_dist(T64, i, T64, j, m), 1e-6, ez,
-                 "simple")
+                 "simple", rows=rows)
     else:
         assert np.all(np.isfinite(P)) and np.all(np.abs(I - np.arange(l)[None, :]) > ez)
         assert np.all(np.diff(P, axis=0) >= -1e-3)   # mean of the k smallest grows with k
         Po, Io = O.mstomp(T64, m, ez, rows=rows)
         for k in range(3):
             _compare(P[k][rows], I[k][rows], Po[k][rows], Io[k][rows],
-                     lambda i, j, k=k: _multi_dist(T64, i, j, m, k + 1), 1e-6, ez, f"k={k + 1}")
+                     lambda i, j, k=k: _multi_dist(T64, i, j, m, k + 1), 1e-6, ez, f"k={k + 1}", rows=rows)

@@ -138,3 +138,37 @@ def test_sine_profile_is_zero():
     T = np.sin(2 * np.pi * t / 97)
     P, I = _run(T, 64, 16, "f32")
     assert np.max(P) < 1e-3
+
+
+@pytest.mark.parametrize("m,precision", [(64, "f64"), (64, "f32"), (256, "f64"), (256, "f32")])
+def test_paper_walk_with_exact_ties(m, precision):
+    """The paper's speed-test input, a +-1 random walk of n = 40000, with the
+    steps of one window copied to two more places: the three windows differ
+    only by an offset, so each has two partners at distance exactly 0 (a tie
+    the tie rule decides).  Every row: admissible, and the reported P is the
+    exact FP64 distance of the reported pair within the tolerance; the three
+    copies find each other at 0; sampled rows against the oracle."""
+    from workloads import paper_walk
+    T = paper_walk()
+    steps = np.diff(T)
+    a, b, c = 5000, 20000, 33000
+    steps[b:b + m - 1] = steps[a:a + m - 1]
+    steps[c:c + m - 1] = steps[a:a + m - 1]
+    T = np.concatenate([[T[0]], T[0] + np.cumsum(steps)])
+    n, ez = T.size, m // 2
+    l = n - m + 1
+    Th = T if precision == "f64" else T.astype(np.float32).astype(np.float64)
+    dt = np.float64 if precision == "f64" else np.float32
+    P, I = _run(Th.astype(dt), m, ez, precision)
+    P = P.astype(np.float64)
+    tol = 1e-9 if precision == "f64" else 1e-3 * np.sqrt(m)
+    assert np.all(np.isfinite(P)) and np.all(np.abs(I - np.arange(l)) > ez) and np.all((I >= 0) & (I < l))
+    for w in (a, b, c):
+        assert P[w] <= tol and I[w] in {a, b, c} - {w}, (w, P[w], I[w])
+    rng = np.random.default_rng(40 + m)
+    for i in rng.choice(l, 200, replace=False):
+        assert abs(P[i] - O.pair_distance(Th, int(i), Th, int(I[i]), m)) <= tol
+    rows = np.unique(np.concatenate([rng.choice(l, 125, replace=False), [a, b, c]]))
+    Po, Io = cimpl.selfjoin_rows(Th, m, ez, rows)
+    compare_profile(Th, m, P[rows], I[rows], Po, Io, tol, ez=ez, where=f"m={m} {precision}", rows=rows)
+    assert Io[np.searchsorted(rows, b)] == a   # the oracle's tie rule: the smallest index
