@@ -165,6 +165,15 @@ __device__ __forceinline__ double clean(double v) {
   return ((__double_as_longlong(v) >> 52) & 0x7ff) == 0x7ff ? 0.0 : v;
 }
 
+// Exchange of a double between the two lanes of each pair (quad_perm
+// [1, 0, 3, 2]).
+__device__ __forceinline__ double swap_pair(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), 0xB1, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0xB1, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // Load of a wave-uniform address through the constant address space, so that
 // it becomes a scalar load (the data was written by an earlier kernel and is
 // read-only here).
@@ -189,7 +198,7 @@ __device__ __forceinline__ T ldu(const T *p) {
 // Minimum resident waves per SIMD the register allocation must allow.
 template <typename FE, int NS>
 struct SweepMinWaves {
-  static constexpr int value = (sizeof(FE) == 4 && NS <= 12) ? 4 : 2;
+  static constexpr int value = (sizeof(FE) == 4 && NS <= 12) ? 4 : (sizeof(FE) == 8 ? 3 : 2);
 };
 
 template <typename F, typename Tin, int DT, int TP>
@@ -338,71 +347,84 @@ __global__ void __launch_bounds__(64, (SweepMinWaves<F, DT>::value))
 
     if constexpr (std::is_same_v<F, double>) {
       // FP64: one row at a time (there is no 3-input FP64 minimum, so row
-      // pairs would only hold a second key array), and the column entering
-      // at lane 63 is read from LDS as the DPP fallback operand instead of
-      // being written into the lane from a scalar register.  Each block's
-      // entering columns are prefetched one block ahead (lane u holds row
-      // u's) and staged into LDS between the two barriers of the flush.
-      __shared__ double lnew[TP][3];
-      double pa = 0.0, pg = 0.0, ps = 0.0;
+      // pairs would only hold a second key array).  The records of a block's
+      // rows and of the columns entering at lane 63 are loaded one block
+      // ahead (lane u holds row u's) and staged in LDS between the two
+      // barriers of the flush, so no row waits on a memory load: each row
+      // reads its record as an LDS broadcast and the entering column as the
+      // DPP fallback operand.  A row's 64 lane minima are halved by a DPP
+      // exchange within lane pairs before they go to LDS; the 32 partials of
+      // row u sit in a row-rotated order (pair p at position p ^ u), so the
+      // writes of a row and the flush's reads (lane r reads row r) each touch
+      // 32 distinct banks.  Lane 0's column minimum rides in the spare slot
+      // of the entering-column record.  10 KB of LDS per wave.
+      static_assert(TP <= 32, "row-rotated partials");
+      __shared__ double lrec[TP][4];   // a_i, g_i, s_i, u_i of row sb + u
+      __shared__ double lent[TP][4];   // a, g, s of the column entering after row sb + u;
+                                       // [3]: the column minimum leaving through lane 0
+      __shared__ double lhalf[TP][32]; // row minima of lane pairs
+      V4 prow = {0.0, 0.0, 0.0, 0.0}, pcol = {0.0, 0.0, 0.0, 0.0};
       auto prefetch = [&](int64_t sb2) {
         if (lane < TP && sb2 + lane < nsteps) {
-          const V4 v = newcol[sb2 + lane];
-          pa = v.x;
-          pg = v.y;
-          ps = v.z;
+          prow = rowd[i0 + sb2 + lane];
+          pcol = newcol[sb2 + lane];
         }
       };
       auto stage = [&]() {
         if (lane < TP) {
-          lnew[lane][0] = pa;
-          lnew[lane][1] = pg;
-          lnew[lane][2] = ps;
+          lrec[lane][0] = prow.x;
+          lrec[lane][1] = prow.y;
+          lrec[lane][2] = prow.z;
+          lrec[lane][3] = prow.w;
+          lent[lane][0] = pcol.x;
+          lent[lane][1] = pcol.y;
+          lent[lane][2] = pcol.z;
         }
       };
       prefetch(0);
       stage();
       prefetch(TP);
       __syncthreads();
+      const double big = IK::big();
       for (int64_t sb = 0; sb < nsteps; sb += TP) {
         const int nb = (int)min((int64_t)TP, nsteps - sb);  // a multiple of DT
         static_for<TP>([&](auto uc) {
           constexpr int u = decltype(uc)::value;
           constexpr int r0 = u % DT;  // register of slot 0
-          if (u < nb) {
-            K k[DT];
-            const V4 rd = ldu(rowd + i0 + sb + u);
-            const F ai = rd.x, gi = rd.y, si = rd.z, ui = rd.w;
-            static_for<DT>([&](auto tc) {
-              constexpr int t = decltype(tc)::value;
-              constexpr int p = (t + r0) % DT;
-              k[t] = IK::make(fma(-(C[t] * si), S[p], ui), (unsigned)(lane * DT + t));
-              C[t] = fma(A[p], gi, C[t]);
-              C[t] = fma(G[p], ai, C[t]);
-            });
-            lrow[u][lane] = IK::rowmin(k);
-            // register p met slot p - r0
-            static_for<DT>([&](auto pc) {
-              constexpr int q = decltype(pc)::value;
-              CP[q] = IK::kmin(CP[q], k[(q - r0 + DT) % DT]);
-            });
-            if (lane == 0) lcol[u] = CP[r0];
-            CP[r0] = IK::shl(CP[r0]);
-            A[r0] = shl_keep63(lnew[u][0], A[r0]);
-            G[r0] = shl_keep63(lnew[u][1], G[r0]);
-            S[r0] = shl_keep63(lnew[u][2], S[r0]);
-          }
+          if (u >= nb) return;
+          K k[DT];
+          const F ai = lrec[u][0], gi = lrec[u][1], si = lrec[u][2], ui = lrec[u][3];
+          static_for<DT>([&](auto tc) {
+            constexpr int t = decltype(tc)::value;
+            constexpr int p = (t + r0) % DT;
+            k[t] = IK::make(fma(-(C[t] * si), S[p], ui), (unsigned)(lane * DT + t));
+            C[t] = fma(A[p], gi, C[t]);
+            C[t] = fma(G[p], ai, C[t]);
+          });
+          K r = IK::rowmin(k);
+          r = IK::kmin(r, swap_pair(r));
+          if (!(lane & 1)) lhalf[u][(lane >> 1) ^ u] = r;
+          // register p met slot p - r0
+          static_for<DT>([&](auto pc) {
+            constexpr int q = decltype(pc)::value;
+            CP[q] = IK::kmin(CP[q], k[(q - r0 + DT) % DT]);
+          });
+          if (lane == 0) lent[u][3] = CP[r0];
+          CP[r0] = shl_keep63(big, CP[r0]);
+          A[r0] = shl_keep63(lent[u][0], A[r0]);
+          G[r0] = shl_keep63(lent[u][1], G[r0]);
+          S[r0] = shl_keep63(lent[u][2], S[r0]);
         });
-        // flush, with the next block's entering columns staged between the
-        // barriers (every read of this block's is done)
+        // flush, with the next block's records staged between the barriers
+        // (every read of this block's is done)
         __syncthreads();
         if (lane < nb) {
-          K best = lrow[lane][0];
+          K best = lhalf[lane][lane];
 #pragma unroll 8
-          for (int q = 1; q < 64; ++q) best = IK::kmin(best, lrow[lane][q]);
+          for (int q = 1; q < 32; ++q) best = IK::kmin(best, lhalf[lane][q ^ lane]);
           const int64_t s = sb + lane;
           if (s < nr) emit_row(i0 + s, best);
-          emit_col(i0 + s + k0, lcol[lane]);
+          emit_col(i0 + s + k0, lent[lane][3]);
         }
         stage();
         prefetch(sb + 2 * TP);
