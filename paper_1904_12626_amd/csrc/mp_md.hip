@@ -183,15 +183,17 @@ __device__ __forceinline__ double md_shl_in(double in63, double v) {
 // dimension and Q; k-dimensional: a, g, s, v per dimension), the cross
 // product of every dimension and one running column minimum per output; DT
 // (a power of two) is the largest slot count whose state fits the register
-// budget (176 for SiMPle, 100 for the k-dimensional profiles, whose per-cell
-// temporaries are larger; measured on 3 dimensions: 2 slots 101 ms, 4 slots
-// 129 ms, 1 slot 171 ms).  TP rows pass between two LDS reductions of the
-// row minima.
+// budget (176 for SiMPle; for the k-dimensional profiles, whose per-cell
+// temporaries are larger, 144 up to 5 dimensions and 100 beyond, where two
+// slots spill enough to lose: measured with the row records staged, 3
+// dimensions 4 slots 76.5 ms vs 2 slots 87.3 ms, 5 dimensions 2 slots vs 1
+// at 0.69 of the time, 6 dimensions 2 slots 2 % slower).  TP rows pass
+// between two LDS reductions of the row minima.
 template <int D, int MODE>
 struct MdShape {
   static constexpr int NP = MODE == kMdMulti ? D : 1;
   static constexpr int kSlotRegs = MODE == kMdSimple ? 8 * D + 4 : 12 * D;
-  static constexpr int kFit = (MODE == kMdSimple ? 176 : 100) / kSlotRegs;
+  static constexpr int kFit = (MODE == kMdSimple ? 176 : (D <= 5 ? 144 : 100)) / kSlotRegs;
   static constexpr int DT = kFit >= 8 ? 8 : (kFit >= 4 ? 4 : (kFit >= 2 ? 2 : 1));
   static constexpr int TP = NP == 1 ? 16 : (NP <= 3 ? 8 : 4);
   static constexpr int W = 64 * DT;
@@ -201,6 +203,16 @@ struct MdShape {
   // entering-column doubles each lane prefetches for the next row block
   static constexpr int NPF = (TP * NF + 63) / 64;
   static_assert(TP % DT == 0 && 64 % TP == 0, "row blocks");
+  // Row records staged in LDS (read as broadcasts) where that measured
+  // faster than scalar loads in the row loop, which wait on every row: the
+  // staged form needs more VGPRs and does not fit the shapes that already
+  // take every register (SiMPle at 2 and from 4 dimensions on, the
+  // k-dimensional profiles from 7 on).
+  static constexpr bool kStageRows = MODE == kMdSimple ? (D == 1 || D == 3) : D <= 6;
+  // resident waves per SIMD the register allocation must allow (without a
+  // bound the compiler hoists the LDS reads of later rows and drops to one
+  // wave)
+  static constexpr int kMinWaves = kStageRows ? 2 : 1;
 };
 
 constexpr int md_code_bits(int w) { return w <= 1 ? 1 : 1 + md_code_bits((w + 1) / 2); }
@@ -260,7 +272,7 @@ struct MdKey {
 };
 
 template <typename Tin, int D, int MODE>
-__global__ void __launch_bounds__(64) k_md_sweep(const Plan plan, const Tin *__restrict__ Tb,
+__global__ void __launch_bounds__(64, (MdShape<D, MODE>::kMinWaves)) k_md_sweep(const Plan plan, const Tin *__restrict__ Tb,
                                                  const Double4 *__restrict__ rec,
                                                  const double2 *__restrict__ mu2, int64_t stride,
                                                  const int64_t *__restrict__ seg_prefix,
@@ -278,6 +290,7 @@ __global__ void __launch_bounds__(64) k_md_sweep(const Plan plan, const Tin *__r
   __shared__ double lrow[NP][TP][65];  // per row, each lane's minimum over its slots
   __shared__ double lcol[NP][TP];      // column minima leaving the strip through lane 0
   __shared__ double lfresh[TP][NF];    // records of the columns entering at lane 63
+  __shared__ double lrrec[Sh::kStageRows ? TP : 1][NF];  // records of the block's rows
 
   const int lane = threadIdx.x;
   unsigned codes[DT];
@@ -366,14 +379,20 @@ __global__ void __launch_bounds__(64) k_md_sweep(const Plan plan, const Tin *__r
     }
 
     // Records of the columns entering at lane 63 during the rows of a block
-    // (column newc + row offset), spread over the lanes: element e is
-    // double f = e % NF of the block's column e / NF.
-    double pf[NPF];
+    // (column newc + row offset) and of the block's rows (row rrow + row
+    // offset), spread over the lanes: element e is double f = e % NF of the
+    // block's column or row e / NF.  They are loaded one block ahead and
+    // staged in LDS, so no row waits on a memory load (rows only where
+    // kStageRows is set).  A row record holds
+    // the same terms as a column record except, in the k-dimensional mode,
+    // u_i (from mu2) in place of v_j.
+    double pf[NPF], pr[NPF];
     auto prefetch = [&](int64_t sb) {
 #pragma unroll
       for (int k = 0; k < NPF; ++k) {
         const int e = lane + 64 * k;
         pf[k] = 0.0;
+        pr[k] = 0.0;
         if (e < TP * NF && sb < nsteps) {
           const int u = e / NF, f = e % NF;
           int d, comp;
@@ -385,6 +404,10 @@ __global__ void __launch_bounds__(64) k_md_sweep(const Plan plan, const Tin *__r
             comp = f % 4;
           }
           pf[k] = reinterpret_cast<const double *>(rec + d * stride + newc + sb + u)[comp];
+          if constexpr (Sh::kStageRows) {
+            if (!kSimple && comp == 3) pr[k] = mu2[d * stride + rrow + sb + u].y;
+            else pr[k] = reinterpret_cast<const double *>(rec + d * stride + rrow + sb + u)[comp];
+          }
         }
       }
     };
@@ -392,7 +415,10 @@ __global__ void __launch_bounds__(64) k_md_sweep(const Plan plan, const Tin *__r
 #pragma unroll
       for (int k = 0; k < NPF; ++k) {
         const int e = lane + 64 * k;
-        if (e < TP * NF) lfresh[e / NF][e % NF] = pf[k];
+        if (e < TP * NF) {
+          lfresh[e / NF][e % NF] = pf[k];
+          if constexpr (Sh::kStageRows) lrrec[e / NF][e % NF] = pr[k];
+        }
       }
     };
     prefetch(0);
@@ -419,16 +445,28 @@ __global__ void __launch_bounds__(64) k_md_sweep(const Plan plan, const Tin *__r
     for (int64_t sb = 0; sb < nsteps; sb += TP) {
       md_for<TP>([&](auto uc) {
         constexpr int u = decltype(uc)::value, r0 = u % DT;  // set of slot 0
-        const int64_t ri = rrow + sb + u;
         double ai[D], gi[D], zi[D], ui[D], qi = 0.0;
+        if constexpr (Sh::kStageRows) {
 #pragma unroll
-        for (int d = 0; d < D; ++d) {
-          const Double4 rr = ldu_md(rec + d * stride + ri);
-          ai[d] = rr.x;
-          gi[d] = rr.y;
-          zi[d] = rr.z;
-          if (d == 0) qi = rr.w;
-          if constexpr (!kSimple) ui[d] = ldu_md(&mu2[d * stride + ri].y);
+          for (int d = 0; d < D; ++d) {
+            constexpr int kw = kSimple ? 3 : 4;
+            ai[d] = lrrec[u][kw * d];
+            gi[d] = lrrec[u][kw * d + 1];
+            zi[d] = lrrec[u][kw * d + 2];
+            if constexpr (!kSimple) ui[d] = lrrec[u][kw * d + 3];
+          }
+          if constexpr (kSimple) qi = lrrec[u][3 * D];
+        } else {
+          const int64_t ri = rrow + sb + u;
+#pragma unroll
+          for (int d = 0; d < D; ++d) {
+            const Double4 rr = ldu_md(rec + d * stride + ri);
+            ai[d] = rr.x;
+            gi[d] = rr.y;
+            zi[d] = rr.z;
+            if (d == 0) qi = rr.w;
+            if constexpr (!kSimple) ui[d] = ldu_md(&mu2[d * stride + ri].y);
+          }
         }
         double rmin[NP];
         md_for<DT>([&](auto tc) {
