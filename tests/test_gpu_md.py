@@ -122,6 +122,29 @@ def test_eight_dimensions(mode):
             _compare(P[k], I[k], Po[k], Io[k], lambda i, j, k=k: _multi_dist(T, i, j, m, k + 1), 1e-6, ez, f"k={k + 1}")
 
 
+@pytest.mark.parametrize("mode,D", [("simple", 4), ("simple", 6), ("simple", 7), ("multi", 4), ("multi", 5),
+                                    ("multi", 6), ("multi", 7)])
+def test_remaining_dimension_counts(mode, D):
+    """Dimension counts not covered above: the kernel's slot count and
+    whether a row's records are staged in LDS or loaded per row both depend
+    on the mode and D."""
+    import paper_1904_12626_amd as mpx
+    rng = np.random.default_rng(190 + D + (10 if mode == "multi" else 0))
+    n, m, ez = 640, 16, 4
+    dtype = np.float32 if D % 2 else np.float64
+    T = np.cumsum(rng.standard_normal((D, n)), axis=1).astype(dtype)
+    P, I = [x.cpu().numpy() for x in mpx.mdjoin(torch.from_numpy(T).to(DEV), m, ez, mode=mode)]
+    T64 = T.astype(np.float64)
+    if mode == "simple":
+        Po, Io = O.simple_join(T64, m, ez)
+        _compare(P, I, Po, Io, lambda i, j: _simple_dist(T64, i, T64, j, m), 1e-6, ez, f"simple D={D}")
+    else:
+        Po, Io = O.mstomp(T64, m, ez)
+        for k in range(D):
+            _compare(P[k], I[k], Po[k], Io[k], lambda i, j, k=k: _multi_dist(T64, i, j, m, k + 1), 1e-6, ez,
+                     f"D={D} k={k + 1}")
+
+
 def test_simple_abjoin_float32_and_short_series():
     import paper_1904_12626_amd as mpx
     rng = np.random.default_rng(181)
