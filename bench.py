@@ -409,7 +409,39 @@ def main():
         result["graph_replay_equals_eager"] = same
         result["config"]["series"] = len(wl["rb"].series)
     if wl["kind"] == "diff":
-        result["config"]["note"] = "value counts forward cells per second of forward+backward steps"
+        # the same forward + backward step captured once and replayed: dL/dP
+        # = 1 comes from a static ones tensor (torch's multi-block sum would
+        # put a memset into the graph), outputs and gradient are static
+        plan = plans["f32"]
+        ones = torch.ones_like(out32[0])
+        xs = Tg.clone().requires_grad_(True)
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            mpx.MatrixProfileFn.apply(xs, plan)[0].backward(ones)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        xs.grad = None
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            Pg, Ig = mpx.MatrixProfileFn.apply(xs, plan)
+            Pg.backward(ones)
+        for _ in range(args.warmup):
+            graph.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            graph.replay()
+        torch.cuda.synchronize()
+        msg = (time.perf_counter() - t0) * 1e3 / args.steps
+        same = bool(torch.equal(Pg, out32[0]) and torch.equal(Ig, out32[1]) and torch.equal(xs.grad, out32[2]))
+        log(f"[bench] graph replay: {msg:.2f} ms/step (eager {ms32:.2f}); replay equals eager: {same}")
+        result["eager_ms_per_step"] = ms32
+        result["ms_per_step"] = msg
+        result["value"] = cells / (msg / 1e3)
+        result["graph_replay_equals_eager"] = same
+        result["config"]["note"] = ("value counts forward cells per second of forward+backward steps, "
+                                    "replayed as one captured graph")
     if wl["kind"] == "md":
         # algorithmic VALU operations per cell of the multidimensional sweep
         D = wl["T"].shape[0]

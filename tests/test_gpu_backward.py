@@ -137,3 +137,48 @@ def test_abjoin_plan_and_backward(precision, dtype):
     for g, ref in ((Ax.grad, gA), (Bx.grad, gB)):
         g = g.double().cpu().numpy()
         np.testing.assert_allclose(g, ref, rtol=tol, atol=tol * np.abs(ref).max())
+
+
+def test_forward_backward_graph_replay_equals_eager():
+    """The differentiable profile's forward and backward (dL/dP = 1, that is
+    L = sum(P), given as a static ones tensor so that no reduction kernel is
+    captured) in one captured graph: four replays, each after its outputs
+    are overwritten and with unrelated eager work in between, equal the eager
+    step bitwise."""
+    import paper_1904_12626_amd as mpx
+    B, n, m, ez = 8, 3000, 50, 12
+    T = np.cumsum(np.random.default_rng(77).standard_normal((B, n)), axis=1).astype(np.float32)
+    Tg = torch.from_numpy(T).to(DEV)
+    plan = mpx.BatchPlan([n] * B, [m] * B, [ez] * B, dtype=torch.float32, device=DEV)
+    ones = torch.ones((B, n - m + 1), dtype=torch.float32, device=DEV)
+    x0 = Tg.clone().requires_grad_(True)
+    P0, I0 = mpx.MatrixProfileFn.apply(x0, plan)
+    P0.backward(ones)
+    torch.cuda.synchronize()
+    P0, I0, g0 = P0.detach().cpu(), I0.cpu(), x0.grad.cpu()
+    xs = Tg.clone().requires_grad_(True)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):   # warm-up outside the graph (no reference kept)
+        mpx.MatrixProfileFn.apply(xs, plan)[0].backward(ones)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    xs.grad = None
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        Pg, Ig = mpx.MatrixProfileFn.apply(xs, plan)
+        Pg.backward(ones)
+    gx = xs.grad
+    for rep in range(4):
+        with torch.no_grad():
+            Pg.fill_(-1.0)
+            gx.fill_(float("nan"))
+        Ig.fill_(-7)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(Pg.detach().cpu(), P0), rep
+        assert torch.equal(Ig.cpu(), I0), rep
+        assert torch.equal(gx.cpu(), g0), rep
+        _ = (Tg * 2).sum().item()   # unrelated eager work between replays
+
