@@ -172,3 +172,27 @@ def test_paper_walk_with_exact_ties(m, precision):
     Po, Io = cimpl.selfjoin_rows(Th, m, ez, rows)
     compare_profile(Th, m, P[rows], I[rows], Po, Io, tol, ez=ez, where=f"m={m} {precision}", rows=rows)
     assert Io[np.searchsorted(rows, b)] == a   # the oracle's tie rule: the smallest index
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_long_window(precision):
+    """A window of 2048 samples (eight times the largest elsewhere): long
+    FP64 seeds, and in the FP32 sweep a cross product of size ~m sigma^2
+    carried over whole tiles.  Sampled rows against the oracle; every row
+    admissible and consistent with its reported pair."""
+    n, m, ez = 24000, 2048, 512
+    T = random_walk(n, 91, np.float32)
+    Th = T.astype(np.float64)
+    # the FP64 path on float64 input (P comes back in the input's type)
+    P, I = _run(Th if precision == "f64" else T, m, ez, precision)
+    P = P.astype(np.float64)
+    l = n - m + 1
+    tol = 1e-9 if precision == "f64" else 1e-3 * np.sqrt(m)
+    assert np.all(np.isfinite(P)) and np.all(np.abs(I - np.arange(l)) > ez) and np.all((I >= 0) & (I < l))
+    assert np.all(P <= 2 * np.sqrt(m) + tol)
+    rng = np.random.default_rng(92)
+    rows = np.unique(np.concatenate([rng.choice(l, 90, replace=False), [0, l - 1]]))
+    for i in rows[:30]:
+        assert abs(P[i] - O.pair_distance(Th, int(i), Th, int(I[i]), m)) <= tol
+    Po, Io = cimpl.selfjoin_rows(Th, m, ez, rows)
+    compare_profile(Th, m, P[rows], I[rows], Po, Io, tol, ez=ez, where=f"m={m} {precision}", rows=rows)
