@@ -43,6 +43,21 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def host_cpu():
+    """The host the CPU baseline ran on: CPU model and the cores this
+    process may use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "affinity_cores": len(os.sched_getaffinity(0))}
+
+
 def measured_traffic():
     """HBM bytes per sweep launch from the committed rocprofv3 counter runs
     (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the FP32 sweep
@@ -351,6 +366,8 @@ def main():
                                       "sample": f"{rows.size} full rows of the grown series' self-join, {pairs} pairs, "
                                                 f"{dt:.1f} s"}
             result["oracle_check"] = {"rows": int(rows.size), "max_abs_dP_vs_oracle": float(np.max(np.abs(Pg - Po)))}
+        if "cpu_baseline" in result:
+            result["cpu_baseline"]["host"] = host_cpu()
         print(json.dumps(result), flush=True)
         return
     out32, ms32, sweep32, tot32 = timed("f32", args.steps, args.warmup)
@@ -610,6 +627,8 @@ def main():
             "max_abs_dP_f32_vs_oracle": float(max(np.max(np.abs(out32[0].double().cpu().numpy()[ra] - Pa)),
                                                   np.max(np.abs(out32[2].double().cpu().numpy()[rb_] - Pb)))),
         }
+    if "cpu_baseline" in result:
+        result["cpu_baseline"]["host"] = host_cpu()
     print(json.dumps(result), flush=True)
 
 
