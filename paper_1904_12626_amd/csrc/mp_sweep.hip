@@ -12,7 +12,8 @@
 //           of every diagonal is seeded in FP64 at row i0 (so R is also the
 //           reseed interval of the FP32 sweep).
 // At row i every lane handles cells (i, i + k0 + L*DT + t).  The per-row
-// values (a_i, g_i, s_i, u_i) are wave-uniform scalar loads.  Column values
+// values (a_i, g_i, s_i, u_i) are wave-uniform scalar loads (the FP64 sweep
+// stages them in LDS one block ahead and reads them as broadcasts).  Column values
 // move one lane down per row: slot t at row i+1 reads the column slot t+1
 // held at row i, so slots rotate through registers (full unroll by DT) and
 // the last slot receives lane L+1's first slot through a DPP wave shift;
