@@ -183,17 +183,22 @@ __device__ __forceinline__ double md_shl_in(double in63, double v) {
 // dimension and Q; k-dimensional: a, g, s, v per dimension), the cross
 // product of every dimension and one running column minimum per output; DT
 // (a power of two) is the largest slot count whose state fits the register
-// budget (176 for SiMPle; for the k-dimensional profiles, whose per-cell
-// temporaries are larger, 144 up to 5 dimensions and 100 beyond, where two
-// slots spill enough to lose: measured with the row records staged, 3
-// dimensions 4 slots 76.5 ms vs 2 slots 87.3 ms, 5 dimensions 2 slots vs 1
-// at 0.69 of the time, 6 dimensions 2 slots 2 % slower).  TP rows pass
-// between two LDS reductions of the row minima.
+// budget, chosen by measurement with the row records staged and two waves
+// per SIMD, where a few spilled VGPRs cost less than fewer slots:
+//  * SiMPle: 120 up to 6 dimensions (n = 2^17 walk: 8, 4, 4, 2, 2, 2 slots;
+//    3 dimensions 4 slots 8.3 ms; 6 dimensions 2 slots 26.2 ms vs 1 slot
+//    36.7 ms), 1 slot beyond (7 dimensions: 33.5 ms vs 38.9 ms at 2);
+//  * k-dimensional profiles, whose per-cell temporaries are larger: 144 up
+//    to 5 dimensions and 100 beyond, where two slots spill enough to lose
+//    (3 dimensions 4 slots 76.5 ms vs 2 slots 87.3 ms at n = 2^18, 5
+//    dimensions 2 slots vs 1 at 0.69 of the time, 6 dimensions 2 slots 2 %
+//    slower).
+// TP rows pass between two LDS reductions of the row minima.
 template <int D, int MODE>
 struct MdShape {
   static constexpr int NP = MODE == kMdMulti ? D : 1;
   static constexpr int kSlotRegs = MODE == kMdSimple ? 8 * D + 4 : 12 * D;
-  static constexpr int kFit = (MODE == kMdSimple ? 176 : (D <= 5 ? 144 : 100)) / kSlotRegs;
+  static constexpr int kFit = (MODE == kMdSimple ? (D <= 6 ? 120 : 60) : (D <= 5 ? 144 : 100)) / kSlotRegs;
   static constexpr int DT = kFit >= 8 ? 8 : (kFit >= 4 ? 4 : (kFit >= 2 ? 2 : 1));
   static constexpr int TP = NP == 1 ? 16 : (NP <= 3 ? 8 : 4);
   static constexpr int W = 64 * DT;
@@ -204,11 +209,10 @@ struct MdShape {
   static constexpr int NPF = (TP * NF + 63) / 64;
   static_assert(TP % DT == 0 && 64 % TP == 0, "row blocks");
   // Row records staged in LDS (read as broadcasts) where that measured
-  // faster than scalar loads in the row loop, which wait on every row: the
-  // staged form needs more VGPRs and does not fit the shapes that already
-  // take every register (SiMPle at 2 and from 4 dimensions on, the
-  // k-dimensional profiles from 7 on).
-  static constexpr bool kStageRows = MODE == kMdSimple ? (D == 1 || D == 3) : D <= 6;
+  // faster than scalar loads in the row loop, which wait on every row: every
+  // SiMPle shape, and the k-dimensional profiles up to 6 dimensions (beyond,
+  // the staged form needs more VGPRs than their state leaves).
+  static constexpr bool kStageRows = MODE == kMdSimple ? true : D <= 6;
   // resident waves per SIMD the register allocation must allow (without a
   // bound the compiler hoists the LDS reads of later rows and drops to one
   // wave)
