@@ -208,15 +208,10 @@ struct MdShape {
   // entering-column doubles each lane prefetches for the next row block
   static constexpr int NPF = (TP * NF + 63) / 64;
   static_assert(TP % DT == 0 && 64 % TP == 0, "row blocks");
-  // Row records staged in LDS (read as broadcasts) where that measured
-  // faster than scalar loads in the row loop, which wait on every row: every
-  // SiMPle shape, and the k-dimensional profiles up to 6 dimensions (beyond,
-  // the staged form needs more VGPRs than their state leaves).
-  static constexpr bool kStageRows = MODE == kMdSimple ? true : D <= 6;
   // resident waves per SIMD the register allocation must allow (without a
   // bound the compiler hoists the LDS reads of later rows and drops to one
   // wave)
-  static constexpr int kMinWaves = kStageRows ? 2 : 1;
+  static constexpr int kMinWaves = 2;
 };
 
 constexpr int md_code_bits(int w) { return w <= 1 ? 1 : 1 + md_code_bits((w + 1) / 2); }
@@ -294,7 +289,7 @@ __global__ void __launch_bounds__(64, (MdShape<D, MODE>::kMinWaves)) k_md_sweep(
   __shared__ double lrow[NP][TP][65];  // per row, each lane's minimum over its slots
   __shared__ double lcol[NP][TP];      // column minima leaving the strip through lane 0
   __shared__ double lfresh[TP][NF];    // records of the columns entering at lane 63
-  __shared__ double lrrec[Sh::kStageRows ? TP : 1][NF];  // records of the block's rows
+  __shared__ double lrrec[TP][NF];     // records of the block's rows
 
   const int lane = threadIdx.x;
   unsigned codes[DT];
@@ -386,8 +381,9 @@ __global__ void __launch_bounds__(64, (MdShape<D, MODE>::kMinWaves)) k_md_sweep(
     // (column newc + row offset) and of the block's rows (row rrow + row
     // offset), spread over the lanes: element e is double f = e % NF of the
     // block's column or row e / NF.  They are loaded one block ahead and
-    // staged in LDS, so no row waits on a memory load (rows only where
-    // kStageRows is set).  A row record holds
+    // staged in LDS, so no row waits on a memory load (scalar loads of each
+    // row's records, waited on in every row, were slower at every mode and
+    // dimension count).  A row record holds
     // the same terms as a column record except, in the k-dimensional mode,
     // u_i (from mu2) in place of v_j.
     double pf[NPF], pr[NPF];
@@ -408,10 +404,8 @@ __global__ void __launch_bounds__(64, (MdShape<D, MODE>::kMinWaves)) k_md_sweep(
             comp = f % 4;
           }
           pf[k] = reinterpret_cast<const double *>(rec + d * stride + newc + sb + u)[comp];
-          if constexpr (Sh::kStageRows) {
-            if (!kSimple && comp == 3) pr[k] = mu2[d * stride + rrow + sb + u].y;
-            else pr[k] = reinterpret_cast<const double *>(rec + d * stride + rrow + sb + u)[comp];
-          }
+          if (!kSimple && comp == 3) pr[k] = mu2[d * stride + rrow + sb + u].y;
+          else pr[k] = reinterpret_cast<const double *>(rec + d * stride + rrow + sb + u)[comp];
         }
       }
     };
@@ -421,7 +415,7 @@ __global__ void __launch_bounds__(64, (MdShape<D, MODE>::kMinWaves)) k_md_sweep(
         const int e = lane + 64 * k;
         if (e < TP * NF) {
           lfresh[e / NF][e % NF] = pf[k];
-          if constexpr (Sh::kStageRows) lrrec[e / NF][e % NF] = pr[k];
+          lrrec[e / NF][e % NF] = pr[k];
         }
       }
     };
@@ -450,28 +444,15 @@ __global__ void __launch_bounds__(64, (MdShape<D, MODE>::kMinWaves)) k_md_sweep(
       md_for<TP>([&](auto uc) {
         constexpr int u = decltype(uc)::value, r0 = u % DT;  // set of slot 0
         double ai[D], gi[D], zi[D], ui[D], qi = 0.0;
-        if constexpr (Sh::kStageRows) {
 #pragma unroll
-          for (int d = 0; d < D; ++d) {
-            constexpr int kw = kSimple ? 3 : 4;
-            ai[d] = lrrec[u][kw * d];
-            gi[d] = lrrec[u][kw * d + 1];
-            zi[d] = lrrec[u][kw * d + 2];
-            if constexpr (!kSimple) ui[d] = lrrec[u][kw * d + 3];
-          }
-          if constexpr (kSimple) qi = lrrec[u][3 * D];
-        } else {
-          const int64_t ri = rrow + sb + u;
-#pragma unroll
-          for (int d = 0; d < D; ++d) {
-            const Double4 rr = ldu_md(rec + d * stride + ri);
-            ai[d] = rr.x;
-            gi[d] = rr.y;
-            zi[d] = rr.z;
-            if (d == 0) qi = rr.w;
-            if constexpr (!kSimple) ui[d] = ldu_md(&mu2[d * stride + ri].y);
-          }
+        for (int d = 0; d < D; ++d) {
+          constexpr int kw = kSimple ? 3 : 4;
+          ai[d] = lrrec[u][kw * d];
+          gi[d] = lrrec[u][kw * d + 1];
+          zi[d] = lrrec[u][kw * d + 2];
+          if constexpr (!kSimple) ui[d] = lrrec[u][kw * d + 3];
         }
+        if constexpr (kSimple) qi = lrrec[u][3 * D];
         double rmin[NP];
         md_for<DT>([&](auto tc) {
           constexpr int t = decltype(tc)::value, p = (t + r0) % DT;
