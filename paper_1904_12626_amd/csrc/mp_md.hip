@@ -200,7 +200,10 @@ struct MdShape {
   static constexpr int kSlotRegs = MODE == kMdSimple ? 8 * D + 4 : 12 * D;
   static constexpr int kFit = (MODE == kMdSimple ? (D <= 6 ? 120 : 60) : (D <= 5 ? 144 : 100)) / kSlotRegs;
   static constexpr int DT = kFit >= 8 ? 8 : (kFit >= 4 ? 4 : (kFit >= 2 ? 2 : 1));
-  static constexpr int TP = NP == 1 ? 16 : (NP <= 3 ? 8 : 4);
+  // rows between flushes: fewer for more profiles (their row minima share
+  // the LDS; at 3 profiles 4 rows leave the prefetch 4 fewer VGPRs, 46 -> 2
+  // spilled, and ran 20.2 -> 19.5 ms on an n = 2^17 walk)
+  static constexpr int TP = NP == 1 ? 16 : (NP == 2 ? 8 : 4);
   static constexpr int W = 64 * DT;
   // doubles of one column record set: SiMPle a, g, z per dimension and Q;
   // k-dimensional a, g, s, v per dimension
