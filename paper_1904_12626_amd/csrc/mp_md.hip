@@ -202,8 +202,11 @@ struct MdShape {
   static constexpr int DT = kFit >= 8 ? 8 : (kFit >= 4 ? 4 : (kFit >= 2 ? 2 : 1));
   // rows between flushes: fewer for more profiles (their row minima share
   // the LDS; at 3 profiles 4 rows leave the prefetch 4 fewer VGPRs, 46 -> 2
-  // spilled, and ran 20.2 -> 19.5 ms on an n = 2^17 walk)
-  static constexpr int TP = NP == 1 ? 16 : (NP == 2 ? 8 : 4);
+  // spilled, and ran 20.2 -> 19.5 ms on an n = 2^17 walk).  SiMPle at 6 and
+  // 8 dimensions, whose 16-row prefetch spilled 77 and 90 VGPRs, runs faster
+  // with 8 (26.2 -> 22.3 and 56.8 -> 47.7 ms); at 4, 5 and 7 dimensions 8
+  // rows were slower.
+  static constexpr int TP = NP == 1 ? ((D == 6 || D == 8) ? 8 : 16) : (NP == 2 ? 8 : 4);
   static constexpr int W = 64 * DT;
   // doubles of one column record set: SiMPle a, g, z per dimension and Q;
   // k-dimensional a, g, s, v per dimension
