@@ -190,7 +190,8 @@ __device__ __forceinline__ double md_shl_in(double in63, double v) {
 //    36.7 ms), 1 slot beyond (7 dimensions: 33.5 ms vs 38.9 ms at 2);
 //  * k-dimensional profiles, whose per-cell temporaries are larger: 144 up
 //    to 5 dimensions and 100 beyond, where two slots spill enough to lose
-//    (3 dimensions 4 slots 76.5 ms vs 2 slots 87.3 ms at n = 2^18, 5
+//    (3 dimensions 4 slots 76.5 ms vs 2 slots 87.3 ms at n = 2^18, 4
+//    dimensions 4 slots 46.1 ms vs 2 slots 38.5 ms at n = 2^17, 5
 //    dimensions 2 slots vs 1 at 0.69 of the time, 6 dimensions 2 slots 2 %
 //    slower).
 // TP rows pass between two LDS reductions of the row minima.
