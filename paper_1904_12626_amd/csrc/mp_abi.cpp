@@ -5,9 +5,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -267,20 +269,29 @@ mpx::Plan plan_of(const Job &j, const Layout &L, void *ws, bool external) {
 bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
 // Benchmark timing: event quadruples (start, sweep start, sweep end, end) per
-// call, recycled after each query.
+// call, recycled after each query.  Calls may come from several host
+// threads, so the event lists are guarded by a mutex.
 struct Timing {
-  bool on = false;
+  std::atomic<bool> on{false};
+  std::mutex mu;
   std::vector<hipEvent_t> pool;   // free events
   std::vector<hipEvent_t> rec;    // 4 per recorded call
   hipEvent_t get() {
-    if (!pool.empty()) {
-      hipEvent_t e = pool.back();
-      pool.pop_back();
-      return e;
+    {
+      std::lock_guard<std::mutex> g(mu);
+      if (!pool.empty()) {
+        hipEvent_t e = pool.back();
+        pool.pop_back();
+        return e;
+      }
     }
     hipEvent_t e = nullptr;
     if (hipEventCreate(&e) != hipSuccess) return nullptr;
     return e;
+  }
+  void record(const hipEvent_t (&ev)[4]) {
+    std::lock_guard<std::mutex> g(mu);
+    for (hipEvent_t e : ev) rec.push_back(e);
   }
 };
 Timing g_timing;
@@ -297,7 +308,8 @@ mp_status run_job(const Job &j, const mpx::Plan &plan, const mpx::Work &w, const
                   const mpx::Outputs &o, bool out_f64, hipStream_t st) {
   const Options &op = j.opt;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-  if (g_timing.on) {
+  const bool rec = g_timing.on;
+  if (rec) {
     for (auto &e : ev) e = g_timing.get();
     if (ev[0]) (void)hipEventRecord(ev[0], st);
   }
@@ -318,9 +330,9 @@ mp_status run_job(const Job &j, const mpx::Plan &plan, const mpx::Work &w, const
   if (mpx::launch_rescan(plan, w, T, j.t_f64, o, out_f64, op.fp64_finalize, st) != hipSuccess)
     return MP_ELAUNCH;
   if (j.lr && mpx::launch_lr_combine(o, out_f64, j.series[0].l, st) != hipSuccess) return MP_ELAUNCH;
-  if (g_timing.on) {
+  if (rec) {
     if (ev[3]) (void)hipEventRecord(ev[3], st);
-    for (auto &e : ev) g_timing.rec.push_back(e);
+    g_timing.record(ev);
   }
   return MP_OK;
 }
@@ -667,8 +679,14 @@ mp_status mp_timing_query(double *sweep_ms, double *total_ms, int64_t *calls) {
   double sw = 0.0, tot = 0.0;
   int64_t n = 0;
   mp_status st = MP_OK;
-  for (size_t q = 0; q + 3 < g_timing.rec.size(); q += 4) {
-    hipEvent_t *e = &g_timing.rec[q];
+  std::vector<hipEvent_t> recs;
+  {
+    std::lock_guard<std::mutex> g(g_timing.mu);
+    recs.swap(g_timing.rec);
+  }
+  std::vector<hipEvent_t> done;
+  for (size_t q = 0; q + 3 < recs.size(); q += 4) {
+    hipEvent_t *e = &recs[q];
     float a = 0.f, b = 0.f;
     if (e[0] && e[1] && e[2] && e[3] && hipEventSynchronize(e[3]) == hipSuccess &&
         hipEventElapsedTime(&a, e[1], e[2]) == hipSuccess &&
@@ -680,9 +698,12 @@ mp_status mp_timing_query(double *sweep_ms, double *total_ms, int64_t *calls) {
       st = MP_ELAUNCH;
     }
     for (int k = 0; k < 4; ++k)
-      if (e[k]) g_timing.pool.push_back(e[k]);
+      if (e[k]) done.push_back(e[k]);
   }
-  g_timing.rec.clear();
+  {
+    std::lock_guard<std::mutex> g(g_timing.mu);
+    g_timing.pool.insert(g_timing.pool.end(), done.begin(), done.end());
+  }
   if (sweep_ms) *sweep_ms = sw;
   if (total_ms) *total_ms = tot;
   if (calls) *calls = n;
@@ -828,7 +849,7 @@ mp_status mp_mdjoin(int32_t mode, int32_t D, const void *A, int64_t nA, const vo
     return MP_ELAUNCH;
   if (g_timing.on) {
     if (ev[3]) (void)hipEventRecord(ev[3], st);
-    for (auto &e : ev) g_timing.rec.push_back(e);
+    g_timing.record(ev);
   }
   return MP_OK;
 }

@@ -747,10 +747,10 @@ int md_strip_width(int mode, int D) {
 }
 
 int md_sweep_grid(int mode, int D) {
-  int dev = 0, cus = 256;
-  hipDeviceProp_t prop;
-  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
-    cus = prop.multiProcessorCount;
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+    cus = 256;
   int per = 0;
   const hipError_t e = mode == kMdSimple ? md_occupancy_t<kMdSimple>(D, &per) : md_occupancy_t<kMdMulti>(D, &per);
   if (e != hipSuccess || per <= 0) per = 8;

@@ -509,14 +509,12 @@ __global__ void __launch_bounds__(64, (SweepMinWaves<F, DT>::value))
 }
 
 int sweep_grid(bool f64_sweep, int slots) {
-  static int cus = -1;
-  if (cus < 0) {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
-    else cus = 256;
-  }
+  // compute units of the current device (asked on every call: a process may
+  // drive several devices)
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+    cus = 256;
   int per = 0;
   hipError_t e;
   if (f64_sweep)
