@@ -68,7 +68,9 @@ typedef enum {
   MP_EINVAL = -1,        /* bad size, pointer, alignment or option      */
   MP_EWORKSPACE = -2,    /* workspace null, misaligned or too small     */
   MP_ELAUNCH = -3,       /* a kernel launch failed                      */
-  MP_EUNSUPPORTED = -4   /* valid request this build does not support   */
+  MP_EUNSUPPORTED = -4,  /* valid request this build does not support   */
+  MP_ETOOLARGE = -5      /* job exceeds the fixed scratch of
+                            mp_selfjoin_noalloc                         */
 } mp_status;
 
 typedef enum {
@@ -106,6 +108,30 @@ size_t mp_selfjoin_workspace(int64_t n, int32_t m, mp_dtype dtype, const mp_opti
 mp_status mp_selfjoin(const void *T, int64_t n, int32_t m, int32_t ez, mp_dtype dtype,
                       const mp_options *opt, void *P, int64_t *I, void *ws, size_t ws_bytes,
                       void *stream);
+
+/* ------------------------------------------- self-join without allocation
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * self-join of mp_selfjoin with the same arguments minus the workspace,
+ * same kernels, bitwise the same P and I.  Its scratch is a fixed device
+ * array of MP_NOALLOC_SCRATCH_BYTES inside the library, one per device,
+ * held from the first call on a device until the process ends; the call
+ * itself allocates and frees nothing (no hipMalloc, no events; timing is
+ * never recorded for it).
+ *   Limit: a job whose mp_selfjoin_workspace(n, m, dtype, opt) exceeds
+ *   MP_NOALLOC_SCRATCH_BYTES returns MP_ETOOLARGE and enqueues nothing
+ *   (64 MiB holds the FP32 sweep's workspace up to about 1.15 million
+ *   windows, the FP64 sweep's up to about 0.87 million).
+ *   Device: the scratch of the current device is used; a non-NULL stream
+ *   must belong to that device (else MP_EINVAL).
+ *   Sharing: every call on one device uses the same scratch.  Calls that
+ *   overlap on one device (two streams, two host threads) race and give
+ *   undefined results; order them on one stream.  The kernels initialise
+ *   every scratch entry they read, so nothing needs clearing between calls.
+ */
+#define MP_NOALLOC_SCRATCH_BYTES (64u << 20)
+mp_status mp_selfjoin_noalloc(const void *T, int64_t n, int32_t m, int32_t ez, mp_dtype dtype,
+                              const mp_options *opt, void *P, int64_t *I, void *stream);
 
 /* ----------------------------------------------------------------- AB-join
  * Section 3.2: two series.  P_ab[i] = min_j d(A_i, B_j) (index into B),

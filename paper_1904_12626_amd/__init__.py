@@ -22,7 +22,7 @@ package computes it with hand-written HIP kernels behind a C ABI
 from ._binding import (  # noqa: F401
     EXPORTS, LIB_PATH, MPError, ABJoinPlan, BatchPlan, SelfJoinPlan, SelfJoinStream, abjoin, abjoin_cells, anytime_order, chains, fluss,
     anytime_selfjoin, exclusion_zone, left_right_profiles, lib, make_options, mdjoin, recheck, selfjoin,
-    selfjoin_cells, selfjoin_chunks, timing_enable, timing_query,
+    selfjoin_cells, selfjoin_noalloc, selfjoin_chunks, timing_enable, timing_query,
 )
 from .autograd import MatrixProfileFn, abjoin_profile, matrix_profile  # noqa: F401
 
@@ -30,5 +30,5 @@ __all__ = [
     "selfjoin", "abjoin", "BatchPlan", "recheck", "MatrixProfileFn", "matrix_profile",
     "exclusion_zone", "selfjoin_cells", "abjoin_cells", "MPError", "lib", "SelfJoinPlan",
     "selfjoin_chunks", "anytime_order", "anytime_selfjoin", "left_right_profiles", "fluss", "chains",
-    "ABJoinPlan", "abjoin_profile", "mdjoin", "SelfJoinStream",
+    "ABJoinPlan", "abjoin_profile", "mdjoin", "SelfJoinStream", "selfjoin_noalloc",
 ]

@@ -18,7 +18,8 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmpx.so")
 
-MP_OK, MP_EINVAL, MP_EWORKSPACE, MP_ELAUNCH, MP_EUNSUPPORTED = 0, -1, -2, -3, -4
+MP_OK, MP_EINVAL, MP_EWORKSPACE, MP_ELAUNCH, MP_EUNSUPPORTED, MP_ETOOLARGE = 0, -1, -2, -3, -4, -5
+MP_NOALLOC_SCRATCH_BYTES = 64 << 20
 MP_F64, MP_F32 = 0, 1
 MP_PREC_F64, MP_PREC_F32 = 0, 1
 MP_FLAG_FP64_FINALIZE = 1
@@ -33,7 +34,7 @@ EXPORTS = (
     "mp_selfjoin_chunks", "mp_selfjoin_plan_create", "mp_anytime_order",
     "mp_fluss_workspace", "mp_fluss", "mp_chains_workspace", "mp_chains", "mp_abjoin_plan_create",
     "mp_mdjoin_workspace", "mp_mdjoin", "mp_mdjoin_cells",
-    "mp_stream_workspace", "mp_stream_init", "mp_stream_append",
+    "mp_stream_workspace", "mp_stream_init", "mp_stream_append", "mp_selfjoin_noalloc",
 )
 
 
@@ -66,6 +67,7 @@ def lib():
     sig = {
         "mp_selfjoin_workspace": (sz, [i64, i32, i32, op]),
         "mp_selfjoin": (ctypes.c_int, [vp, i64, i32, i32, i32, op, vp, vp, vp, sz, vp]),
+        "mp_selfjoin_noalloc": (ctypes.c_int, [vp, i64, i32, i32, i32, op, vp, vp, vp]),
         "mp_abjoin_workspace": (sz, [i64, i64, i32, i32, op]),
         "mp_abjoin": (ctypes.c_int, [vp, i64, vp, i64, i32, i32, op, vp, vp, vp, vp, vp, sz, vp]),
         "mp_batch_plan_create": (ctypes.c_int, [i32, vp, vp, vp, i32, op, ctypes.POINTER(vp)]),
@@ -177,6 +179,30 @@ def selfjoin(T: torch.Tensor, m: int, ez: int | None = None, *, exclusion_zone_f
     ws = workspace if workspace is not None else torch.empty(ws_bytes, dtype=torch.uint8, device=T.device)
     _check("mp_selfjoin", L.mp_selfjoin(_ptr(T), n, m, int(ez), dt, ctypes.byref(opt), _ptr(P), _ptr(I),
                                         _ptr(ws), ws.numel(), _stream(stream)))
+    return P, I
+
+
+def selfjoin_noalloc(T: torch.Tensor, m: int, ez: int | None = None, *, P: torch.Tensor, I: torch.Tensor,
+                     exclusion_zone_frac=Fraction(1, 2), precision: str = "f32", reseed_rows: int = 0,
+                     tile_slots: int = 0, fp64_finalize: bool = True, stream=None):
+    """Self-join into caller-given P (T's dtype) and I (int64), both of length
+    n - m + 1, through mp_selfjoin_noalloc: nothing is allocated, the
+    library's fixed per-device scratch serves as the workspace (jobs whose
+    workspace exceeds MP_NOALLOC_SCRATCH_BYTES raise MPError with
+    MP_ETOOLARGE).  Calls on one device must be ordered on one stream."""
+    T = _series(T, "T")
+    n = T.numel()
+    l = n - m + 1
+    if ez is None:
+        ez = exclusion_zone(m, exclusion_zone_frac)
+    for t, name, dt_ in ((P, "P", T.dtype), (I, "I", torch.int64)):
+        if not isinstance(t, torch.Tensor) or t.device != T.device or t.dtype != dt_ or t.numel() != l \
+                or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous {dt_} tensor of {l} entries on {T.device}")
+    opt = make_options(precision, reseed_rows, tile_slots, fp64_finalize)
+    _check("mp_selfjoin_noalloc", lib().mp_selfjoin_noalloc(_ptr(T), n, m, int(ez), _dtype_code(T),
+                                                            ctypes.byref(opt), _ptr(P), _ptr(I),
+                                                            _stream(stream)))
     return P, I
 
 

@@ -304,11 +304,13 @@ mp_status check_ws(void *ws, size_t ws_bytes, size_t need) {
 
 // The full launch sequence of a job whose descriptors are reachable through
 // `plan`.
+// `timed`: record benchmark events when timing is enabled (the entry point
+// without allocations never does: creating an event is an allocation).
 mp_status run_job(const Job &j, const mpx::Plan &plan, const mpx::Work &w, const void *T,
-                  const mpx::Outputs &o, bool out_f64, hipStream_t st) {
+                  const mpx::Outputs &o, bool out_f64, hipStream_t st, bool timed = true) {
   const Options &op = j.opt;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-  const bool rec = g_timing.on;
+  const bool rec = timed && g_timing.on;
   if (rec) {
     for (auto &e : ev) e = g_timing.get();
     if (ev[0]) (void)hipEventRecord(ev[0], st);
@@ -453,6 +455,8 @@ const char *mp_strerror(mp_status s) {
     case MP_EWORKSPACE: return "workspace missing, misaligned or too small";
     case MP_ELAUNCH: return "kernel launch failed";
     case MP_EUNSUPPORTED: return "unsupported option combination";
+    case MP_ETOOLARGE:
+      return "job needs more scratch than the fixed MP_NOALLOC_SCRATCH_BYTES of mp_selfjoin_noalloc";
   }
   return "unknown status";
 }
@@ -490,6 +494,68 @@ mp_status mp_selfjoin(const void *T, int64_t n, int32_t m, int32_t ez, mp_dtype 
   o.P[0] = P;
   o.I[0] = I;
   return run_job(j, p, w, T, o, dtype == MP_F64, (hipStream_t)stream);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Fixed device scratch of mp_selfjoin_noalloc: the self-join workspace lives
+// here instead of in caller memory.  Every device the library runs on holds
+// one copy (at its own address) until the process ends.  In host code the
+// array's name is only a stand-in; the device address comes from
+// hipGetSymbolAddress, taken once per device and kept in g_scratch_ptr.
+static __device__ __align__(256) unsigned char scratch[MP_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// The scratch address on the current device (looked up on the first call
+// there).
+mp_status scratch_of_current_device(void **out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return MP_ELAUNCH;
+  if (dev < 0 || dev >= kMaxDevices) return MP_EUNSUPPORTED;
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return MP_ELAUNCH;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return MP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mp_status mp_selfjoin_noalloc(const void *T, int64_t n, int32_t m, int32_t ez, mp_dtype dtype,
+                              const mp_options *opt, void *P, int64_t *I, void *stream) {
+  Job j;
+  mp_status s = build_selfjoin(n, m, ez, dtype, opt, j);
+  if (s != MP_OK) return s;
+  if (!T || !P || !I || !aligned(T, esize(dtype)) || !aligned(P, esize(dtype)) || !aligned(I, 8))
+    return MP_EINVAL;
+  const Layout L = layout_of(j, false);
+  if (L.total > (size_t)MP_NOALLOC_SCRATCH_BYTES) return MP_ETOOLARGE;
+  hipStream_t st = (hipStream_t)stream;
+  if (st) {
+    // the scratch used is the current device's; the stream must run there
+    int cur = -1;
+    hipDevice_t sdev = -1;
+    if (hipGetDevice(&cur) != hipSuccess || hipStreamGetDevice(st, &sdev) != hipSuccess) return MP_ELAUNCH;
+    if (sdev != cur) return MP_EINVAL;
+  }
+  void *ws = nullptr;
+  if ((s = scratch_of_current_device(&ws)) != MP_OK) return s;
+  const mpx::Work w = work_of(L, ws);
+  const mpx::Plan p = plan_of(j, L, ws, false);
+  mpx::Outputs o{};
+  o.P[0] = P;
+  o.I[0] = I;
+  return run_job(j, p, w, T, o, dtype == MP_F64, st, /*timed=*/false);
 }
 
 size_t mp_abjoin_workspace(int64_t nA, int64_t nB, int32_t m, mp_dtype dtype, const mp_options *opt) {

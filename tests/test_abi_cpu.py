@@ -33,8 +33,9 @@ def test_library_exports_every_declared_symbol():
 
 def test_strerror():
     lib = B.lib()
-    for s in (0, -1, -2, -3, -4):
+    for s in (0, -1, -2, -3, -4, -5):
         assert lib.mp_strerror(s)
+    assert b"scratch" in lib.mp_strerror(B.MP_ETOOLARGE)
 
 
 def test_cell_counts():
@@ -206,3 +207,20 @@ def test_new_entry_points_reject_bad_arguments():
     assert lib.mp_selfjoin_plan_create(4096, 64, 16, B.MP_F32, None, 1, 0, None, ctypes.byref(h)) == 0
     assert lib.mp_backward(h, ok, ok, ok, ok, ok, 1 << 40, None) == B.MP_EUNSUPPORTED
     lib.mp_batch_plan_destroy(h)
+
+
+def test_noalloc_selfjoin_host_checks():
+    """mp_selfjoin_noalloc checks sizes, pointers and its scratch limit on
+    the host, before any device call."""
+    lib = B.lib()
+    ok = ctypes.c_void_p(1 << 20)
+    opt = B.make_options("f32")
+    # the FP32 workspace of n = 2^20, m = 256 fits the fixed scratch, 2^21 does not
+    assert lib.mp_selfjoin_workspace(1 << 20, 256, B.MP_F32, ctypes.byref(opt)) <= B.MP_NOALLOC_SCRATCH_BYTES
+    assert lib.mp_selfjoin_workspace(1 << 21, 256, B.MP_F32, ctypes.byref(opt)) > B.MP_NOALLOC_SCRATCH_BYTES
+    assert lib.mp_selfjoin_noalloc(ok, 1 << 21, 256, 64, B.MP_F32, ctypes.byref(opt), ok, ok,
+                                   None) == B.MP_ETOOLARGE
+    assert lib.mp_selfjoin_noalloc(ok, 100, 1, 0, B.MP_F32, None, ok, ok, None) == B.MP_EINVAL
+    assert lib.mp_selfjoin_noalloc(None, 100, 10, 2, B.MP_F32, None, ok, ok, None) == B.MP_EINVAL
+    assert lib.mp_selfjoin_noalloc(ok, 100, 10, 2, B.MP_F32, None, ctypes.c_void_p((1 << 20) + 2), ok,
+                                   None) == B.MP_EINVAL
