@@ -27,8 +27,11 @@
  *     and it is never chosen as a neighbour.  A row with no admissible
  *     neighbour also gets (+inf, -1).  These are results, not errors.
  *   - P holds distances (not squared distances); I is 0-based and local to
- *     its series; ties go to the smallest index up to the key resolution of
- *     the chosen precision.
+ *     its series.  Equal distances go to the smallest index when the tied
+ *     pairs lie in different tiles of the sweep (tile_slots x 64 diagonal
+ *     offsets by reseed_rows rows); inside one tile either index may be
+ *     returned.  "Equal" is at the resolution of the sweep's keys (FP32:
+ *     13 significant bits of 1 - rho; FP64: 43).
  *   - Self-join: pairs with |i - j| <= ez are excluded.  AB-join: no zone.
  *
  * Memory and streams

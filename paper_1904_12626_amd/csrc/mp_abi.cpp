@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <cmath>
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
@@ -304,6 +305,20 @@ mp_status check_ws(void *ws, size_t ws_bytes, size_t need) {
 
 // The full launch sequence of a job whose descriptors are reachable through
 // `plan`.
+// Key error floor of the FP32 sweep.  A key is 1 - rho = d^2 / (2m); the
+// FP32 cross product drifts between FP64 seeds by rounding steps of about
+// 2^-24 of its size, so over a tile of R rows the key error grows like
+// 2^-24 sqrt(2R): measured on the n = 2^20, m = 256 planted walk at
+// R = 4104, the largest key error over all rows was 4.5e-5 among rows with
+// P < 3 (1e-4 at P ~ 30, where the code bits of the key dominate), i.e.
+// 8 x 2^-24 sqrt(2R).  delta = 16 x 2^-24 sqrt(2R) doubles that.  Two
+// candidates whose keys differ by less than 2 delta may be ordered wrongly;
+// near d = 0 that costs up to sqrt(4 m delta) in d after the FP64 finalize,
+// above the tolerance, so rows whose raw key is below 2 delta (near-exact
+// repeats, d < sqrt(4 m delta) ~ 0.3 at m = 256) are re-found exactly by
+// the FP64 rescan.  Rows above it can lose at most 2 m delta / d.
+double fp32_key_floor(int R) { return 2.0 * 16.0 * std::ldexp(1.0, -24) * std::sqrt(2.0 * R); }
+
 // `timed`: record benchmark events when timing is enabled (the entry point
 // without allocations never does: creating an event is an allocation).
 mp_status run_job(const Job &j, const mpx::Plan &plan, const mpx::Work &w, const void *T,
@@ -326,7 +341,8 @@ mp_status run_job(const Job &j, const mpx::Plan &plan, const mpx::Work &w, const
   }
   if (ev[2]) (void)hipEventRecord(ev[2], st);
   if (mpx::launch_special(plan, w, st) != hipSuccess) return MP_ELAUNCH;
-  if (mpx::launch_finalize(plan, w, T, j.t_f64, o, out_f64, op.fp64_finalize, j.total_l, st) !=
+  const double kappa = (!op.f64 && op.fp64_finalize) ? fp32_key_floor(j.R) : 0.0;
+  if (mpx::launch_finalize(plan, w, T, j.t_f64, o, out_f64, op.fp64_finalize, kappa, j.total_l, st) !=
       hipSuccess)
     return MP_ELAUNCH;
   if (mpx::launch_rescan(plan, w, T, j.t_f64, o, out_f64, op.fp64_finalize, st) != hipSuccess)
@@ -354,7 +370,9 @@ mp_status build_selfjoin(int64_t n, int32_t m, int32_t ez, mp_dtype dt, const mp
   return MP_OK;
 }
 
-mp_status build_abjoin(int64_t nA, int64_t nB, int64_t b_off, int32_t m, mp_dtype dt,
+// B's samples: at b_off in the call's one sample array (b_sep = false, the
+// AB-join plans' [A | B] layout), or at the start of a second array (b_sep).
+mp_status build_abjoin(int64_t nA, int64_t nB, int64_t b_off, bool b_sep, int32_t m, mp_dtype dt,
                        const mp_options *opt, Job &j) {
   if (dt != MP_F64 && dt != MP_F32) return MP_EINVAL;
   if (m < 2 || nA < m || nB < m) return MP_EINVAL;
@@ -363,7 +381,8 @@ mp_status build_abjoin(int64_t nA, int64_t nB, int64_t b_off, int32_t m, mp_dtyp
   if (s != MP_OK) return s;
   j.t_f64 = dt == MP_F64;
   add_series(j, 0, nA, m, -1, 1, 0);
-  add_series(j, b_off, nB, m, -1, 0, 1);
+  add_series(j, b_sep ? 0 : b_off, nB, m, -1, 0, 1);
+  j.series[1].tsel = b_sep ? 1 : 0;
   j.series[1].p_off = 0;  // second output array
   const int64_t lA = nA - m + 1, lB = nB - m + 1;
   add_sweep(j, 0, 1, 0, 1, 0, lB - 1);  // rows A, columns B, j >= i
@@ -560,7 +579,7 @@ mp_status mp_selfjoin_noalloc(const void *T, int64_t n, int32_t m, int32_t ez, m
 
 size_t mp_abjoin_workspace(int64_t nA, int64_t nB, int32_t m, mp_dtype dtype, const mp_options *opt) {
   Job j;
-  if (build_abjoin(nA, nB, 0, m, dtype, opt, j) != MP_OK) return 0;
+  if (build_abjoin(nA, nB, 0, true, m, dtype, opt, j) != MP_OK) return 0;
   return layout_of(j, false).total;
 }
 
@@ -572,16 +591,14 @@ mp_status mp_abjoin(const void *A, int64_t nA, const void *B, int64_t nB, int32_
   if (!aligned(A, es) || !aligned(B, es) || !aligned(P_ab, es) || !aligned(P_ba, es) ||
       !aligned(I_ab, 8) || !aligned(I_ba, 8))
     return MP_EINVAL;
-  // B is addressed relative to A (one flat device address space)
-  const int64_t diff = (int64_t)((intptr_t)B - (intptr_t)A);
-  if (diff % (int64_t)es != 0) return MP_EINVAL;
   Job j;
-  mp_status s = build_abjoin(nA, nB, diff / (int64_t)es, m, dtype, opt, j);
+  mp_status s = build_abjoin(nA, nB, 0, true, m, dtype, opt, j);
   if (s != MP_OK) return s;
   const Layout L = layout_of(j, false);
   if ((s = check_ws(ws, ws_bytes, L.total)) != MP_OK) return s;
   const mpx::Work w = work_of(L, ws);
-  const mpx::Plan p = plan_of(j, L, ws, false);
+  mpx::Plan p = plan_of(j, L, ws, false);
+  p.t2 = B;  // series 1 (B) reads its samples from B
   mpx::Outputs o{};
   o.P[0] = P_ab;
   o.I[0] = I_ab;
@@ -636,7 +653,7 @@ mp_status mp_abjoin_plan_create(int64_t nA, int64_t nB, int32_t m, mp_dtype dtyp
   *out = nullptr;
   mp_batch_plan *pl = new (std::nothrow) mp_batch_plan();
   if (!pl) return MP_EINVAL;
-  const mp_status s = build_abjoin(nA, nB, nA, m, dtype, opt, pl->job);
+  const mp_status s = build_abjoin(nA, nB, nA, false, m, dtype, opt, pl->job);
   if (s != MP_OK) {
     delete pl;
     return s;
@@ -805,8 +822,9 @@ struct MdLayout {
   int64_t stride;
 };
 
-mp_status build_md(int32_t mode, int32_t D, int64_t nA, int64_t nB, int64_t b_off, int32_t m,
-                   int32_t ez, bool self, mp_dtype dt, Job &j, MdLayout &L) {
+// An AB-join's B is a second sample array (SeriesDesc::tsel = 1, Plan::t2).
+mp_status build_md(int32_t mode, int32_t D, int64_t nA, int64_t nB, int32_t m, int32_t ez, bool self,
+                   mp_dtype dt, Job &j, MdLayout &L) {
   if (dt != MP_F64 && dt != MP_F32) return MP_EINVAL;
   if (mode != MP_MD_SIMPLE && mode != MP_MD_MULTI) return MP_EINVAL;
   if (D < 1 || D > mpx::kMdMaxDims || m < 2 || nA < m) return MP_EINVAL;
@@ -820,7 +838,8 @@ mp_status build_md(int32_t mode, int32_t D, int64_t nA, int64_t nB, int64_t b_of
     add_sweep(j, 0, 0, 0, 0, (int64_t)ez + 1, nA - m);
   } else {
     add_series(j, 0, nA, m, -1, 1, 0);
-    add_series(j, b_off, nB, m, -1, 0, 1);
+    add_series(j, 0, nB, m, -1, 0, 1);
+    j.series[1].tsel = 1;
     j.series[1].p_off = 0;
     add_sweep(j, 0, 1, 0, 1, 0, nB - m);
     add_sweep(j, 1, 0, 1, 0, 1, nA - m);
@@ -867,7 +886,7 @@ size_t mp_mdjoin_workspace(int32_t mode, int32_t D, int64_t nA, int64_t nB, int3
   Job j;
   MdLayout L;
   const bool self = nB <= 0;
-  if (build_md(mode, D, nA, nB, 0, m, 0, self, MP_F32, j, L) != MP_OK) return 0;
+  if (build_md(mode, D, nA, nB, m, 0, self, MP_F32, j, L) != MP_OK) return 0;
   return L.total;
 }
 
@@ -877,20 +896,16 @@ mp_status mp_mdjoin(int32_t mode, int32_t D, const void *A, int64_t nA, const vo
   const bool self = B == nullptr;
   const size_t es = esize(dtype);
   if (!A || !P || !I || !aligned(A, es) || !aligned(P, es) || !aligned(I, 8)) return MP_EINVAL;
-  int64_t b_off = 0;
-  if (!self) {
-    if (!P_ba || !I_ba || !aligned(B, es) || !aligned(P_ba, es) || !aligned(I_ba, 8)) return MP_EINVAL;
-    const int64_t diff = (int64_t)((intptr_t)B - (intptr_t)A);
-    if (diff % (int64_t)es != 0) return MP_EINVAL;
-    b_off = diff / (int64_t)es;
-  }
+  if (!self && (!P_ba || !I_ba || !aligned(B, es) || !aligned(P_ba, es) || !aligned(I_ba, 8)))
+    return MP_EINVAL;
   Job j;
   MdLayout L;
-  mp_status s = build_md(mode, D, nA, nB, b_off, m, ez, self, dtype, j, L);
+  mp_status s = build_md(mode, D, nA, nB, m, ez, self, dtype, j, L);
   if (s != MP_OK) return s;
   if ((s = check_ws(ws, ws_bytes, L.total)) != MP_OK) return s;
   char *b = (char *)ws;
-  const mpx::Plan p = plan_of(j, Layout{}, ws, false);
+  mpx::Plan p = plan_of(j, Layout{}, ws, false);
+  p.t2 = self ? nullptr : B;
   mpx::Work w{};
   w.seg_prefix = (int64_t *)(b + L.segp);
   w.seg_sweep = (int32_t *)(b + L.segs);

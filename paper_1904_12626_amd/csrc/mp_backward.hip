@@ -62,7 +62,7 @@ __global__ void __launch_bounds__(256) k_bwd_stats(Plan plan, BwdWork b, const T
   const int64_t wi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (wi >= total_l) return;
   const SeriesDesc S = plan.series(find_series_by_w(plan, wi));
-  const Tin *x = Tb + S.t_off + (wi - S.w_off);
+  const Tin *x = series_samples(plan, Tb, S) + (wi - S.w_off);
   const int m = S.m;
   double s = 0.0, lo = 0.0, hi = 0.0;
   bool ok = true;
@@ -110,8 +110,8 @@ __global__ void __launch_bounds__(256) k_bwd_coef(Plan plan, BwdWork b, const Ti
     jw = Q.w_off + j;
     const double isi = b.isig[wi], isj = b.isig[jw];
     if (isi > 0.0 && isj > 0.0) {
-      const Tin *xi = Tb + S.t_off + i;
-      const Tin *xj = Tb + Q.t_off + j;
+      const Tin *xi = series_samples(plan, Tb, S) + i;
+      const Tin *xj = series_samples(plan, Tb, Q) + j;
       const double mi = b.mu[wi], mj = b.mu[jw];
       double d2 = 0.0, dot = 0.0;
       for (int u = 0; u < S.m; ++u) {

@@ -32,7 +32,7 @@ struct SeriesDesc {
   int32_t partner;  // series whose windows are this series' candidates
   int32_t out;      // output slot: 0 (single array) or the AB side (0/1)
   int32_t side;     // self-join candidates: 0 both sides, kSideRight j > i, kSideLeft j < i
-  int32_t pad_;
+  int32_t tsel;     // samples in the call's T array (0) or in its second array (1, Plan::t2)
 };
 constexpr int32_t kSideRight = 1;
 constexpr int32_t kSideLeft = 2;
@@ -63,10 +63,20 @@ struct Plan {
   // in the set.  Null = every admissible offset.
   const uint32_t *kmask;
   int64_t kchunk;
+  // Second sample array of a call given two series as separate allocations
+  // (the AB-joins): series with tsel = 1 index it with their t_off.
+  const void *t2;
 
   __device__ __forceinline__ SeriesDesc series(int i) const { return s_ext ? s_ext[i] : s_inl[i]; }
   __device__ __forceinline__ SweepDesc sweep(int i) const { return w_ext ? w_ext[i] : w_inl[i]; }
 };
+
+// First sample of series S: in the call's sample array Tb, or in the second
+// array of a two-array call.
+template <typename Tin>
+__device__ __forceinline__ const Tin *series_samples(const Plan &plan, const Tin *Tb, const SeriesDesc &S) {
+  return (S.tsel ? static_cast<const Tin *>(plan.t2) : Tb) + S.t_off;
+}
 
 // Workspace arrays (device).
 struct Work {
@@ -134,9 +144,10 @@ hipError_t launch_sweep(const Plan &plan, const Work &w, const void *T, bool t_f
                         int slots, int R, int64_t total_tiles, int64_t nseg, int grid,
                         hipStream_t st);
 hipError_t launch_special(const Plan &plan, const Work &w, hipStream_t st);
+// kappa: rows whose key is below it are queued for the exact rescan (0: none)
 hipError_t launch_finalize(const Plan &plan, const Work &w, const void *T, bool t_f64,
-                           const Outputs &o, bool out_f64, bool fp64_finalize, int64_t total_l,
-                           hipStream_t st);
+                           const Outputs &o, bool out_f64, bool fp64_finalize, double kappa,
+                           int64_t total_l, hipStream_t st);
 hipError_t launch_rescan(const Plan &plan, const Work &w, const void *T, bool t_f64,
                          const Outputs &o, bool out_f64, bool fp64_finalize, hipStream_t st);
 hipError_t launch_lr_combine(const Outputs &o, bool out_f64, int64_t l, hipStream_t st);

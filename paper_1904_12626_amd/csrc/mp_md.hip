@@ -100,7 +100,7 @@ __global__ void __launch_bounds__(256) k_md_stats(Plan plan, int D, const Tin *_
   bool ok = true;
   double Q = 0.0;
   for (int d = 0; d < D; ++d) {
-    const Tin *x = Tb + S.t_off + (int64_t)d * S.n + w;
+    const Tin *x = series_samples(plan, Tb, S) + (int64_t)d * S.n + w;
     double s = 0.0, lo = 0.0, hi = 0.0;
     for (int u = 0; u < m; ++u) {
       const double v = (double)x[u];
@@ -338,8 +338,8 @@ __global__ void __launch_bounds__(64, (MdShape<D, MODE>::kMinWaves)) k_md_sweep(
     double C[DT][D];
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-      const Tin *__restrict__ Tr = Tb + RS.t_off + (int64_t)d * RS.n + i0;
-      const Tin *__restrict__ Tc = Tb + CS.t_off + (int64_t)d * CS.n;
+      const Tin *__restrict__ Tr = series_samples(plan, Tb, RS) + (int64_t)d * RS.n + i0;
+      const Tin *__restrict__ Tc = series_samples(plan, Tb, CS) + (int64_t)d * CS.n;
       const double mur = ldu_md(&mu2[d * stride + rrow].x);
       double acc[DT], xr[DT];
 #pragma unroll
@@ -598,8 +598,8 @@ __global__ void __launch_bounds__(256) k_md_finalize(Plan plan, int D, const Tin
       if (MODE == kMdSimple) {
         double s = 0.0;
         for (int d = 0; d < D; ++d) {
-          const Tin *a = Tb + S.t_off + (int64_t)d * S.n + w;
-          const Tin *b = Tb + Q.t_off + (int64_t)d * Q.n + idx;
+          const Tin *a = series_samples(plan, Tb, S) + (int64_t)d * S.n + w;
+          const Tin *b = series_samples(plan, Tb, Q) + (int64_t)d * Q.n + idx;
           for (int u = 0; u < m; ++u) {
             const double e = (double)a[u] - (double)b[u];
             s = fma(e, e, s);
@@ -611,8 +611,8 @@ __global__ void __launch_bounds__(256) k_md_finalize(Plan plan, int D, const Tin
         for (int d = 0; d < D; ++d) {
           const Double4 ra = rec[d * stride + S.rc_off + w], rb = rec[d * stride + Q.rc_off + idx];
           const double ma = mu2[d * stride + S.rc_off + w].x, mb = mu2[d * stride + Q.rc_off + idx].x;
-          const Tin *a = Tb + S.t_off + (int64_t)d * S.n + w;
-          const Tin *b = Tb + Q.t_off + (int64_t)d * Q.n + idx;
+          const Tin *a = series_samples(plan, Tb, S) + (int64_t)d * S.n + w;
+          const Tin *b = series_samples(plan, Tb, Q) + (int64_t)d * Q.n + idx;
           const double ia = ra.z / sqrt(2.0), ib = rb.z / sqrt(2.0);  // 1/sigma or 0
           double s = 0.0;
           for (int u = 0; u < m; ++u) {

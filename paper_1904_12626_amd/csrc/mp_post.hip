@@ -36,6 +36,9 @@ __device__ __forceinline__ double sample(const Tin *p) {
 template <typename Tin>
 __device__ double pair_dist64(const Tin *TA, double muA, double sgA, bool cA, const Tin *TB,
                               double muB, double sgB, bool cB, int m) {
+  // z_a - z_b must be exactly 0 for windows that are offset copies: each z is
+  // rounded before the subtraction (no contraction into a fused multiply-add)
+#pragma clang fp contract(off)
   const double ia = cA ? 0.0 : 1.0 / sgA, ib = cB ? 0.0 : 1.0 / sgB;
   double s = 0.0;
   for (int u = 0; u < m; ++u) {
@@ -134,10 +137,14 @@ __device__ __forceinline__ void store_out(const Outputs &o, const SeriesDesc &S,
 //    scores such pairs too high);
 //  * if the chosen partner is invalid or past the end of the partner series
 //    (the sweep scores such columns like rho = 0), the window is queued for
-//    an exact rescan.
+//    an exact rescan;
+//  * so is a window whose key is below `kappa` (FP32 sweep): there the
+//    FP32 keys cannot order the candidates (near-exact repeats), and the
+//    exact FP64 scan picks the neighbour.
 template <typename Tin, typename Tout>
 __global__ void __launch_bounds__(256) k_finalize(Plan plan, Work wk, const Tin *__restrict__ Tb,
-                                                  Outputs o, int fp64_finalize, int64_t total_l) {
+                                                  Outputs o, int fp64_finalize, double kappa,
+                                                  int64_t total_l) {
   const int64_t wi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (wi >= total_l) return;
   const int si = find_series_w(plan, wi);
@@ -182,7 +189,7 @@ __global__ void __launch_bounds__(256) k_finalize(Plan plan, Work wk, const Tin 
       idx = jc;
     }
   }
-  if (idx >= Q.l || ((sp & 1) && idx >= 0 && !(wk.flags[Q.w_off + idx] & 1))) {
+  if (idx >= Q.l || ((sp & 1) && idx >= 0 && !(wk.flags[Q.w_off + idx] & 1)) || (idx >= 0 && val < kappa)) {
     const unsigned long long pos = atomicAdd(&wk.counters[1], 1ull);
     wk.rescan[pos] = wi;
     store_out<Tout>(o, S, w, INFINITY, -1);
@@ -192,7 +199,7 @@ __global__ void __launch_bounds__(256) k_finalize(Plan plan, Work wk, const Tin 
   if (idx >= 0) {
     P = sqrt(2.0 * S.m * fmax(val, 0.0));
     if (fp64_finalize && !(wk.flags[Q.w_off + idx] & 2)) {
-      P = pair_dist64(Tb + S.t_off + w, wk.mu[wi], wk.sig[wi], false, Tb + Q.t_off + idx,
+      P = pair_dist64(series_samples(plan, Tb, S) + w, wk.mu[wi], wk.sig[wi], false, series_samples(plan, Tb, Q) + idx,
                       wk.mu[Q.w_off + idx], wk.sig[Q.w_off + idx], false, S.m);
     }
   }
@@ -215,7 +222,7 @@ __global__ void __launch_bounds__(256) k_rescan(Plan plan, Work wk, const Tin *_
     const SeriesDesc S = plan.series(si);
     const SeriesDesc Q = plan.series(S.partner);
     const int64_t w = wi - S.w_off;
-    const Tin *Tw = Tb + S.t_off + w;
+    const Tin *Tw = series_samples(plan, Tb, S) + w;
     const double muw = wk.mu[wi], sgw = wk.sig[wi];
     double best = INFINITY;
     int64_t arg = -1;
@@ -227,7 +234,7 @@ __global__ void __launch_bounds__(256) k_rescan(Plan plan, Work wk, const Tin *_
       if (fj & 2) {
         key = 0.5;
       } else {
-        const Tin *Tj = Tb + Q.t_off + j;
+        const Tin *Tj = series_samples(plan, Tb, Q) + j;
         const double muj = wk.mu[Q.w_off + j];
         double c = 0.0;
         for (int u = 0; u < S.m; ++u) c = fma(sample(Tw + u) - muw, sample(Tj + u) - muj, c);
@@ -255,7 +262,7 @@ __global__ void __launch_bounds__(256) k_rescan(Plan plan, Work wk, const Tin *_
       if (j >= 0) {
         P = sqrt(2.0 * S.m * fmax(bk[0], 0.0));
         if (fp64_finalize && !(wk.flags[Q.w_off + j] & 2))
-          P = pair_dist64(Tw, muw, sgw, false, Tb + Q.t_off + j, wk.mu[Q.w_off + j],
+          P = pair_dist64(Tw, muw, sgw, false, series_samples(plan, Tb, Q) + j, wk.mu[Q.w_off + j],
                           wk.sig[Q.w_off + j], false, S.m);
       }
       store_out<Tout>(o, S, w, P, j);
@@ -265,16 +272,16 @@ __global__ void __launch_bounds__(256) k_rescan(Plan plan, Work wk, const Tin *_
 }
 
 hipError_t launch_finalize(const Plan &plan, const Work &w, const void *T, bool t_f64,
-                           const Outputs &o, bool out_f64, bool fp64_finalize, int64_t total_l,
-                           hipStream_t st) {
+                           const Outputs &o, bool out_f64, bool fp64_finalize, double kappa,
+                           int64_t total_l, hipStream_t st) {
   const dim3 blk(256), grd((unsigned)((total_l + 255) / 256));
   const int f = fp64_finalize ? 1 : 0;
   if (t_f64) {
-    if (out_f64) hipLaunchKernelGGL((k_finalize<double, double>), grd, blk, 0, st, plan, w, (const double *)T, o, f, total_l);
-    else hipLaunchKernelGGL((k_finalize<double, float>), grd, blk, 0, st, plan, w, (const double *)T, o, f, total_l);
+    if (out_f64) hipLaunchKernelGGL((k_finalize<double, double>), grd, blk, 0, st, plan, w, (const double *)T, o, f, kappa, total_l);
+    else hipLaunchKernelGGL((k_finalize<double, float>), grd, blk, 0, st, plan, w, (const double *)T, o, f, kappa, total_l);
   } else {
-    if (out_f64) hipLaunchKernelGGL((k_finalize<float, double>), grd, blk, 0, st, plan, w, (const float *)T, o, f, total_l);
-    else hipLaunchKernelGGL((k_finalize<float, float>), grd, blk, 0, st, plan, w, (const float *)T, o, f, total_l);
+    if (out_f64) hipLaunchKernelGGL((k_finalize<float, double>), grd, blk, 0, st, plan, w, (const float *)T, o, f, kappa, total_l);
+    else hipLaunchKernelGGL((k_finalize<float, float>), grd, blk, 0, st, plan, w, (const float *)T, o, f, kappa, total_l);
   }
   return hipGetLastError();
 }

@@ -119,7 +119,7 @@ __global__ void __launch_bounds__(256) k_stats(Plan plan, Work w, const Tin *__r
     rc[r] = FTraits<F>::pad4();
     return;
   }
-  const Tin *x = Tb + S.t_off + i;
+  const Tin *x = series_samples(plan, Tb, S) + i;
   const int m = S.m;
   bool fin = true;
   double s = 0.0, lo = 0.0, hi = 0.0;

@@ -270,8 +270,8 @@ __global__ void __launch_bounds__(64, (SweepMinWaves<F, DT>::value))
     const int64_t c0 = i0 + k0 + (int64_t)lane * DT;
     F C[DT];
     {
-      const Tin *__restrict__ Tr = Tb + RS.t_off + i0;
-      const Tin *__restrict__ Tc = Tb + CS.t_off;
+      const Tin *__restrict__ Tr = series_samples(plan, Tb, RS) + i0;
+      const Tin *__restrict__ Tc = series_samples(plan, Tb, CS);
       const double mur = ldu(mu + RS.w_off + i0);
       const int64_t ncol = CS.n;
       double acc[DT], xr[DT];

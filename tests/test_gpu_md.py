@@ -183,3 +183,26 @@ def test_benchmark_size_sampled_rows(mode):
         for k in range(3):
             _compare(P[k][rows], I[k][rows], Po[k][rows], Io[k][rows],
                      lambda i, j, k=k: _multi_dist(T64, i, j, m, k + 1), 1e-6, ez, f"k={k + 1}", rows=rows)
+
+
+def test_multi_hand_worked_case():
+    """The two-dimensional case whose k = 2 neighbour differs between the
+    mean of distances and the root of the mean of squared distances (see the
+    oracle pin): the GPU profile follows the mean of distances."""
+    import paper_1904_12626_amd as mpx
+    from tests.test_oracle_pins import _two_readings_series
+    T = _two_readings_series()
+    P, I = mpx.mdjoin(torch.from_numpy(T).to(DEV), 4, 0, mode="multi")
+    P, I = P.double().cpu().numpy(), I.cpu().numpy()
+    Po, Io = O.mstomp(T, 4, 0)
+    assert np.array_equal(np.isfinite(P), np.isfinite(Po))
+    fin = np.isfinite(Po)
+    assert np.max(np.abs(P[fin] - Po[fin])) < 1e-9
+    # row 10, k = 1: windows 0 and 5 tie exactly at 2.5 (both are left
+    # partners, where the column minimum may keep the larger index); every
+    # other entry has a unique minimum
+    tie = np.zeros_like(I, dtype=bool)
+    tie[0, 10] = True
+    assert np.array_equal(I[~tie], Io[~tie])
+    assert I[0, 10] in (0, 5)
+    assert I[1, 0] == 5 and abs(P[1, 0] - 2.0) < 1e-9

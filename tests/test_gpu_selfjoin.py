@@ -196,3 +196,43 @@ def test_long_window(precision):
         assert abs(P[i] - O.pair_distance(Th, int(i), Th, int(I[i]), m)) <= tol
     Po, Io = cimpl.selfjoin_rows(Th, m, ez, rows)
     compare_profile(Th, m, P[rows], I[rows], Po, Io, tol, ez=ez, where=f"m={m} {precision}", rows=rows)
+
+
+def test_exact_tie_order_of_the_fp64_sweep():
+    """Exact ties (integer +-1 walk, m = 64: every quantity of the FP64
+    sweep is a dyadic rational computed without rounding up to the key, so
+    equal distances give bitwise equal keys).  Copies of one window's steps
+    at a, a2 = a + 100 and c: all three windows differ by an offset only.
+      row a: right partners a2 and c (distance 0) in different strips ->
+             the packed global minimum takes the smallest index, a2;
+      row a2: left partner a and right partner c -> a (the packed minimum
+             across the row and column paths takes the smaller index);
+      row c: left partners a and a2.  With tiles of 64 rows their cells lie
+             in different tiles, whose column minima meet in the packed
+             minimum: a.  With 4096-row tiles both cells share a tile, where
+             the in-wave minimum orders equal keys by their diagonal code,
+             not by index: either copy may come out (both at P = 0).
+    The oracle takes the smallest index: a2, a, a."""
+    from workloads import paper_walk
+    T = paper_walk()
+    m, ez = 64, 32
+    steps = np.diff(T)
+    a, a2 = 5000, 5100
+    # c chosen so that offsets c - a2 and c - a fall in one strip of the
+    # FP64 sweep (W = 512 offsets, strips start at ez + 1)
+    W = 512
+    s = (30000 - a - (ez + 1)) // W
+    c = a + ez + 1 + s * W + 150
+    assert (c - a2 - (ez + 1)) // W == (c - a - (ez + 1)) // W
+    for p in (a2, c):
+        steps[p:p + m - 1] = steps[a:a + m - 1]
+    T = np.concatenate([[T[0]], T[0] + np.cumsum(steps)])
+    Po, Io = cimpl.selfjoin_rows(T, m, ez, np.array([a, a2, c]))
+    assert list(Io) == [a2, a, a] and list(Po) == [0.0, 0.0, 0.0]
+    P, I = _run(T, m, ez, "f64", reseed=64)
+    assert P[a] == 0.0 and P[a2] == 0.0 and P[c] == 0.0
+    assert (I[a], I[a2], I[c]) == (a2, a, a)
+    assert a // 4096 == a2 // 4096
+    P, I = _run(T, m, ez, "f64", reseed=4096)
+    assert P[a] == 0.0 and P[a2] == 0.0 and P[c] == 0.0
+    assert (I[a], I[a2]) == (a2, a) and I[c] in (a, a2)

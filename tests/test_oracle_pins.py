@@ -615,3 +615,58 @@ def test_mstomp_finds_a_motif_living_in_some_dimensions():
     assert abs(int(I[1, 150]) - 600) <= 2 and abs(int(I[1, 600]) - 150) <= 2
     assert P[1, 150] < 0.5 * np.median(P[1])
     assert P[2, 150] > P[1, 150]
+
+
+def _two_readings_series():
+    """Two dimensions, m = 4, three valid windows separated by NaN samples
+    (windows over a NaN are invalid, so rows 0, 5 and 10 see only each
+    other).  Built from the Walsh patterns w1 = [1,1,-1,-1], w2 = [1,-1,-1,1],
+    w3 = [1,-1,1,-1]: zero mean, population std 1, mutually orthogonal, so
+    z-normalisation leaves them as they are and d^2 = 2m(1 - rho) = 8(1 - rho).
+      window 0  (query)  dim 1: w3,                dim 2: w3
+      window 5  (A)      dim 1: w3,                dim 2: -w3
+      window 10 (B)      dim 1: c w3 + s w1,       dim 2: c w3 + s w2
+    with c = 7/32, s = sqrt(1 - c^2) (zero mean, std 1, rho with w3 = c)."""
+    c = 7.0 / 32.0
+    s = np.sqrt(1.0 - c * c)
+    w1 = np.array([1.0, 1.0, -1.0, -1.0])
+    w2 = np.array([1.0, -1.0, -1.0, 1.0])
+    w3 = np.array([1.0, -1.0, 1.0, -1.0])
+    nan = np.array([np.nan])
+    d1 = np.concatenate([w3, nan, w3, nan, c * w3 + s * w1])
+    d2 = np.concatenate([w3, nan, -w3, nan, c * w3 + s * w2])
+    return np.stack([d1, d2])
+
+
+def test_mstomp_hand_worked_case_fixes_the_mean_of_distances():
+    """Pins the k-dimensional distance as the mean of the k smallest
+    per-dimension distances (Section 3.3.5 reading), not the root of the
+    mean of squared distances, on a case where the two choose different
+    neighbours.  By hand (d^2 = 8(1 - rho)):
+      row 0 vs A: dim 1 rho = 1 -> 0;  dim 2 rho = -1 -> 4
+      row 0 vs B: both dims rho = c = 7/32 -> d^2 = 8 * 25/32 = 6.25 -> 2.5
+      k = 1: min(0, 2.5) = 0 at A (window 5)
+      k = 2: mean of distances A (0 + 4)/2 = 2.0 < B 2.5 -> P = 2.0, I = 5
+             (the other reading: A sqrt(16/2) = 2.83 > B 2.5 would give 2.5, I = 10)
+      row 10 (B) vs 0: (2.5, 2.5); vs A: dim 1 rho = c -> 2.5, dim 2
+             rho = -c -> d^2 = 8 * 39/32 = 9.75 -> 3.1225
+      k = 1: 2.5 at both -> the smaller index 0; k = 2: 2.5 (row 0) < 2.811 -> I = 0
+      row 5 (A) vs 0: (0, 4); vs B: (2.5, 3.1225) -> k = 1: 0 at 0;
+             k = 2: 2.0 at 0 (vs 2.811)
+    Every other window holds a NaN: +inf, -1."""
+    T = _two_readings_series()
+    P, I = O.mstomp(T, 4, 0)
+    l = T.shape[1] - 3
+    assert P.shape == (2, l)
+    want = {0: ((0.0, 5), (2.0, 5)), 5: ((0.0, 0), (2.0, 0)), 10: ((2.5, 0), (2.5, 0))}
+    for i in range(l):
+        for k in range(2):
+            if i in want:
+                p, j = want[i][k]
+                assert abs(P[k, i] - p) < 1e-12, (i, k, P[k, i], p)
+                assert I[k, i] == j, (i, k, I[k, i], j)
+            else:
+                assert P[k, i] == np.inf and I[k, i] == -1
+    # the per-dimension distances the derivation uses
+    assert abs(O.pair_distance(T[0], 10, T[0], 5, 4) - 2.5) < 1e-12
+    assert abs(O.pair_distance(T[1], 10, T[1], 5, 4) - np.sqrt(9.75)) < 1e-12
