@@ -12,9 +12,14 @@ resident in HBM before timing starts.
 Printed: one JSON line with cells/s (admissible pairs per second), the
 sweep kernel's VALU roofline fraction (timed live with HIP events on the
 launch stream), the FP64 GPU path's rate and the FP32-vs-FP64 agreement,
-and the FP64 CPU oracle timed on sampled rows of the same workload.
+and the FP64 CPU oracle timed on sampled rows of the same workload.  The
+default run adds one record per further workload under "workloads" (the
+plain FP64 self-join n=4096, the ECG-like AB-join, the ragged batch of 512
+series, the differentiable batch of 64 series): each timed as the median of
+at least 5 event-timed steps after 3 warm-ups, with its sweep's roofline
+fraction, its tolerance check and its own timed CPU-oracle baseline.
 
-Usage: python bench.py [--steps K] [--warmup W] [--workload NAME]
+Usage: python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-workloads]
 """
 
 from __future__ import annotations
@@ -32,11 +37,19 @@ sys.path.insert(0, ROOT)
 
 METRIC = "matrix-profile cells/sec (FP32-mixed vs FP64) at stated max |ΔP| vs FP64 oracle"
 
-# VALU roofline of the sweep: MI355X has 256 CUs, each issuing one 64-lane
-# VALU instruction per clock (4 SIMDs x 16 lanes), at 2.4 GHz.  Packed FP32
-# instructions are disabled in this build, so FP32 and FP64 share that rate.
-PEAK_LANE_OPS = 256 * 64 * 2.4e9            # 3.93e13 lane-ops/s
-OPS_PER_CELL = 6                            # 2 FMA (C update), MUL + FMA (key), row min, column min
+# VALU roofline of the sweep from MI355X's published rates: 256 CUs at
+# 2.4 GHz; FP32 vector 157.3 TFLOP/s = 128 FP32 lanes per CU per clock, FP64
+# vector 78.6 TFLOP/s = 64 lanes; other VALU instructions (integer minima)
+# 64 lanes (4 SIMDs x 16).  A cell costs 6 algorithmic operations: 2 FMA
+# (cross product), MUL + FMA (key) in the sweep's precision, and a row and
+# a column minimum (integer compares of packed keys).
+CU_CLOCKS = 256 * 2.4e9
+PEAK_LANE_OPS = CU_CLOCKS * 64               # 3.93e13: one 64-lane instruction per CU per clock
+OPS_PER_CELL = 6
+PEAK_CELLS = {"f32": CU_CLOCKS / (4 / 128 + 2 / 64),   # 9.83e12 cells/s (FP32-mixed sweep)
+              "f64": CU_CLOCKS / (4 / 64 + 2 / 64)}    # 6.55e12 cells/s (FP64 sweep)
+PEAK_NOTE = ("published MI355X rates: 4 FP ops per cell at the FP32 (157.3 TFLOP/s: 128 lanes/CU/clock) or FP64 "
+             "(78.6: 64 lanes) vector rate plus 2 integer minima at 64 lanes/CU/clock, 256 CUs at 2.4 GHz")
 
 
 def log(msg):
@@ -74,6 +87,63 @@ def measured_traffic():
     except OSError:
         return None
     return r["traffic_bytes_per_launch"] if h and r.get("sweep_isa_sha256") == h else None
+
+
+def valu_ceiling(log):
+    """Issue rates the device sustains for the sweep's instruction classes
+    and per-cell mixes (bench_valu.hip, built next to the library objects),
+    or None when the probe is missing or fails."""
+    import subprocess
+    exe = os.path.join(ROOT, "paper_1904_12626_amd", "_build", "bench_valu")
+    if not os.path.exists(exe):
+        return None
+    try:
+        r = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+        if r.returncode != 0:
+            log(f"[bench] VALU probe failed: {r.stderr.strip()[:200]}")
+            return None
+        return json.loads(r.stdout)
+    except (OSError, ValueError, subprocess.TimeoutExpired) as e:
+        log(f"[bench] VALU probe failed: {e}")
+        return None
+
+
+# VALU instructions per cell of the sweeps' loops as compiled (the mixes the
+# probe replays): FP32, 24 cells per row pair at 12 slots: 48 v_fmac + 24
+# v_fma + 24 v_mul + 24 v_and_or + 21 v_min3 + 4 v_min + 8 DPP + 8 lane
+# writes = 161; FP64, 8 cells per row: 24 FMA + 8 MUL + 8 v_and_or + 16
+# v_min_f64 + 10 DPP + 8 moves = 74
+MIX_F32_PER_CELL = 161 / 24
+MIX_F64_PER_CELL = 74 / 8
+
+
+def ceilings(vc, sweep32_cells_s, sweep64_ms, cells):
+    """The sweep's rate against three ceilings: the nominal 6 operations per
+    cell at one 64-lane VALU instruction per CU-clock (2.4 GHz); the issue
+    rate the probe measured for the loop's own instruction mix; and the
+    probe's FMA rate for the 4 floating-point operations per cell alone
+    (the bound if every other instruction were free)."""
+    out = {"probe": {k: {"lane_instructions_per_s": v["lane_instructions_per_s"],
+                         "wave_instructions_per_cu_clock": v["wave_instructions_per_cu_clock"],
+                         "core_clock_mhz": v["core_clock_mhz"]}
+                     for k, v in vc.items() if isinstance(v, dict)}}
+    nominal = PEAK_LANE_OPS / OPS_PER_CELL
+    mix32 = vc["fp32_sweep_mix"]["lane_instructions_per_s"] / MIX_F32_PER_CELL
+    fp32 = vc["v_fmac_f32"]["lane_instructions_per_s"] / 4
+    out["fp32"] = {"published_rates_cells_per_s": PEAK_CELLS["f32"],
+                   "frac_published_rates": sweep32_cells_s / PEAK_CELLS["f32"],
+                   "one_instruction_per_cu_clock_cells_per_s": nominal, "frac_one_instruction": sweep32_cells_s / nominal,
+                   "measured_mix_cells_per_s": mix32, "frac_measured_mix": sweep32_cells_s / mix32,
+                   "measured_fma_only_cells_per_s": fp32, "frac_measured_fma_only": sweep32_cells_s / fp32}
+    if sweep64_ms:
+        s64 = cells / (sweep64_ms / 1e3)
+        mix64 = vc["fp64_sweep_mix"]["lane_instructions_per_s"] / MIX_F64_PER_CELL
+        fp64 = vc["v_fma_f64"]["lane_instructions_per_s"] / 4
+        out["fp64"] = {"published_rates_cells_per_s": PEAK_CELLS["f64"],
+                       "frac_published_rates": s64 / PEAK_CELLS["f64"],
+                       "measured_mix_cells_per_s": mix64, "frac_measured_mix": s64 / mix64,
+                       "measured_fma_only_cells_per_s": fp64, "frac_measured_fma_only": s64 / fp64}
+    return out
 
 
 def workload(name: str, n_override=None):
@@ -132,6 +202,324 @@ def workload(name: str, n_override=None):
     raise SystemExit(f"unknown workload {name}")
 
 
+def ev_steps(fn, steps, warmup):
+    """Run `fn` `warmup` times, then `steps` times with a pair of events on
+    the current stream around each; returns (last output, median ms, all ms)."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    out = None
+    for a, b in ev:
+        a.record()
+        out = fn()
+        b.record()
+    torch.cuda.synchronize()
+    ms = [a.elapsed_time(b) for a, b in ev]
+    return out, float(np.median(ms)), ms
+
+
+def lib_sweep_ms(fn, reps):
+    """Mean duration of the library's sweep kernel and of its whole launch
+    sequence per call (HIP events the library records on its stream)."""
+    import torch
+    import paper_1904_12626_amd as mpx
+    torch.cuda.synchronize()
+    mpx.timing_query()
+    mpx.timing_enable(True)
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    mpx.timing_enable(False)
+    sw, tot, calls = mpx.timing_query()
+    return sw / max(1, calls), tot / max(1, calls)
+
+
+def roofline_of(cells, sweep_ms, kernel, prec="f32"):
+    ach = cells * OPS_PER_CELL / (sweep_ms / 1e3) / 1e12
+    peak = PEAK_CELLS[prec] * OPS_PER_CELL / 1e12
+    return {"bound": "alu", "kernel": kernel, "ops_per_cell": OPS_PER_CELL, "sweep_ms_per_launch": sweep_ms,
+            "achieved": ach, "peak": peak, "unit": "TOP/s", "frac": ach / peak, "peak_model": PEAK_NOTE,
+            "frac_one_instruction_per_cu_clock": ach / (PEAK_LANE_OPS / 1e12)}
+
+
+def admissible(I, l, ez):
+    """Indices in range and outside the exclusion zone (self-join)."""
+    i = np.arange(I.size)
+    return bool(np.all((I >= 0) & (I < l) & (np.abs(I - i) > ez)))
+
+
+def rec_selfjoin_f64(steps, warmup, dev):
+    """Plain FP64 self-join of a float64 random walk, n = 4096, m = 64,
+    ez = 16: the FP64 sweep, P float64, checked against the full oracle."""
+    import torch
+    import paper_1904_12626_amd as mpx
+    import workloads as W
+    T, m, ez = W.selfjoin_small()
+    n = T.size
+    l = n - m + 1
+    Tg = torch.from_numpy(T).to(dev)
+    cells = mpx.selfjoin_cells(n, m, ez)
+    step = lambda: mpx.selfjoin(Tg, m, ez, precision="f64")  # noqa: E731
+    (P, I), med, _ = ev_steps(step, steps, warmup)
+    sweep_ms, _ = lib_sweep_ms(step, steps)
+    Pg, Ig = P.cpu().numpy(), I.cpu().numpy()
+    tol = 1e-3 * np.sqrt(m)
+    rec = {"workload": f"plain FP64 self-join, float64 random walk n={n}, m={m}, ez={ez}; FP64 sweep, P float64",
+           "cells": cells, "dtype": "f64", "steps": steps, "warmup": warmup, "ms_per_step_median": med,
+           "cells_per_s": cells / (med / 1e3), "roofline": roofline_of(cells, sweep_ms, "k_sweep<double>", "f64")}
+    from oracle import cimpl   # CPU baseline leg: the full oracle, timed
+    t0 = time.perf_counter()
+    Po, Io = cimpl.selfjoin(T, m, ez)
+    dt = time.perf_counter() - t0
+    rec["cpu_baseline"] = {"value": cells / dt, "unit": "cells/s", "cores": cimpl.max_threads(), "kind": "oracle",
+                           "sample": f"the whole join ({l} rows, {cells} pairs), each O(m) in FP64, {dt:.2f} s"}
+    dP = float(np.max(np.abs(Pg - Po)))
+    rec["check"] = {"against": "oracle, every row", "max_abs_dP": dP, "tolerance": tol,
+                    "index_agreement": float(np.mean(Ig == Io)), "indices_admissible": admissible(Ig, l, ez),
+                    "pass": bool(dP <= tol and admissible(Ig, l, ez))}
+    return rec
+
+
+def rec_abjoin(steps, warmup, dev):
+    """AB-join of two float32 ECG-like series n = 2^19, m = 128: FP32 sweep
+    and the FP64 GPU path, both directions; the oracle on 256 rows of each."""
+    import torch
+    import paper_1904_12626_amd as mpx
+    import workloads as W
+    A, Bh, m = W.abjoin_ecg()
+    Ag, Bg = torch.from_numpy(A).to(dev), torch.from_numpy(Bh).to(dev)
+    cells = mpx.abjoin_cells(A.size, Bh.size, m)
+    lA, lB = A.size - m + 1, Bh.size - m + 1
+    step32 = lambda: mpx.abjoin(Ag, Bg, m, precision="f32")  # noqa: E731
+    step64 = lambda: mpx.abjoin(Ag, Bg, m, precision="f64")  # noqa: E731
+    o32, med32, _ = ev_steps(step32, steps, warmup)
+    sw32, _ = lib_sweep_ms(step32, max(5, steps // 2))
+    o64, med64, _ = ev_steps(step64, steps, warmup)
+    sw64, _ = lib_sweep_ms(step64, 5)
+    tol = 1e-3 * np.sqrt(m)
+    P32 = np.concatenate([o32[0].double().cpu().numpy(), o32[2].double().cpu().numpy()])
+    I32 = np.concatenate([o32[1].cpu().numpy(), o32[3].cpu().numpy()])
+    P64 = np.concatenate([o64[0].double().cpu().numpy(), o64[2].double().cpu().numpy()])
+    I64 = np.concatenate([o64[1].cpu().numpy(), o64[3].cpu().numpy()])
+    dP = float(np.max(np.abs(P32 - P64)))
+    rec = {"workload": f"AB-join, two float32 ECG-like series n={A.size}, m={m}; P_ab, I_ab, P_ba, I_ba; "
+                       "FP32 sweep with FP64 stats and seeds, FP64 finalize",
+           "cells": cells, "dtype": "f32", "steps": steps, "warmup": warmup, "ms_per_step_median": med32,
+           "cells_per_s": cells / (med32 / 1e3), "roofline": roofline_of(cells, sw32, "k_sweep<float>"),
+           "fp64_path": {"ms_per_step_median": med64, "cells_per_s": cells / (med64 / 1e3),
+                         "sweep_ms_per_launch": sw64, "speedup_f32_over_f64": med64 / med32,
+                         "max_abs_dP_f32_vs_f64": dP, "index_agreement_f32_vs_f64": float(np.mean(I32 == I64))}}
+    from oracle import cimpl
+    rng = np.random.default_rng(0)
+    ra = np.sort(rng.choice(lA, 256, replace=False))
+    rb = np.sort(rng.choice(lB, 256, replace=False))
+    A64, B64 = A.astype(np.float64), Bh.astype(np.float64)
+    t0 = time.perf_counter()
+    Pa, Ia = cimpl.abjoin_rows(A64, B64, m, ra)
+    Pb, Ib = cimpl.abjoin_rows(B64, A64, m, rb)
+    dt = time.perf_counter() - t0
+    pairs = int(ra.size * lB + rb.size * lA)
+    rec["cpu_baseline"] = {"value": pairs / dt, "unit": "cells/s", "cores": cimpl.max_threads(), "kind": "oracle",
+                           "sample": f"{ra.size} rows of P_ab and {rb.size} rows of P_ba, {pairs} pairs, each O(m) "
+                                     f"in FP64, {dt:.1f} s"}
+    d32 = max(float(np.max(np.abs(P32[:lA][ra] - Pa))), float(np.max(np.abs(P32[lA:][rb] - Pb))))
+    d64 = max(float(np.max(np.abs(P64[:lA][ra] - Pa))), float(np.max(np.abs(P64[lA:][rb] - Pb))))
+    agree = float(np.mean(np.concatenate([I32[:lA][ra] == Ia, I32[lA:][rb] == Ib])))
+    rec["check"] = {"against": "oracle on 256 + 256 sampled rows; FP64 GPU path on every row",
+                    "max_abs_dP_f32_vs_oracle": d32, "max_abs_dP_f64_vs_oracle": d64,
+                    "index_agreement_f32_vs_oracle": agree, "max_abs_dP_f32_vs_f64": dP, "tolerance": tol,
+                    "min_P_ab_equals_min_P_ba": bool(abs(P32[:lA].min() - P32[lA:].min()) <= tol),
+                    "pass": bool(max(d32, dP) <= tol)}
+    return rec
+
+
+def rec_batch(steps, warmup, dev, log):
+    """512 ragged float32 random walks in one launch sequence, tile shape
+    from the autotuner, replayed from a captured graph."""
+    import torch
+    import paper_1904_12626_amd as mpx
+    from paper_1904_12626_amd import autotune as AT
+    import workloads as W
+    rb = W.batch_ragged()
+    Tc, off = rb.concat()
+    Tg = torch.from_numpy(Tc).to(dev)
+    lengths = [s.size for s in rb.series]
+    choice, entry = AT.tune_batch(Tg, lengths, rb.m, rb.ez, force=True, log=log, return_entry=True)
+    plans = {}
+
+    def plan_for(prec, slots=0, rows=0):
+        k = (prec, slots, rows)
+        if k not in plans:
+            plans[k] = mpx.BatchPlan(lengths, rb.m, rb.ez, dtype=torch.float32, device=dev, precision=prec,
+                                     tile_slots=slots, reseed_rows=rows)
+        return plans[k]
+
+    def replay_ms(plan):
+        Pg = torch.empty(plan.profile_length, dtype=torch.float32, device=dev)
+        Ig = torch.empty(plan.profile_length, dtype=torch.int64, device=dev)
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            plan.run(Tg, Pg, Ig)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            plan.run(Tg, Pg, Ig)
+        _, med, _ = ev_steps(graph.replay, steps, warmup)
+        return Pg, Ig, med
+
+    tuned = plan_for("f32", choice["tile_slots"], choice["reseed_rows"])
+    cells = tuned.cells
+    Pe, Ie = tuned.run(Tg)
+    Pr, Ir, med = replay_ms(tuned)
+    same = bool(torch.equal(Pr, Pe) and torch.equal(Ir, Ie))
+    sweep_ms, _ = lib_sweep_ms(lambda: tuned.run(Tg), 5)
+    _, _, med_default = replay_ms(plan_for("f32"))
+    P64, I64 = plan_for("f64").run(Tg)
+    Pg, Ig = Pr.double().cpu().numpy(), Ir.cpu().numpy()
+    P64, I64 = P64.double().cpu().numpy(), I64.cpu().numpy()
+    ratio, agree = [], []
+    for s, (a, b) in enumerate(zip(tuned.p_off[:-1], tuned.p_off[1:])):
+        tol = 1e-3 * np.sqrt(rb.m[s])
+        ratio.append(float(np.max(np.abs(Pg[a:b] - P64[a:b]))) / tol)
+        agree.append(np.mean(Ig[a:b] == I64[a:b]))
+    rec = {"workload": f"{len(lengths)} float32 random walks, lengths U{{2048..65536}}, m in {{32,64,128}}, ez=m/4; "
+                       "one launch sequence replayed from a captured graph; FP32 sweep, FP64 finalize",
+           "cells": cells, "dtype": "f32", "steps": steps, "warmup": warmup, "ms_per_step_median": med,
+           "cells_per_s": cells / (med / 1e3), "roofline": roofline_of(cells, sweep_ms, "k_sweep<float>"),
+           "graph_replay_equals_eager": same, "ms_per_step_median_library_defaults": med_default,
+           "autotune": {"space": entry["space"], "choice": choice, "budget": entry["budget"],
+                        "trials": [{k: t[k] for k in ("tile_slots", "reseed_rows", "sweep_ms", "within_budget")
+                                    if k in t} for t in entry["trials"]]}}
+    from oracle import cimpl
+    order = np.argsort(lengths, kind="stable")
+    short = [int(s) for s in order[:8]]
+    rng = np.random.default_rng(0)
+    rest = [int(s) for s in rng.choice(order[8:], 8, replace=False)]
+    t0 = time.perf_counter()
+    res, pairs = [], 0
+    for s in short:
+        T64 = rb.series[s].astype(np.float64)
+        Po, Io = cimpl.selfjoin(T64, rb.m[s], rb.ez[s])
+        res.append((s, np.arange(Po.size), Po, Io))
+        pairs += mpx.selfjoin_cells(T64.size, rb.m[s], rb.ez[s])
+    for s in rest:
+        T64 = rb.series[s].astype(np.float64)
+        l = T64.size - rb.m[s] + 1
+        rows = np.sort(rng.choice(l, 32, replace=False))
+        Po, Io = cimpl.selfjoin_rows(T64, rb.m[s], rb.ez[s], rows)
+        res.append((s, rows, Po, Io))
+        pairs += int(sum(l - (min(l - 1, r + rb.ez[s]) - max(0, r - rb.ez[s]) + 1) for r in rows))
+    dt = time.perf_counter() - t0
+    rec["cpu_baseline"] = {"value": pairs / dt, "unit": "cells/s", "cores": cimpl.max_threads(), "kind": "oracle",
+                           "sample": f"the whole joins of the 8 shortest series and 32 random rows of 8 other "
+                                     f"series, {pairs} pairs, each O(m) in FP64, {dt:.1f} s"}
+    worst, iok = 0.0, []
+    for s, rows, Po, Io in res:
+        a = tuned.p_off[s]
+        worst = max(worst, float(np.max(np.abs(Pg[a + rows] - Po))) / (1e-3 * np.sqrt(rb.m[s])))
+        iok.append(np.mean(Ig[a + rows] == Io))
+    rec["check"] = {"against": "oracle on 16 series (8 whole, 8 sampled); FP64 GPU batch on every series",
+                    "max_abs_dP_over_tolerance_vs_oracle": worst,
+                    "index_agreement_vs_oracle": float(np.mean(iok)),
+                    "max_abs_dP_over_tolerance_vs_f64": float(max(ratio)),
+                    "index_agreement_vs_f64": float(np.mean(agree)),
+                    "tolerance": "1e-3 sqrt(m_s) per series",
+                    "pass": bool(worst <= 1.0 and max(ratio) <= 1.0 and same)}
+    return rec
+
+
+def rec_diff(steps, warmup, dev, log):
+    """Differentiable profile of 64 float32 random walks n = 16384, m = 100:
+    forward + backward of L = sum(P) replayed from one captured graph, tile
+    shape from the autotuner; the FP64 reference gradient timed on the host."""
+    import torch
+    import paper_1904_12626_amd as mpx
+    from paper_1904_12626_amd import autotune as AT
+    import workloads as W
+    T, m, ez = W.diff_batch()
+    Bn, n = T.shape
+    Tg = torch.from_numpy(T).to(dev)
+    flat = Tg.reshape(-1)
+    choice, entry = AT.tune_batch(flat, [n] * Bn, [m] * Bn, [ez] * Bn, force=True, log=log, return_entry=True)
+    plan = mpx.BatchPlan([n] * Bn, [m] * Bn, [ez] * Bn, dtype=torch.float32, device=dev,
+                         tile_slots=choice["tile_slots"], reseed_rows=choice["reseed_rows"])
+    cells = plan.cells
+    ones = torch.ones(Bn, n - m + 1, dtype=torch.float32, device=dev)
+    xs = Tg.clone().requires_grad_(True)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        mpx.MatrixProfileFn.apply(xs, plan)[0].backward(ones)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    eager_grad = xs.grad.clone()
+    xs.grad = None
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        Pg, Ig = mpx.MatrixProfileFn.apply(xs, plan)
+        Pg.backward(ones)
+    _, med, _ = ev_steps(graph.replay, steps, warmup)
+    same = bool(torch.equal(xs.grad, eager_grad))
+    sweep_ms, fwd_ms = lib_sweep_ms(lambda: plan.run(flat), 5)
+    Pf, If = plan.run(flat)
+    gP = torch.ones(plan.profile_length, dtype=torch.float32, device=dev)
+    _, bwd_ms, _ = ev_steps(lambda: plan.backward(flat, If, gP), steps, warmup)
+    rec = {"workload": f"differentiable profile: {Bn} float32 random walks n={n}, m={m}, ez={ez}; forward + "
+                       "backward of L = sum(P) replayed as one captured graph",
+           "cells": cells, "dtype": "f32", "steps": steps, "warmup": warmup, "ms_per_step_median": med,
+           "cells_per_s": cells / (med / 1e3), "roofline": roofline_of(cells, sweep_ms, "k_sweep<float>"),
+           "forward_ms": fwd_ms, "backward_ms_median": bwd_ms, "graph_replay_equals_eager": same,
+           "note": "cells_per_s counts forward cells per second of forward+backward steps",
+           "autotune": {"space": entry["space"], "choice": choice, "budget": entry["budget"],
+                        "trials": [{k: t[k] for k in ("tile_slots", "reseed_rows", "sweep_ms", "within_budget")
+                                    if k in t} for t in entry["trials"]]}}
+    g = xs.grad.double().cpu().numpy()
+    Ih = Ig.cpu().numpy()
+    P64, _ = mpx.BatchPlan([n] * Bn, [m] * Bn, [ez] * Bn, dtype=torch.float32, device=dev,
+                           precision="f64").run(flat)
+    dP = float(np.max(np.abs(Pg.detach().double().cpu().numpy().reshape(-1) - P64.double().cpu().numpy())))
+    from oracle import mp_oracle as O
+    rng = np.random.default_rng(0)
+    sel = np.sort(rng.choice(Bn, 4, replace=False))
+    T64 = T.astype(np.float64)
+    t0 = time.perf_counter()
+    refs = [O.reference_gradient(T64[b], m, Ih[b], np.ones(Ih.shape[1])) for b in sel]
+    dt = time.perf_counter() - t0
+    rel = max(float(np.max(np.abs(g[b] - r)) / np.max(np.abs(r))) for b, r in zip(sel, refs))
+    rows = int(sel.size * Ih.shape[1])
+    rec["cpu_baseline"] = {"value": rows / dt, "unit": "rows/s", "cores": 1, "kind": "oracle",
+                           "sample": f"FP64 reference gradient (closed form through each row's argmin pair, numpy) "
+                                     f"of {sel.size} of the {Bn} series, {rows} rows, {dt:.1f} s; the GPU backward "
+                                     f"does {Bn * Ih.shape[1]} rows in {bwd_ms:.3f} ms"}
+    rec["check"] = {"against": "FP64 reference gradient on 4 series; FP64 GPU forward on every row",
+                    "max_rel_grad_err": rel, "grad_tolerance": 1e-4, "max_abs_dP_f32_vs_f64": dP,
+                    "tolerance": 1e-3 * np.sqrt(m), "pass": bool(rel <= 1e-4 and dP <= 1e-3 * np.sqrt(m) and same)}
+    return rec
+
+
+def extra_workloads(steps, warmup, dev, log):
+    out = {}
+    for name, fn in (("selfjoin_f64_n4096_m64", lambda: rec_selfjoin_f64(steps, warmup, dev)),
+                     ("abjoin_ecg_2x2p19_m128", lambda: rec_abjoin(steps, warmup, dev)),
+                     ("batch_ragged_512", lambda: rec_batch(steps, warmup, dev, log)),
+                     ("diff_batch_64x16384_m100", lambda: rec_diff(steps, warmup, dev, log))):
+        t0 = time.perf_counter()
+        try:
+            out[name] = fn()
+            r = out[name]
+            log(f"[bench] {name}: {r['ms_per_step_median']:.3f} ms/step, {r['cells_per_s']:.3e} cells/s, "
+                f"roofline {r['roofline']['frac']:.3f}, check pass={r['check']['pass']} "
+                f"({time.perf_counter() - t0:.1f} s)")
+        except Exception as e:  # keep the headline line even if one record fails
+            out[name] = {"error": f"{type(e).__name__}: {e}"}
+            log(f"[bench] {name}: FAILED {type(e).__name__}: {e}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -148,6 +536,8 @@ def main():
     ap.add_argument("--autotune", action="store_true",
                     help="pick tile slots and reseed rows with the autotuner before timing (search logged)")
     ap.add_argument("--cpu-rows", type=int, default=256, help="oracle rows timed for the CPU baseline (0 = skip)")
+    ap.add_argument("--no-workloads", action="store_true",
+                    help="default workload only: skip the records of the other workloads")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (a known-traffic reference "
                          "for hardware byte counters)")
@@ -309,20 +699,26 @@ def main():
         args.slots, args.reseed = ch["tile_slots"], ch["reseed_rows"]
         plans.clear() if wl["kind"] == "batch" else None
 
+    step_med = {}
+
     def timed(precision, steps, warmup):
         for _ in range(warmup):
             step(precision)
         torch.cuda.synchronize()
         mpx.timing_query()                      # drop earlier records
         mpx.timing_enable(True)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(steps):
+        for a, b in ev:
+            a.record()
             out = step(precision)
+            b.record()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         mpx.timing_enable(False)
         sweep_ms, total_ms, calls = mpx.timing_query()
+        step_med["ms"] = float(np.median([a.elapsed_time(b) for a, b in ev]))
         return out, (t1 - t0) * 1e3 / steps, sweep_ms / max(calls, 1), total_ms / max(calls, 1)
 
     log(f"[bench] workload: {wl['desc']}; cells={cells}")
@@ -374,6 +770,7 @@ def main():
     log(f"[bench] f32: {ms32:.2f} ms/step, sweep {sweep32:.2f} ms, launch sequence {tot32:.2f} ms")
     value = cells / (ms32 / 1e3)
     achieved = cells * OPS_PER_CELL / (sweep32 / 1e3) / 1e12
+    peak32 = PEAK_CELLS["f32"] * OPS_PER_CELL / 1e12
     result = {
         "metric": METRIC,
         "value": value,
@@ -382,6 +779,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms32,
+        "ms_per_step_median": step_med.get("ms"),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -389,10 +787,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl["desc"] + "; FP32 sweep with FP64 stats and seeds, FP64 finalize and recheck",
                    "cells": cells, "tile_slots": args.slots or "auto", "reseed_rows": args.reseed or "auto"},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_LANE_OPS / 1e12, "unit": "TOP/s",
-                     "frac": achieved / (PEAK_LANE_OPS / 1e12),
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak32, "unit": "TOP/s",
+                     "frac": achieved / peak32, "peak_model": PEAK_NOTE,
+                     "frac_one_instruction_per_cu_clock": achieved / (PEAK_LANE_OPS / 1e12),
                      "traffic": measured_traffic() if (wl["kind"] == "self" and args.n is None and not args.slots
                                                        and not args.reseed and args.workload == "selfjoin_large") else None,
+                     "traffic_source": "rocprofv3 FETCH_SIZE + WRITE_SIZE of the FP32 sweep on this workload "
+                                       "(copy-calibrated), profiles/k_sweep_f32_traffic.json; reported only "
+                                       "while the built sweep's gfx950 assembly hash equals the counted one, "
+                                       "else null",
                      "kernel": "k_sweep<float>", "ops_per_cell": OPS_PER_CELL,
                      "sweep_ms_per_launch": sweep32, "sweep_cells_per_s": cells / (sweep32 / 1e3)},
     }
@@ -506,8 +909,10 @@ def main():
         result["config"]["chunks_timed"] = len(anytime_plan(args.fraction).chunks)
 
     if not args.no_fp64 and wl["kind"] in ("self", "ab"):
-        out64, ms64, sweep64, tot64 = timed("f64", max(1, min(args.steps, 3)), 1)
-        log(f"[bench] f64: {ms64:.2f} ms/step, sweep {sweep64:.2f} ms")
+        # FP64 GPU path: 3 warm-ups, then the median of at least 5 event-timed steps
+        out64, ms64, _ = ev_steps(lambda: step("f64"), max(5, min(args.steps, 8)), 3)
+        sweep64, _ = lib_sweep_ms(lambda: step("f64"), 3)
+        log(f"[bench] f64: {ms64:.2f} ms/step (median), sweep {sweep64:.2f} ms")
         P32, I32 = out32[0].double().cpu().numpy(), out32[1].cpu().numpy()
         P64, I64 = out64[0].double().cpu().numpy(), out64[1].cpu().numpy()
         if wl["kind"] == "ab":   # both directions
@@ -522,11 +927,13 @@ def main():
             raw = float(np.max(np.abs(Praw.double().cpu().numpy()[fin] - P64[fin])))
         result["fp64_path"] = {
             "value": cells / (ms64 / 1e3), "ms_per_step": ms64, "sweep_ms_per_launch": sweep64,
-            "speedup_f32_over_f64": ms64 / ms32,
+            "speedup_f32_over_f64": ms64 / ms32, "steps": max(5, min(args.steps, 8)), "warmup": 3,
+            "timing": "median of event-timed steps",
             "max_abs_dP_f32_vs_f64": float(np.max(np.abs(P32[fin] - P64[fin]))),
             "max_abs_dP_f32_raw_vs_f64": raw,
             "index_agreement_f32_vs_f64": float(np.mean(I32 == I64)),
             "tolerance": 1e-3 * np.sqrt(m),
+            "roofline": roofline_of(cells, sweep64, "k_sweep<double>", "f64"),
         }
 
     if args.cpu_rows > 0 and wl["kind"] == "self":
@@ -537,6 +944,7 @@ def main():
         if wl["planted"] is not None:
             for a, b in wl["planted"].motif_pairs:
                 rows += [a, b]
+            rows += list(wl["planted"].discords)
         rows = np.array(sorted(set(int(r) for r in rows)), dtype=np.int64)
         T64 = T.astype(np.float64)
         threads = cimpl.max_threads()
@@ -548,17 +956,23 @@ def main():
         I32 = out32[1].cpu().numpy()[rows]
         result["cpu_baseline"] = {
             "value": pairs / dt, "unit": "cells/s", "cores": threads, "kind": "oracle",
-            "sample": f"{rows.size} full rows of the same self-join ({args.cpu_rows} random + planted motif "
-                      f"members), {pairs} pairs, each O(m) in FP64, {dt:.1f} s",
+            "sample": f"{rows.size} full rows of the same self-join ({args.cpu_rows} random + the planted motif "
+                      f"members and discords), {pairs} pairs, each O(m) in FP64, {dt:.1f} s",
         }
+        tol = 1e-3 * np.sqrt(m)
+        dP = float(np.max(np.abs(P32 - Po)))
         result["oracle_check"] = {
             "rows": int(rows.size),
-            "max_abs_dP_f32_vs_oracle": float(np.max(np.abs(P32 - Po))),
+            "max_abs_dP_f32_vs_oracle": dP,
             "index_agreement": float(np.mean(I32 == Io)),
+            "tolerance": tol,
         }
+        ok = dP <= tol
         if not args.no_fp64:
             P64r = out64[0].double().cpu().numpy()[rows]
             result["oracle_check"]["max_abs_dP_f64_vs_oracle"] = float(np.max(np.abs(P64r - Po)))
+            ok = ok and result["fp64_path"]["max_abs_dP_f32_vs_f64"] <= tol
+        result["oracle_check"]["pass"] = bool(ok)
     if args.cpu_rows > 0 and wl["kind"] == "anytime":
         from oracle import cimpl
         plan = anytime_plan(args.fraction)
@@ -629,6 +1043,14 @@ def main():
         }
     if "cpu_baseline" in result:
         result["cpu_baseline"]["host"] = host_cpu()
+    if (args.workload == "selfjoin_large" and not args.no_workloads and args.n is None and not args.slots
+            and not args.reseed and not args.autotune):
+        vc = valu_ceiling(log)
+        if vc is not None:
+            result["roofline"]["ceilings"] = ceilings(vc, result["roofline"]["sweep_cells_per_s"],
+                                                      result.get("fp64_path", {}).get("sweep_ms_per_launch"),
+                                                      cells)
+        result["workloads"] = extra_workloads(max(5, min(args.steps, 20)), 3, dev, log)
     print(json.dumps(result), flush=True)
 
 

@@ -52,6 +52,12 @@ def _hipcc() -> str:
     return "hipcc"
 
 
+# Issue-rate probe of the sweep's VALU instruction mix (bench.py runs it and
+# reports the sweep against the rate it measures)
+PROBE_SRC = os.path.join(ROOT, "bench_valu.hip")
+PROBE = os.path.join(OBJ, "bench_valu")
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(OBJ, exist_ok=True)
     hipcc = _hipcc()
@@ -88,10 +94,19 @@ def build(verbose: bool = False) -> str:
                         inside = False
         return h.hexdigest()
 
-    with ThreadPoolExecutor(max_workers=len(SOURCES) + 1) as ex:
+    def probe():
+        cmd = [hipcc, "--offload-arch=gfx950", "-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang",
+               "-packed-fp32-ops", "-Wno-unused-command-line-argument", PROBE_SRC, "-o", PROBE]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"hipcc failed for bench_valu.hip:\n{r.stdout}\n{r.stderr}")
+
+    with ThreadPoolExecutor(max_workers=len(SOURCES) + 2) as ex:
         isa = ex.submit(sweep_isa)
+        prb = ex.submit(probe)
         objs = list(ex.map(compile_one, SOURCES.items()))
         isa_hash = isa.result()
+        prb.result()
     tmp = LIB + ".tmp"
     cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)

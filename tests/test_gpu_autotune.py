@@ -36,13 +36,16 @@ def test_autotune_selfjoin_and_cache(tmp_path, monkeypatch):
     best = min(ok, key=lambda t: t["sweep_ms"])
     assert (best["tile_slots"], best["reseed_rows"]) == (choice["tile_slots"], choice["reseed_rows"])
     for t in trials:
-        if "max_abs_dP_vs_f64" in t:
-            assert t["within_budget"] == (t["max_abs_dP_vs_f64"] <= budget)
+        if "raw_max_abs_dP_vs_f64" in t:
+            assert t["within_budget"] == (t["raw_max_abs_dP_vs_f64"] <= budget
+                                          and t["index_excess_vs_f64"] <= budget)
+    assert entry["space"] == {"tile_slots": list(AT.SLOTS), "reseed_rows": list(AT.ROWS)}
     assert any("chose" in s for s in lines)
     # a second call answers from the cache, and the chosen options reproduce
     # a profile within the budget of the FP64 sweep
     again = AT.tune_selfjoin(T, m, ez, log=lines.append)
     assert again == choice
-    P, _ = mpx.selfjoin(T, m, ez, tile_slots=choice["tile_slots"], reseed_rows=choice["reseed_rows"])
+    P, _ = mpx.selfjoin(T, m, ez, tile_slots=choice["tile_slots"], reseed_rows=choice["reseed_rows"],
+                        fp64_finalize=False)
     P64, _ = mpx.selfjoin(T, m, ez, precision="f64")
     assert float((P.double() - P64.double()).abs().max()) <= budget
