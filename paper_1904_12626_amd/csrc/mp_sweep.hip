@@ -217,8 +217,6 @@ __global__ void __launch_bounds__(64, (SweepMinWaves<F, DT>::value))
   using K = typename IK::K;
   using V4 = typename FTraits<F>::V4;
 
-  __shared__ K lrow[TP][65];
-  __shared__ K lcol[TP];
 
   const int lane = threadIdx.x;
   auto series = [&](int i) -> SeriesDesc { return s_ext ? ldu(s_ext + i) : plan.s_inl[i]; };
@@ -330,22 +328,6 @@ __global__ void __launch_bounds__(64, (SweepMinWaves<F, DT>::value))
         atomicMin((unsigned long long *)(ckeys + c), (unsigned long long)pack_global(val, i, ib));
       }
     };
-    // Rows [fb, fb+cnt) of this tile: reduce the 64 lane partials of each
-    // row (one row per lane) and merge; merge the column minima that left
-    // the strip through lane 0 at those rows.
-    auto flush = [&](int64_t fb, int cnt) {
-      __syncthreads();
-      if (lane < cnt) {
-        K best = lrow[lane][0];
-#pragma unroll 8
-        for (int q = 1; q < 64; ++q) best = IK::kmin(best, lrow[lane][q]);
-        const int64_t s = fb + lane;
-        if (s < nr) emit_row(i0 + s, best);
-        emit_col(i0 + s + k0, lcol[lane]);
-      }
-      __syncthreads();
-    };
-
     if constexpr (std::is_same_v<F, double>) {
       // FP64: one row at a time (there is no 3-input FP64 minimum, so row
       // pairs would only hold a second key array).  The records of a block's
@@ -436,6 +418,37 @@ __global__ void __launch_bounds__(64, (SweepMinWaves<F, DT>::value))
     // each row of the pair, so its minimum is a single 3-input min, and each
     // row's own minimum is a chain of 3-input mins.
     static_assert(TP % 2 == 0 && DT % 2 == 0, "row pairs");
+    // Row partials: lane q's minimum of row u sits in component q % 4 of
+    // lrow[q / 4][u].  A row's 64 writes then land on distinct banks (the
+    // stride of TP + 1 records is 20 banks mod 64), and the flush (lane r
+    // reduces row r) reads them as 16 contiguous 16-byte records per lane.
+    __shared__ int4 lrow[16][TP + 1];
+    __shared__ K lcol[TP];
+    int *const lrow_w = reinterpret_cast<int *>(&lrow[lane >> 2][0]) + (lane & 3);
+    // Rows [fb, fb+cnt) of this tile: reduce the 64 lane partials of each
+    // row (one row per lane) and merge; merge the column minima that left
+    // the strip through lane 0 at those rows.
+    auto flush = [&](int64_t fb, int cnt) {
+      __syncthreads();
+      if (lane < cnt) {
+        const int4 v0 = lrow[0][lane];
+        K best = IK::kmin3(v0.x, v0.y, IK::kmin(v0.z, v0.w));
+#pragma unroll
+        for (int q = 1; q < 16; ++q) {
+          const int4 v = lrow[q][lane];
+          best = IK::kmin3(best, v.x, v.y);
+          best = IK::kmin3(best, v.z, v.w);
+        }
+        const int64_t s = fb + lane;
+        if (s < nr) emit_row(i0 + s, best);
+        emit_col(i0 + s + k0, lcol[lane]);
+      }
+      __syncthreads();
+    };
+    // The row and entering-column records of a pair of rows are loaded one
+    // pair ahead (scalar loads; a pair past the tile reads padding records,
+    // which are never used), so their latency overlaps a pair's arithmetic.
+    V4 nrd0 = ldu(rowd + i0), nrd1 = ldu(rowd + i0 + 1), nnc0 = ldu(newcol), nnc1 = ldu(newcol + 1);
     for (int64_t sb = 0; sb < nsteps; sb += TP) {
       const int nb = (int)min((int64_t)TP, nsteps - sb);  // a multiple of DT (even)
       static_for<TP / 2>([&](auto qc) {
@@ -443,9 +456,14 @@ __global__ void __launch_bounds__(64, (SweepMinWaves<F, DT>::value))
         constexpr int r0 = u0 % DT, r1 = u1 % DT;  // register of slot 0 in each row
         if (u0 < nb) {
           K k0[DT], k1[DT];
+          const V4 rd0 = nrd0, rd1 = nrd1, nc0 = nnc0, nc1 = nnc1;
+          nrd0 = ldu(rowd + i0 + sb + u0 + 2);
+          nrd1 = ldu(rowd + i0 + sb + u1 + 2);
+          nnc0 = ldu(newcol + sb + u0 + 2);
+          nnc1 = ldu(newcol + sb + u1 + 2);
           // ---- row u0
           {
-            const V4 rd = ldu(rowd + i0 + sb + u0);
+            const V4 rd = rd0;
             const F ai = rd.x, gi = rd.y, si = rd.z, ui = rd.w;
             static_for<DT>([&](auto tc) {
               constexpr int t = decltype(tc)::value;
@@ -454,10 +472,10 @@ __global__ void __launch_bounds__(64, (SweepMinWaves<F, DT>::value))
               C[t] = fma(A[p], gi, C[t]);
               C[t] = fma(G[p], ai, C[t]);
             });
-            lrow[u0][lane] = IK::rowmin(k0);
+            lrow_w[4 * u0] = IK::rowmin(k0);
             CP[r0] = IK::kmin(CP[r0], k0[0]);
             if (lane == 0) lcol[u0] = CP[r0];
-            const V4 nc = ldu(newcol + sb + u0);
+            const V4 nc = nc0;
             CP[r0] = IK::shl(CP[r0]);
             A[r0] = shlv<F>(A[r0], nc.x);
             G[r0] = shlv<F>(G[r0], nc.y);
@@ -465,7 +483,7 @@ __global__ void __launch_bounds__(64, (SweepMinWaves<F, DT>::value))
           }
           // ---- row u1
           {
-            const V4 rd = ldu(rowd + i0 + sb + u1);
+            const V4 rd = rd1;
             const F ai = rd.x, gi = rd.y, si = rd.z, ui = rd.w;
             static_for<DT>([&](auto tc) {
               constexpr int t = decltype(tc)::value;
@@ -474,7 +492,7 @@ __global__ void __launch_bounds__(64, (SweepMinWaves<F, DT>::value))
               C[t] = fma(A[p], gi, C[t]);
               C[t] = fma(G[p], ai, C[t]);
             });
-            lrow[u1][lane] = IK::rowmin(k1);
+            lrow_w[4 * u1] = IK::rowmin(k1);
           }
           // ---- column minima: register p met slot p-r0 in row u0 and slot
           // p-r1 in row u1; register r0 holds the column that entered after
@@ -488,7 +506,7 @@ __global__ void __launch_bounds__(64, (SweepMinWaves<F, DT>::value))
             }
           });
           if (lane == 0) lcol[u1] = CP[r1];
-          const V4 nc = ldu(newcol + sb + u1);
+          const V4 nc = nc1;
           CP[r1] = IK::shl(CP[r1]);
           A[r1] = shlv<F>(A[r1], nc.x);
           G[r1] = shlv<F>(G[r1], nc.y);
