@@ -31,7 +31,7 @@ import torch
 from . import _binding as B
 
 SLOTS = (8, 12, 16)
-ROWS = (1024, 2048, 4096, 8192)
+ROWS = (512, 1024, 2048, 4096, 8192)
 
 
 def _cache_path():

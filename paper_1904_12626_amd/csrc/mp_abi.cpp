@@ -165,7 +165,8 @@ void finish_job(Job &j) {
 
 struct Layout {
   size_t mu, sig, keys, flags, nc, nv, rc, special, counters, segp, segs, segq, rescan, sdesc, wdesc, kmask;
-  size_t b_mu, b_isig, b_wpos, b_coef, b_nbr, b_count, b_fill, b_off, b_tmp, b_erec, b_wrec, b_chunk;
+  size_t b_mu, b_isig, b_wpos, b_coef, b_nbr, b_count, b_fill, b_off, b_tmp, b_erec, b_wrec, b_chunk, b_big,
+      b_nbig;
   size_t total;
 };
 
@@ -204,6 +205,8 @@ Layout layout_of(const Job &j, bool with_batch_tables) {
     L.b_erec = take(sizeof(mpx::BwdEdge) * 2 * tl);
     L.b_wrec = take(sizeof(mpx::BwdWin) * tl);
     L.b_chunk = take(8 * ((tl + 1023) / 1024 + 1));
+    L.b_big = take(8 * (tl / (size_t)mpx::kBwdSmallBucket + 1));
+    L.b_nbig = take(8);
     L.sdesc = take(sizeof(SeriesDesc) * j.series.size());
     L.wdesc = take(sizeof(SweepDesc) * j.sweeps.size());
     L.kmask = take(4 * std::max<size_t>(1, j.kmask.size()));
@@ -246,6 +249,8 @@ mpx::BwdWork bwd_work_of(const Layout &L, void *ws) {
   w.erec = (mpx::BwdEdge *)(b + L.b_erec);
   w.wrec = (mpx::BwdWin *)(b + L.b_wrec);
   w.chunk = (int64_t *)(b + L.b_chunk);
+  w.big = (int64_t *)(b + L.b_big);
+  w.nbig = (unsigned long long *)(b + L.b_nbig);
   return w;
 }
 

@@ -54,20 +54,46 @@ __device__ __forceinline__ int find_series_by_t(const Plan &plan, int64_t x) {
 
 }  // namespace
 
+// The samples of a workgroup's 256 consecutive windows, staged once in LDS
+// (256 + m - 1 values) when the windows lie in one series and m <= kTileM;
+// otherwise the kernels read the series directly.  Either way every window
+// sees the same values, so results do not depend on the staging.
+constexpr int kTileW = 256;
+constexpr int kTileM = 2048;
+
+template <typename Tin>
+__device__ __forceinline__ bool stage_tile(const Plan &plan, const Tin *__restrict__ Tb, int64_t total_l,
+                                           double *xs) {
+  const int64_t w0 = (int64_t)blockIdx.x * kTileW;
+  const int64_t wl = min(w0 + kTileW - 1, total_l - 1);
+  const int s0 = find_series_by_w(plan, w0);
+  const SeriesDesc S = plan.series(s0);
+  if (s0 != find_series_by_w(plan, wl) || S.m > kTileM) return false;
+  const Tin *base = series_samples(plan, Tb, S) + (w0 - S.w_off);
+  const int cnt = (int)(wl - w0) + S.m;
+  for (int t = threadIdx.x; t < cnt; t += blockDim.x) xs[t] = (double)base[t];
+  __syncthreads();
+  return true;
+}
+
 // Window statistics for the gradient: mean and 1/sigma (0 for constant or
 // non-finite windows, whose rows and neighbours contribute nothing).
 template <typename Tin>
 __global__ void __launch_bounds__(256) k_bwd_stats(Plan plan, BwdWork b, const Tin *__restrict__ Tb,
                                                    int64_t total_l) {
+  __shared__ double xs[kTileW + kTileM];
+  const bool tiled = stage_tile(plan, Tb, total_l, xs);
   const int64_t wi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (wi == 0) *b.nbig = 0ull;
   if (wi >= total_l) return;
   const SeriesDesc S = plan.series(find_series_by_w(plan, wi));
   const Tin *x = series_samples(plan, Tb, S) + (wi - S.w_off);
+  const double *xl = xs + threadIdx.x;
   const int m = S.m;
   double s = 0.0, lo = 0.0, hi = 0.0;
   bool ok = true;
   for (int u = 0; u < m; ++u) {
-    const double v = (double)x[u];
+    const double v = tiled ? xl[u] : (double)x[u];
     if (!isfinite(v)) ok = false;
     if (u == 0) { lo = v; hi = v; }
     lo = fmin(lo, v);
@@ -77,7 +103,7 @@ __global__ void __launch_bounds__(256) k_bwd_stats(Plan plan, BwdWork b, const T
   const double mu = s / m;
   double q = 0.0;
   for (int u = 0; u < m; ++u) {
-    const double dv = (double)x[u] - mu;
+    const double dv = (tiled ? xl[u] : (double)x[u]) - mu;
     q = fma(dv, dv, q);
   }
   const double sg = sqrt(q / m);
@@ -96,6 +122,8 @@ __global__ void __launch_bounds__(256) k_bwd_coef(Plan plan, BwdWork b, const Ti
   // z_i - z_j must be exactly 0 for identical windows (d == 0 takes the
   // subgradient 0): no contraction of the products into the subtraction.
 #pragma clang fp contract(off)
+  __shared__ double xs[kTileW + kTileM];
+  const bool tiled = stage_tile(plan, Tb, total_l, xs);
   const int64_t wi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (wi >= total_l) return;
   const int si = find_series_by_w(plan, wi);
@@ -114,8 +142,9 @@ __global__ void __launch_bounds__(256) k_bwd_coef(Plan plan, BwdWork b, const Ti
       const Tin *xj = series_samples(plan, Tb, Q) + j;
       const double mi = b.mu[wi], mj = b.mu[jw];
       double d2 = 0.0, dot = 0.0;
+      const double *xl = xs + threadIdx.x;
       for (int u = 0; u < S.m; ++u) {
-        const double zi = ((double)xi[u] - mi) * isi, zj = ((double)xj[u] - mj) * isj;
+        const double zi = ((tiled ? xl[u] : (double)xi[u]) - mi) * isi, zj = ((double)xj[u] - mj) * isj;
         d2 = fma(zi - zj, zi - zj, d2);
         dot = fma(zi, zj, dot);
       }
@@ -147,20 +176,82 @@ __global__ void __launch_bounds__(256) k_bwd_place(BwdWork b, int64_t total_l) {
   const int64_t base = b.off[jw] + (b.nbr[jw] >= 0 ? 1 : 0);
   const unsigned long long pos = atomicAdd(&b.fill[jw], 1ull);
   b.tmp[base + (int64_t)pos] = wi;
+  // the first row placed in a large bucket lists it for the workgroup sort
+  if (pos == 0 && b.off[jw + 1] - base > kBwdSmallBucket) b.big[atomicAdd(b.nbig, 1ull)] = jw;
 }
 
-// Bucket edges in increasing row order: a row's slot is the number of rows of
-// its bucket with a smaller index.
+// Edge record of bucket row wi (neighbour window jw): the row's multiple of
+// its own window's z, applied on window jw.
+__device__ __forceinline__ BwdEdge bucket_edge(const BwdWork &b, int64_t wi, int64_t jw) {
+  const Double4 c = reinterpret_cast<const Double4 *>(b.coef)[wi];
+  return BwdEdge{c.w * b.isig[wi], b.mu[wi], b.wpos[wi] - b.wpos[jw], c.z};
+}
+
+// Bucket edges in increasing row order.  In a bucket of at most
+// kBwdSmallBucket rows a row's slot is the number of rows of the bucket with
+// a smaller index; larger buckets are left to k_bwd_bigsort.
 __global__ void __launch_bounds__(256) k_bwd_rank(BwdWork b, int64_t total_l) {
   const int64_t wi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (wi >= total_l) return;
   const int64_t jw = b.nbr[wi];
   if (jw < 0) return;
   const int64_t a = b.off[jw] + (b.nbr[jw] >= 0 ? 1 : 0), e = b.off[jw + 1];
+  if (e - a > kBwdSmallBucket) return;
   int64_t r = 0;
   for (int64_t p = a; p < e; ++p) r += b.tmp[p] < wi;
-  const Double4 c = reinterpret_cast<const Double4 *>(b.coef)[wi];
-  b.erec[a + r] = BwdEdge{c.w * b.isig[wi], b.mu[wi], b.wpos[wi] - b.wpos[jw], c.z};
+  b.erec[a + r] = bucket_edge(b, wi, jw);
+}
+
+// Large buckets: one workgroup sorts a bucket's row indices (a bitonic
+// network whose comparators all point the same way, so any length works:
+// the missing elements past the end count as +infinity and never move) in
+// LDS, or in place in global memory when longer than the LDS buffer; then
+// writes the bucket's edges in that order.  O(h log^2 h) for h rows.
+constexpr int kSortLds = 4096;
+__device__ __forceinline__ void cmpx(int64_t *v, int64_t i, int64_t p) {
+  const int64_t x = v[i], y = v[p];
+  if (x > y) {
+    v[i] = y;
+    v[p] = x;
+  }
+}
+__device__ void sort_rows(int64_t *v, int64_t n) {
+  int64_t N = 1;
+  while (N < n) N <<= 1;
+  for (int64_t k = 2; k <= N; k <<= 1) {
+    const int64_t hk = k >> 1;
+    for (int64_t t = threadIdx.x; t < N / 2; t += blockDim.x) {
+      const int64_t i = (t / hk) * k + (t % hk), p = i ^ (k - 1);
+      if (p < n) cmpx(v, i, p);
+    }
+    __syncthreads();
+    for (int64_t j = k >> 2; j >= 1; j >>= 1) {
+      for (int64_t t = threadIdx.x; t < N / 2; t += blockDim.x) {
+        const int64_t i = (t / j) * 2 * j + (t % j), p = i | j;
+        if (p < n) cmpx(v, i, p);
+      }
+      __syncthreads();
+    }
+  }
+}
+__global__ void __launch_bounds__(256) k_bwd_bigsort(BwdWork b) {
+  __shared__ int64_t ks[kSortLds];
+  const unsigned long long nb = *b.nbig;
+  for (unsigned long long q = blockIdx.x; q < nb; q += gridDim.x) {
+    const int64_t jw = b.big[q];
+    const int64_t a = b.off[jw] + (b.nbr[jw] >= 0 ? 1 : 0), h = b.off[jw + 1] - a;
+    int64_t *v = b.tmp + a;
+    if (h <= kSortLds) {
+      for (int64_t t = threadIdx.x; t < h; t += blockDim.x) ks[t] = v[t];
+      __syncthreads();
+      sort_rows(ks, h);
+      v = ks;
+    } else {
+      sort_rows(v, h);
+    }
+    for (int64_t t = threadIdx.x; t < h; t += blockDim.x) b.erec[a + t] = bucket_edge(b, v[t], jw);
+    __syncthreads();
+  }
 }
 
 // Per window: its own alpha plus the gammas of its bucket, in edge order.
@@ -298,6 +389,7 @@ hipError_t launch_backward(const Plan &plan, const BwdWork &b, const void *T, bo
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_bwd_place, gl, blk, 0, st, b, total_l);
   hipLaunchKernelGGL(k_bwd_rank, gl, blk, 0, st, b, total_l);
+  hipLaunchKernelGGL(k_bwd_bigsort, dim3(256), blk, 0, st, b);
   hipLaunchKernelGGL(k_bwd_window, gl, blk, 0, st, b, total_l);
   if (t_f64)
     hipLaunchKernelGGL((k_bwd_gather<double, double>), gn, blk, 0, st, plan, b, (const double *)T,

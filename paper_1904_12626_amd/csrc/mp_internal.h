@@ -129,7 +129,12 @@ struct BwdWork {
   BwdEdge *erec;       // [2 total_l] edges
   BwdWin *wrec;        // [total_l] per-window self coefficient
   int64_t *chunk;      // [ceil(total_l / 1024) + 1] scan partials
+  int64_t *big;        // [total_l / kBwdSmallBucket + 1] buckets with more than kBwdSmallBucket rows
+  unsigned long long *nbig;  // [1] entries of `big`
 };
+// Buckets of at most this many rows are ordered by a per-row count; larger
+// ones (hub windows named by many rows) are sorted by one workgroup each.
+constexpr int64_t kBwdSmallBucket = 64;
 
 struct Outputs {
   void *P[2];
