@@ -294,9 +294,14 @@ __device__ __forceinline__ void covering(const Plan &plan, int64_t x, int64_t &l
 // One wave = 64 consecutive samples.  Every sample of a series is covered by
 // at least one window and the covering ranges are non-decreasing in the
 // sample index, so the wave walks [lo(first sample), hi(last sample)].
+// Records are fetched 64 at a time, one per lane (coalesced, all in flight
+// together), staged in the wave's own LDS slots and read back by the whole
+// wave as broadcasts (one 16-byte read for a window's, two for an edge's,
+// instead of two lane reads per 8-byte field).
 template <typename Tin, typename Tg>
 __global__ void __launch_bounds__(256) k_bwd_gather(Plan plan, BwdWork b, const Tin *__restrict__ Tb,
                                                     Tg *gT, int64_t total_n) {
+  __shared__ double4 stage[4][64];  // per wave: 64 window or edge records
   const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t x0 = uni64(x - (int64_t)(threadIdx.x & 63));
   if (x0 >= total_n) return;
@@ -315,25 +320,27 @@ __global__ void __launch_bounds__(256) k_bwd_gather(Plan plan, BwdWork b, const 
   const BwdEdge *__restrict__ erec = b.erec;
   const int64_t *__restrict__ off = b.off;
   const int lane = threadIdx.x & 63;
+  double4 *const st = stage[threadIdx.x >> 6];
+  double2 *const st2 = reinterpret_cast<double2 *>(st);  // st2[2k]: c, mu; st2[2k+1]: delta, window
   double acc = 0.0;
-  // Records are fetched 64 at a time, one per lane (coalesced, all in
-  // flight together), and handed to the whole wave with lane reads.
   // First the multiples of each covering window's own z ...
   for (int64_t c = lo_w; c <= hi_w; c += 64) {
-    double sc_l = 0.0, mu_l = 0.0;
+    double2 wr = make_double2(0.0, 0.0);
     if (c + lane <= hi_w) {
-      const BwdWin wr = wrec[c + lane];
-      sc_l = wr.sc;
-      mu_l = wr.mu;
+      const BwdWin w = wrec[c + lane];
+      wr = make_double2(w.sc, w.mu);
     }
+    st2[2 * lane] = wr;
+    __builtin_amdgcn_wave_barrier();
     const int cnt = (int)min((int64_t)64, hi_w - c + 1);
     for (int k = 0; k < cnt; ++k) {
-      const double sc = lane_d(sc_l, k), mu = lane_d(mu_l, k);
+      const double2 r = st2[2 * k];
       const int64_t d = c + k;
       // sc is 0 for windows without gradient, including non-finite ones
       // whose samples must not reach the sum
-      if (d >= lo_t && d <= hi_t && sc != 0.0) acc = fma(sc, xt - mu, acc);
+      if (d >= lo_t && d <= hi_t && r.x != 0.0) acc = fma(r.x, xt - r.y, acc);
     }
+    __builtin_amdgcn_wave_barrier();
   }
   // ... then the edges of the covering windows, one flat run of the edge
   // array (each edge carries its destination window).  Eight edges per
@@ -343,29 +350,32 @@ __global__ void __launch_bounds__(256) k_bwd_gather(Plan plan, BwdWork b, const 
   // window -1, which no lane covers.
   const int64_t eb = uni64(off[lo_w]), ee = uni64(off[hi_w + 1]);
   for (int64_t c = eb; c < ee; c += 64) {
-    double qc = 0.0, qmu = 0.0;
-    int64_t qdelta = 0, qdst = -1;
+    double4 q = make_double4(0.0, 0.0, 0.0, __longlong_as_double(-1ll));
     if (c + lane < ee) {
-      const BwdEdge q = erec[c + lane];
-      qc = q.c;
-      qmu = q.mu;
-      qdelta = q.delta;
-      qdst = __double_as_longlong(q.gam);
+      const BwdEdge e = erec[c + lane];
+      q = make_double4(e.c, e.mu, __longlong_as_double(e.delta), e.gam);
     }
+    st[lane] = q;
+    __builtin_amdgcn_wave_barrier();
     const int cnt = ((int)min((int64_t)64, ee - c) + 7) & ~7;
     for (int k = 0; k < cnt; k += 8) {
       double v[8];
       bool in[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        const int64_t d = lane_i(qdst, k + u);
+        const double2 dd = st2[2 * (k + u) + 1];
+        const int64_t d = __double_as_longlong(dd.y);
         in[u] = d >= lo_t && d <= hi_t;
-        v[u] = (double)xp[in[u] ? lane_i(qdelta, k + u) : 0];
+        v[u] = (double)xp[in[u] ? __double_as_longlong(dd.x) : 0];
       }
 #pragma unroll
-      for (int u = 0; u < 8; ++u)
-        if (in[u]) acc = fma(lane_d(qc, k + u), v[u] - lane_d(qmu, k + u), acc);
+      for (int u = 0; u < 8; ++u) {
+        const double2 cm = st2[2 * (k + u)];
+        const double t = fma(cm.x, v[u] - cm.y, acc);
+        acc = in[u] ? t : acc;
+      }
     }
+    __builtin_amdgcn_wave_barrier();
   }
   if (act) gT[x] = (Tg)acc;
 }
