@@ -61,12 +61,13 @@ __device__ __forceinline__ int find_series_by_t(const Plan &plan, int64_t x) {
 constexpr int kTileW = 256;
 constexpr int kTileM = 2048;
 
+// Returns whether the tile was staged; s0 = the series of the first window.
 template <typename Tin>
 __device__ __forceinline__ bool stage_tile(const Plan &plan, const Tin *__restrict__ Tb, int64_t total_l,
-                                           double *xs) {
+                                           double *xs, int &s0) {
   const int64_t w0 = (int64_t)blockIdx.x * kTileW;
   const int64_t wl = min(w0 + kTileW - 1, total_l - 1);
-  const int s0 = find_series_by_w(plan, w0);
+  s0 = find_series_by_w(plan, w0);
   const SeriesDesc S = plan.series(s0);
   if (s0 != find_series_by_w(plan, wl) || S.m > kTileM) return false;
   const Tin *base = series_samples(plan, Tb, S) + (w0 - S.w_off);
@@ -82,33 +83,50 @@ template <typename Tin>
 __global__ void __launch_bounds__(256) k_bwd_stats(Plan plan, BwdWork b, const Tin *__restrict__ Tb,
                                                    int64_t total_l) {
   __shared__ double xs[kTileW + kTileM];
-  const bool tiled = stage_tile(plan, Tb, total_l, xs);
+  int s0;
+  const bool tiled = stage_tile(plan, Tb, total_l, xs, s0);
   const int64_t wi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (wi == 0) *b.nbig = 0ull;
   if (wi >= total_l) return;
-  const SeriesDesc S = plan.series(find_series_by_w(plan, wi));
+  const SeriesDesc S = plan.series(tiled ? s0 : find_series_by_w(plan, wi));
   const Tin *x = series_samples(plan, Tb, S) + (wi - S.w_off);
-  const double *xl = xs + threadIdx.x;
   const int m = S.m;
-  double s = 0.0, lo = 0.0, hi = 0.0;
-  bool ok = true;
-  for (int u = 0; u < m; ++u) {
-    const double v = tiled ? xl[u] : (double)x[u];
-    if (!isfinite(v)) ok = false;
-    if (u == 0) { lo = v; hi = v; }
-    lo = fmin(lo, v);
-    hi = fmax(hi, v);
-    s += v;
+  double mu, sg;
+  bool same = true, ok;
+  // instantiated once for the LDS tile and once for global memory
+  auto body = [&](auto at) {
+    const double v0 = at(0);
+    double s = 0.0;
+#pragma unroll 4
+    for (int u = 0; u < m; ++u) {
+      const double v = at(u);
+      same &= (v == v0);  // every sample equal to the first: a constant window
+      s += v;
+    }
+    // A non-finite sample makes the sum non-finite; a sum that is not finite
+    // only because finite samples overflowed is told apart sample by sample.
+    ok = isfinite(s);
+    if (!ok) {
+      ok = true;
+      for (int u = 0; u < m; ++u) ok &= (bool)isfinite(at(u));
+    }
+    mu = s / m;
+    double q = 0.0;
+#pragma unroll 4
+    for (int u = 0; u < m; ++u) {
+      const double dv = at(u) - mu;
+      q = fma(dv, dv, q);
+    }
+    sg = sqrt(q / m);
+  };
+  if (tiled) {
+    const double *xl = xs + threadIdx.x;
+    body([&](int u) { return xl[u]; });
+  } else {
+    body([&](int u) { return (double)x[u]; });
   }
-  const double mu = s / m;
-  double q = 0.0;
-  for (int u = 0; u < m; ++u) {
-    const double dv = (tiled ? xl[u] : (double)x[u]) - mu;
-    q = fma(dv, dv, q);
-  }
-  const double sg = sqrt(q / m);
   b.mu[wi] = ok ? mu : 0.0;
-  b.isig[wi] = (ok && lo != hi && sg > 0.0) ? 1.0 / sg : 0.0;
+  b.isig[wi] = (ok && !same && sg > 0.0) ? 1.0 / sg : 0.0;
   b.wpos[wi] = S.t_off + (wi - S.w_off);
   b.count[wi] = 0ull;
   b.fill[wi] = 0ull;
@@ -123,10 +141,11 @@ __global__ void __launch_bounds__(256) k_bwd_coef(Plan plan, BwdWork b, const Ti
   // subgradient 0): no contraction of the products into the subtraction.
 #pragma clang fp contract(off)
   __shared__ double xs[kTileW + kTileM];
-  const bool tiled = stage_tile(plan, Tb, total_l, xs);
+  int s0;
+  const bool tiled = stage_tile(plan, Tb, total_l, xs, s0);
   const int64_t wi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (wi >= total_l) return;
-  const int si = find_series_by_w(plan, wi);
+  const int si = tiled ? s0 : find_series_by_w(plan, wi);
   const SeriesDesc S = plan.series(si);
   const SeriesDesc Q = plan.series(S.partner);  // the series I indexes into
   const int64_t i = wi - S.w_off;
@@ -142,11 +161,21 @@ __global__ void __launch_bounds__(256) k_bwd_coef(Plan plan, BwdWork b, const Ti
       const Tin *xj = series_samples(plan, Tb, Q) + j;
       const double mi = b.mu[wi], mj = b.mu[jw];
       double d2 = 0.0, dot = 0.0;
-      const double *xl = xs + threadIdx.x;
-      for (int u = 0; u < S.m; ++u) {
-        const double zi = ((tiled ? xl[u] : (double)xi[u]) - mi) * isi, zj = ((double)xj[u] - mj) * isj;
-        d2 = fma(zi - zj, zi - zj, d2);
-        dot = fma(zi, zj, dot);
+      const int m = S.m;
+      // terms summed in sample order; the neighbour's window is read in
+      // 16-byte chunks (for_each_sample)
+      auto row = [&](auto xi_at) {
+        for_each_sample(xj, m, [&](int u, double vj) {
+          const double zi = (xi_at(u) - mi) * isi, zj = (vj - mj) * isj;
+          d2 = fma(zi - zj, zi - zj, d2);
+          dot = fma(zi, zj, dot);
+        });
+      };
+      if (tiled) {
+        const double *xl = xs + threadIdx.x;
+        row([&](int u) { return xl[u]; });
+      } else {
+        row([&](int u) { return (double)xi[u]; });
       }
       const double d = sqrt(d2);
       if (d > 0.0) {

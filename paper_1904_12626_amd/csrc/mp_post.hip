@@ -141,14 +141,36 @@ __device__ __forceinline__ void store_out(const Outputs &o, const SeriesDesc &S,
 //  * so is a window whose key is below `kappa` (FP32 sweep): there the
 //    FP32 keys cannot order the candidates (near-exact repeats), and the
 //    exact FP64 scan picks the neighbour.
+// The FP64 distance of the chosen pair reads the row's own window from a
+// workgroup tile of the series (staged once when the workgroup's 256
+// windows lie in one series and m <= kFinTileM) and the partner's window in
+// 16-byte chunks; the terms are summed in sample order either way.
+constexpr int kFinTile = 256;
+constexpr int kFinTileM = 2048;
+
 template <typename Tin, typename Tout>
 __global__ void __launch_bounds__(256) k_finalize(Plan plan, Work wk, const Tin *__restrict__ Tb,
                                                   Outputs o, int fp64_finalize, double kappa,
                                                   int64_t total_l) {
-  const int64_t wi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // z_a - z_b must be exactly 0 for windows that are offset copies (as in
+  // pair_dist64): no contraction into a fused multiply-add
+#pragma clang fp contract(off)
+  __shared__ Tin xs[kFinTile + kFinTileM];
+  const int64_t w0 = (int64_t)blockIdx.x * kFinTile;
+  const int s0 = find_series_w(plan, w0);
+  const SeriesDesc S0 = plan.series(s0);
+  const bool tiled = fp64_finalize && S0.m <= kFinTileM &&
+                     s0 == find_series_w(plan, min(w0 + kFinTile, total_l) - 1);
+  if (tiled) {
+    const Tin *base = series_samples(plan, Tb, S0) + (w0 - S0.w_off);
+    const int cnt = (int)(min(w0 + kFinTile, total_l) - w0) + S0.m - 1;
+    for (int t = threadIdx.x; t < cnt; t += blockDim.x) xs[t] = base[t];
+  }
+  __syncthreads();
+  const int64_t wi = w0 + threadIdx.x;
   if (wi >= total_l) return;
-  const int si = find_series_w(plan, wi);
-  const SeriesDesc S = plan.series(si);
+  const int si = tiled ? s0 : find_series_w(plan, wi);
+  const SeriesDesc S = tiled ? S0 : plan.series(si);
   const SeriesDesc Q = plan.series(S.partner);
   const int64_t w = wi - S.w_off;
   const uint8_t fw = wk.flags[wi];
@@ -199,8 +221,26 @@ __global__ void __launch_bounds__(256) k_finalize(Plan plan, Work wk, const Tin 
   if (idx >= 0) {
     P = sqrt(2.0 * S.m * fmax(val, 0.0));
     if (fp64_finalize && !(wk.flags[Q.w_off + idx] & 2)) {
-      P = pair_dist64(series_samples(plan, Tb, S) + w, wk.mu[wi], wk.sig[wi], false, series_samples(plan, Tb, Q) + idx,
-                      wk.mu[Q.w_off + idx], wk.sig[Q.w_off + idx], false, S.m);
+      // both windows are valid (all samples finite) and not constant: the
+      // pair_dist64 form without its non-finite guards
+      const double muA = wk.mu[wi], ia = 1.0 / wk.sig[wi];
+      const double muB = wk.mu[Q.w_off + idx], ib = 1.0 / wk.sig[Q.w_off + idx];
+      const Tin *xa = series_samples(plan, Tb, S) + w;
+      const Tin *xl = xs + threadIdx.x;
+      double s2 = 0.0;
+      auto pass = [&](auto a_at) {
+        for_each_sample(series_samples(plan, Tb, Q) + idx, S.m, [&](int u, double vb) {
+          const double za = (a_at(u) - muA) * ia;
+          const double zb = (vb - muB) * ib;
+          const double d = za - zb;
+          s2 = fma(d, d, s2);
+        });
+      };
+      if (tiled)
+        pass([&](int u) { return (double)xl[u]; });
+      else
+        pass([&](int u) { return (double)xa[u]; });
+      P = sqrt(s2);
     }
   }
   store_out<Tout>(o, S, w, P, idx);

@@ -25,7 +25,17 @@ __global__ void __launch_bounds__(1024) k_plan(Plan plan, Work w, int W, int R, 
 
   const int64_t per = (nseg + blockDim.x - 1) / blockDim.x;
   const int64_t a = min(nseg, (int64_t)tid * per), b = min(nseg, a + per);
-  int sw = 0;
+  // sweep holding strip a: the last one whose first strip is <= a
+  int sw0 = 0;
+  {
+    int lo = 0, hi = plan.nsweeps - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (plan.sweep(mid).seg_base <= a) lo = mid; else hi = mid - 1;
+    }
+    sw0 = lo;
+  }
+  int sw = sw0;
   // (full-height tiles, shorter last tile) of strip g, or (all tiles, 0)
   auto tiles_of = [&](int64_t g, int &swi, int64_t &t2) -> int64_t {
     while (swi + 1 < plan.nsweeps && plan.sweep(swi + 1).seg_base <= g) ++swi;
@@ -46,24 +56,23 @@ __global__ void __launch_bounds__(1024) k_plan(Plan plan, Work w, int W, int R, 
     sum += tiles_of(g, sw, t2);
     sum2 += t2;
   }
+  // inclusive scan over the threads (log-step, in LDS), then exclusive
   part[tid] = sum;
   part2[tid] = sum2;
   __syncthreads();
-  if (tid == 0) {
-    int64_t run = 0, run2 = 0;
-    for (int q = 0; q < (int)blockDim.x; ++q) {
-      const int64_t v = part[q], v2 = part2[q];
-      part[q] = run;
-      part2[q] = run2;
-      run += v;
-      run2 += v2;
-    }
-    w.seg_prefix[nseg] = run;
-    if (lpt) w.seg_part[nseg] = run2;
+  for (int d = 1; d < (int)blockDim.x; d <<= 1) {
+    const int64_t a1 = tid >= d ? part[tid - d] : 0, a2 = tid >= d ? part2[tid - d] : 0;
+    __syncthreads();
+    part[tid] += a1;
+    part2[tid] += a2;
+    __syncthreads();
   }
-  __syncthreads();
-  int64_t run = part[tid], run2 = part2[tid];
-  sw = 0;
+  if (tid == (int)blockDim.x - 1) {
+    w.seg_prefix[nseg] = part[tid];
+    if (lpt) w.seg_part[nseg] = part2[tid];
+  }
+  int64_t run = part[tid] - sum, run2 = part2[tid] - sum2;
+  sw = sw0;
   for (int64_t g = a; g < b; ++g) {
     int64_t t2;
     const int64_t t = tiles_of(g, sw, t2);
@@ -91,24 +100,43 @@ hipError_t launch_plan(const Plan &plan, const Work &w, int W, int R, int64_t ns
 // obeys C(i+1,j+1) = C(i,j) + a_j g_i + a_i g_j exactly (expand
 // x[i+m] = x[i] + a_i and mu_{i+1} = mu_i + a_i/m), and the sweep's key
 // u_i - C s_i s_j equals 1 - rho(i,j) for valid windows.
-template <typename F, typename Tin>
-__global__ void __launch_bounds__(256) k_stats(Plan plan, Work w, const Tin *__restrict__ Tb,
-                                               int64_t total_rc) {
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= total_rc) return;
-  // series owning rc entry r
-  int si = 0;
+// Series owning padded row/column entry r.
+__device__ __forceinline__ int series_of_rc(const Plan &plan, int64_t r) {
   if (plan.s_ext) {
     int lo = 0, hi = plan.nseries - 1;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
       if (plan.s_ext[mid].rc_off <= r) lo = mid; else hi = mid - 1;
     }
-    si = lo;
-  } else if (plan.nseries > 1 && r >= plan.s_inl[1].rc_off) {
-    si = 1;
+    return lo;
   }
-  const SeriesDesc S = plan.series(si);
+  return (plan.nseries > 1 && r >= plan.s_inl[1].rc_off) ? 1 : 0;
+}
+
+// A workgroup's 256 entries usually lie in one series: their samples (and
+// the one after each window, for a_i) are then staged once in LDS.
+constexpr int kStatsTile = 256;
+constexpr int kStatsTileM = 2048;
+
+template <typename F, typename Tin>
+__global__ void __launch_bounds__(256) k_stats(Plan plan, Work w, const Tin *__restrict__ Tb,
+                                               int64_t total_rc) {
+  __shared__ Tin xs[kStatsTile + kStatsTileM + 1];
+  const int64_t r0 = (int64_t)blockIdx.x * kStatsTile;
+  const int64_t r = r0 + threadIdx.x;
+  const int s0 = series_of_rc(plan, r0);
+  const SeriesDesc S0 = plan.series(s0);
+  const int64_t i0 = r0 - S0.rc_off;
+  const bool tiled = S0.m <= kStatsTileM && s0 == series_of_rc(plan, min(r0 + kStatsTile, total_rc) - 1);
+  if (tiled && i0 < S0.l) {
+    const Tin *base = series_samples(plan, Tb, S0) + i0;
+    const int cnt = (int)min((int64_t)(kStatsTile + S0.m), S0.n - i0);
+    for (int t = threadIdx.x; t < cnt; t += blockDim.x) xs[t] = base[t];
+  }
+  __syncthreads();
+  if (r >= total_rc) return;
+  const int si = tiled ? s0 : series_of_rc(plan, r);
+  const SeriesDesc S = tiled ? S0 : plan.series(si);
   const int64_t i = r - S.rc_off;
   using V4 = typename FTraits<F>::V4;
   V4 *rc = reinterpret_cast<V4 *>(w.rc);
@@ -121,31 +149,63 @@ __global__ void __launch_bounds__(256) k_stats(Plan plan, Work w, const Tin *__r
   }
   const Tin *x = series_samples(plan, Tb, S) + i;
   const int m = S.m;
-  bool fin = true;
-  double s = 0.0, lo = 0.0, hi = 0.0;
-  for (int u = 0; u < m; ++u) {
-    double v = (double)x[u];
-    if (!isfinite(v)) { fin = false; v = 0.0; }
-    if (u == 0) { lo = v; hi = v; }
-    lo = fmin(lo, v);
-    hi = fmax(hi, v);
-    s += v;
-  }
-  const double mu = s / m;
-  double q = 0.0;
-  for (int u = 0; u < m; ++u) {
-    double v = (double)x[u];
-    if (!isfinite(v)) v = 0.0;
-    const double dv = v - mu;
-    q = fma(dv, dv, q);
+  // Common case: every sample finite (then the sum is finite unless finite
+  // samples overflow).  Otherwise the careful pass below zeroes non-finite
+  // samples; both give the same mean and spread for finite windows.  The
+  // body is instantiated once for the LDS tile and once for global memory.
+  bool fin = true, cst;
+  double mu, q = 0.0, x0, xm = 0.0;
+  auto body = [&](auto at) {
+    const Tin v0 = at(0);
+    double s = 0.0;
+    bool same = true;
+#pragma unroll 4
+    for (int u = 0; u < m; ++u) {
+      const Tin v = at(u);
+      same &= (v == v0);
+      s += (double)v;
+    }
+    cst = same;
+    if (isfinite(s)) {
+      mu = s / m;
+#pragma unroll 4
+      for (int u = 0; u < m; ++u) {
+        const double dv = (double)at(u) - mu;
+        q = fma(dv, dv, q);
+      }
+    } else {
+      double lo = 0.0, hi = 0.0;
+      s = 0.0;
+      for (int u = 0; u < m; ++u) {
+        double v = (double)at(u);
+        if (!isfinite(v)) { fin = false; v = 0.0; }
+        if (u == 0) { lo = v; hi = v; }
+        lo = fmin(lo, v);
+        hi = fmax(hi, v);
+        s += v;
+      }
+      mu = s / m;
+      for (int u = 0; u < m; ++u) {
+        double v = (double)at(u);
+        if (!isfinite(v)) v = 0.0;
+        const double dv = v - mu;
+        q = fma(dv, dv, q);
+      }
+      cst = fin && (lo == hi);
+    }
+    x0 = (double)v0;
+    if (i + m < S.n) xm = (double)at(m);
+  };
+  if (tiled) {
+    const Tin *xl = xs + (i - i0);
+    body([&](int u) { return xl[u]; });
+  } else {
+    body([&](int u) { return x[u]; });
   }
   const double sig = sqrt(q / m);
-  const bool cst = fin && (lo == hi);
-  double x0 = (double)x[0];
   if (!isfinite(x0)) x0 = 0.0;
   double a = 0.0;
   if (i + m < S.n) {
-    double xm = (double)x[m];
     if (!isfinite(xm)) xm = 0.0;
     a = xm - x0;
   }
@@ -164,7 +224,7 @@ __global__ void __launch_bounds__(256) k_stats(Plan plan, Work w, const Tin *__r
 
 hipError_t launch_stats(const Plan &plan, const Work &w, const void *T, bool t_f64, bool f64_sweep,
                         int64_t total_rc, hipStream_t st) {
-  const dim3 blk(256), grd((unsigned)((total_rc + 255) / 256));
+  const dim3 blk(kStatsTile), grd((unsigned)((total_rc + kStatsTile - 1) / kStatsTile));
   if (t_f64) {
     if (f64_sweep)
       hipLaunchKernelGGL((k_stats<double, double>), grd, blk, 0, st, plan, w, (const double *)T, total_rc);

@@ -54,4 +54,45 @@ __device__ __forceinline__ int64_t unpack_idx(uint64_t k, int bits) {
   return (int64_t)(k & ((1ull << bits) - 1ull));
 }
 
+// Sixteen bytes of consecutive samples, aligned only to the element size.
+template <typename T>
+struct __attribute__((aligned(sizeof(T)))) Chunk16 {
+  T v[16 / sizeof(T)];
+};
+
+// f(u, (double)x[u]) for u = 0 .. m-1, in that order.  Meant for a window at
+// an arbitrary offset per lane (a neighbour picked by the profile index):
+// it is read as 16-byte chunks, four in flight, so a wave touches a quarter
+// of the cache lines per load instruction and never waits on the load it is
+// about to use.  Reads stay inside x[0 .. m-1].
+template <typename Tin, typename Fn>
+__device__ __forceinline__ void for_each_sample(const Tin *__restrict__ x, int m, Fn &&f) {
+  constexpr int E = 16 / sizeof(Tin), D = 4;
+  using C = Chunk16<Tin>;
+  const int nch = m / E;
+  auto chunk = [&](int q) { return *reinterpret_cast<const C *>(x + (int64_t)min(q, nch - 1) * E); };
+  int q = 0;
+  if (nch > 0) {
+    C ring[D];
+#pragma unroll
+    for (int r = 0; r < D; ++r) ring[r] = chunk(r);
+    for (; q + D <= nch; q += D) {
+#pragma unroll
+      for (int r = 0; r < D; ++r) {
+        const C c = ring[r];
+        ring[r] = chunk(q + r + D);  // clamped to the last chunk
+#pragma unroll
+        for (int e = 0; e < E; ++e) f((q + r) * E + e, (double)c.v[e]);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < D; ++r)
+      if (q + r < nch) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) f((q + r) * E + e, (double)ring[r].v[e]);
+      }
+  }
+  for (int u = nch * E; u < m; ++u) f(u, (double)x[u]);
+}
+
 }  // namespace mpx
