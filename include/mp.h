@@ -87,6 +87,9 @@ typedef enum {
 
 /* flags */
 #define MP_FLAG_FP64_FINALIZE 1u  /* recompute P[i] = dist(i, I[i]) in FP64 */
+#define MP_FLAG_FLAT_LOADS 2u     /* mp_backward: read samples with flat loads, as it
+                                     does anyway for sample arrays of 2 GiB or more
+                                     (same results; for comparisons)            */
 
 typedef struct {
   int32_t precision;     /* MP_PREC_F64 or MP_PREC_F32                        */
@@ -234,8 +237,8 @@ mp_status mp_anytime_order(int64_t count, uint64_t seed, int64_t *order_host);
  * or a constant or non-finite window on either side contribute nothing.
  * Accumulation is in FP64 without atomics on values: the same inputs give
  * bitwise the same gT.  Any I is accepted (hub neighbours included); the
- * cost is O(total_l * m) plus, per neighbour window, the square of its
- * number of referring rows.
+ * cost is O(total_l * m) plus O(h log^2 h) for a neighbour window named by
+ * h > 64 rows (their order is settled by a sort).
  * Uses the batch plan's layout: T_cat / I_cat / gP_cat as for mp_batch,
  * gT_cat (n values per series, `dtype`) is overwritten.  The workspace is
  * the plan's workspace (its forward contents are overwritten).

@@ -23,6 +23,7 @@ MP_NOALLOC_SCRATCH_BYTES = 64 << 20
 MP_F64, MP_F32 = 0, 1
 MP_PREC_F64, MP_PREC_F32 = 0, 1
 MP_FLAG_FP64_FINALIZE = 1
+MP_FLAG_FLAT_LOADS = 2
 
 # every symbol include/mp.h declares
 EXPORTS = (
@@ -124,11 +125,12 @@ def exclusion_zone(m: int, frac=Fraction(1, 2)) -> int:
 
 
 def make_options(precision: str = "f32", reseed_rows: int = 0, tile_slots: int = 0,
-                 fp64_finalize: bool = True) -> mp_options:
+                 fp64_finalize: bool = True, flat_loads: bool = False) -> mp_options:
     if precision not in ("f32", "f64"):
         raise ValueError("precision must be 'f32' or 'f64'")
+    flags = (MP_FLAG_FP64_FINALIZE if fp64_finalize else 0) | (MP_FLAG_FLAT_LOADS if flat_loads else 0)
     return mp_options(MP_PREC_F32 if precision == "f32" else MP_PREC_F64, int(reseed_rows),
-                      int(tile_slots), MP_FLAG_FP64_FINALIZE if fp64_finalize else 0)
+                      int(tile_slots), flags)
 
 
 def _dtype_code(t: torch.Tensor) -> int:
@@ -238,7 +240,7 @@ class BatchPlan:
 
     def __init__(self, lengths, windows, zones, dtype=torch.float32, device="cuda", *,
                  precision: str = "f32", reseed_rows: int = 0, tile_slots: int = 0,
-                 fp64_finalize: bool = True):
+                 fp64_finalize: bool = True, flat_loads: bool = False):
         L = lib()
         self.lengths = [int(x) for x in lengths]
         self.windows = [int(x) for x in windows]
@@ -259,7 +261,7 @@ class BatchPlan:
         self.t_off = [off[i] for i in range(ns + 1)]
         mm = (ctypes.c_int32 * ns)(*self.windows)
         ee = (ctypes.c_int32 * ns)(*self.zones)
-        self._opt = make_options(precision, reseed_rows, tile_slots, fp64_finalize)
+        self._opt = make_options(precision, reseed_rows, tile_slots, fp64_finalize, flat_loads)
         h = ctypes.c_void_p()
         _check("mp_batch_plan_create", L.mp_batch_plan_create(ns, off, mm, ee, dt, ctypes.byref(self._opt),
                                                               ctypes.byref(h)))

@@ -30,6 +30,7 @@ struct Options {
   int slots = 12;        // diagonals per lane (FP32 default 12, FP64 8)
   int reseed = 0;        // 0 = automatic
   bool fp64_finalize = true;
+  bool flat_loads = false;  // backward gather: flat loads at any size
 };
 
 mp_status parse_options(const mp_options *opt, Options &o) {
@@ -46,8 +47,9 @@ mp_status parse_options(const mp_options *opt, Options &o) {
   if (opt->reseed_rows != 0 && (opt->reseed_rows % 64 != 0 || opt->reseed_rows > (1 << 20)))
     return MP_EINVAL;
   o.reseed = opt->reseed_rows;
-  if (opt->flags & ~MP_FLAG_FP64_FINALIZE) return MP_EINVAL;
+  if (opt->flags & ~(MP_FLAG_FP64_FINALIZE | MP_FLAG_FLAT_LOADS)) return MP_EINVAL;
   o.fp64_finalize = (opt->flags & MP_FLAG_FP64_FINALIZE) != 0;
+  o.flat_loads = (opt->flags & MP_FLAG_FLAT_LOADS) != 0;
   return MP_OK;
 }
 
@@ -810,7 +812,7 @@ mp_status mp_backward(const mp_batch_plan *pl, const void *T_cat, const int64_t 
   const mpx::BwdWork w = bwd_work_of(pl->lay, ws);
   const mpx::Plan p = plan_of(pl->job, pl->lay, ws, true);
   if (mpx::launch_backward(p, w, T_cat, pl->job.t_f64, I_cat, gP_cat, gT_cat, pl->job.total_l,
-                           pl->job.total_n, (hipStream_t)stream) != hipSuccess)
+                           pl->job.total_n, pl->job.opt.flat_loads, (hipStream_t)stream) != hipSuccess)
     return MP_ELAUNCH;
   return MP_OK;
 }

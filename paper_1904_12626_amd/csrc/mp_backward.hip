@@ -320,69 +320,115 @@ __device__ __forceinline__ void covering(const Plan &plan, int64_t x, int64_t &l
   hi = S.w_off + min(t, S.l - 1);
 }
 
+// Source-sample loads of the gather.  kBuf: buffer loads against the whole
+// sample array with 32-bit byte offsets (arrays under 2 GiB).  An offset
+// outside the array reads 0 and does not fault, so a lane outside an edge's
+// window may load at any offset; its term is discarded.  Otherwise flat loads
+// with the offset replaced by 0 (the lane's own sample) outside the window.
+template <typename Tin, bool kBuf>
+struct GatherSrc;
+template <typename Tin>
+struct GatherSrc<Tin, true> {
+  __amdgpu_buffer_rsrc_t r;
+  uint32_t own;  // the lane's sample, in bytes
+  __device__ GatherSrc(const Tin *Tb, int64_t total_n, int64_t x)
+      : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<Tin *>(Tb), (short)0, (int)(total_n * (int64_t)sizeof(Tin)),
+                                            0x00020000)),
+        own((uint32_t)(x * (int64_t)sizeof(Tin))) {}
+  __device__ __forceinline__ double load(int32_t dbytes, int64_t, bool) const {
+    const uint32_t o = own + (uint32_t)dbytes;
+    if constexpr (sizeof(Tin) == 4)
+      return (double)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, o, 0, 0));
+    else
+      return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, o, 0, 0));
+  }
+};
+template <typename Tin>
+struct GatherSrc<Tin, false> {
+  const Tin *xp;
+  __device__ GatherSrc(const Tin *Tb, int64_t, int64_t x) : xp(Tb + x) {}
+  __device__ __forceinline__ double load(int32_t, int64_t delta, bool in) const {
+    return (double)xp[in ? delta : 0];
+  }
+};
+
+// Staged edge: c and mu (one 16-byte read), then the destination window
+// relative to the wave's first covering window, the source offset in bytes
+// (buffer loads) and in samples (flat loads).
+struct GatherEdge {
+  double c, mu;
+  int32_t rel, dbytes;
+  int64_t delta;
+};
+
 // One wave = 64 consecutive samples.  Every sample of a series is covered by
 // at least one window and the covering ranges are non-decreasing in the
 // sample index, so the wave walks [lo(first sample), hi(last sample)].
 // Records are fetched 64 at a time, one per lane (coalesced, all in flight
 // together), staged in the wave's own LDS slots and read back by the whole
-// wave as broadcasts (one 16-byte read for a window's, two for an edge's,
-// instead of two lane reads per 8-byte field).
-template <typename Tin, typename Tg>
+// wave as broadcasts.  Window ranges are tested in 32 bits relative to the
+// wave's first covering window: lane-local (rel - lt) <= span, unsigned.
+template <typename Tin, typename Tg, bool kBuf>
 __global__ void __launch_bounds__(256) k_bwd_gather(Plan plan, BwdWork b, const Tin *__restrict__ Tb,
                                                     Tg *gT, int64_t total_n) {
-  __shared__ double4 stage[4][64];  // per wave: 64 window or edge records
+  __shared__ GatherEdge stage[4][64];  // per wave: 64 window or edge records
   const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t x0 = uni64(x - (int64_t)(threadIdx.x & 63));
   if (x0 >= total_n) return;
   const int64_t xl = min(x0 + 63, total_n - 1);
   const bool act = x < total_n;
+  const int64_t xs = act ? x : xl;
   int64_t lo_t, hi_t, lo_w, hi_w, dummy;
-  covering(plan, act ? x : xl, lo_t, hi_t);
-  if (!act) { lo_t = 1; hi_t = 0; }
+  covering(plan, xs, lo_t, hi_t);
   covering(plan, x0, lo_w, dummy);
   covering(plan, xl, dummy, hi_w);
   lo_w = uni64(lo_w);
   hi_w = uni64(hi_w);
-  const Tin *xp = Tb + (act ? x : xl);
-  const double xt = (double)*xp;
+  const uint32_t lt = (uint32_t)(lo_t - lo_w), span = (uint32_t)(hi_t - lo_t);
+  const GatherSrc<Tin, kBuf> src(Tb, total_n, xs);
+  // a non-finite sample lies only in windows with sc = 0 and mu = 0: read
+  // as 0 it adds exact zeros there
+  double xt = (double)Tb[xs];
+  xt = isfinite(xt) ? xt : 0.0;
   const BwdWin *__restrict__ wrec = b.wrec;
   const BwdEdge *__restrict__ erec = b.erec;
   const int64_t *__restrict__ off = b.off;
   const int lane = threadIdx.x & 63;
-  double4 *const st = stage[threadIdx.x >> 6];
-  double2 *const st2 = reinterpret_cast<double2 *>(st);  // st2[2k]: c, mu; st2[2k+1]: delta, window
+  GatherEdge *const st = stage[threadIdx.x >> 6];
   double acc = 0.0;
   // First the multiples of each covering window's own z ...
   for (int64_t c = lo_w; c <= hi_w; c += 64) {
-    double2 wr = make_double2(0.0, 0.0);
+    GatherEdge q{0.0, 0.0, 0, 0, 0};
     if (c + lane <= hi_w) {
       const BwdWin w = wrec[c + lane];
-      wr = make_double2(w.sc, w.mu);
+      q.c = w.sc;
+      q.mu = w.mu;
     }
-    st2[2 * lane] = wr;
+    st[lane] = q;
     __builtin_amdgcn_wave_barrier();
     const int cnt = (int)min((int64_t)64, hi_w - c + 1);
+    const uint32_t base = (uint32_t)(c - lo_w) - lt;
     for (int k = 0; k < cnt; ++k) {
-      const double2 r = st2[2 * k];
-      const int64_t d = c + k;
-      // sc is 0 for windows without gradient, including non-finite ones
-      // whose samples must not reach the sum
-      if (d >= lo_t && d <= hi_t && r.x != 0.0) acc = fma(r.x, xt - r.y, acc);
+      const double2 r = *reinterpret_cast<const double2 *>(&st[k]);
+      const double dv = xt - r.y;
+      acc = fma(r.x, base + (uint32_t)k <= span ? dv : 0.0, acc);
     }
     __builtin_amdgcn_wave_barrier();
   }
   // ... then the edges of the covering windows, one flat run of the edge
   // array (each edge carries its destination window).  Eight edges per
-  // step: their sample loads are issued together (a lane outside an edge's
-  // window loads its own sample instead, so every load stays in bounds) and
-  // summed afterwards in edge order.  Fetch slots past the run read as
-  // window -1, which no lane covers.
+  // step: their sample loads are issued together and summed afterwards in
+  // edge order.  Fetch slots past the run get a destination no lane covers.
   const int64_t eb = uni64(off[lo_w]), ee = uni64(off[hi_w + 1]);
   for (int64_t c = eb; c < ee; c += 64) {
-    double4 q = make_double4(0.0, 0.0, 0.0, __longlong_as_double(-1ll));
+    GatherEdge q{0.0, 0.0, INT32_MIN, 0, 0};
     if (c + lane < ee) {
       const BwdEdge e = erec[c + lane];
-      q = make_double4(e.c, e.mu, __longlong_as_double(e.delta), e.gam);
+      q.c = e.c;
+      q.mu = e.mu;
+      q.rel = (int32_t)(__double_as_longlong(e.gam) - lo_w);
+      q.dbytes = (int32_t)(e.delta * (int64_t)sizeof(Tin));
+      q.delta = e.delta;
     }
     st[lane] = q;
     __builtin_amdgcn_wave_barrier();
@@ -392,16 +438,17 @@ __global__ void __launch_bounds__(256) k_bwd_gather(Plan plan, BwdWork b, const 
       bool in[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        const double2 dd = st2[2 * (k + u) + 1];
-        const int64_t d = __double_as_longlong(dd.y);
-        in[u] = d >= lo_t && d <= hi_t;
-        v[u] = (double)xp[in[u] ? __double_as_longlong(dd.x) : 0];
+        const GatherEdge &g = st[k + u];
+        in[u] = (uint32_t)g.rel - lt <= span;
+        v[u] = src.load(g.dbytes, g.delta, in[u]);
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        const double2 cm = st2[2 * (k + u)];
-        const double t = fma(cm.x, v[u] - cm.y, acc);
-        acc = in[u] ? t : acc;
+        // a lane outside the window adds c * 0 (its sample, which may be
+        // any value, is replaced before the product)
+        const double2 cm = *reinterpret_cast<const double2 *>(&st[k + u]);
+        const double dv = v[u] - cm.y;
+        acc = fma(cm.x, in[u] ? dv : 0.0, acc);
       }
     }
     __builtin_amdgcn_wave_barrier();
@@ -411,7 +458,7 @@ __global__ void __launch_bounds__(256) k_bwd_gather(Plan plan, BwdWork b, const 
 
 hipError_t launch_backward(const Plan &plan, const BwdWork &b, const void *T, bool t_f64,
                            const int64_t *I, const void *gP, void *gT, int64_t total_l,
-                           int64_t total_n, hipStream_t st) {
+                           int64_t total_n, bool flat_loads, hipStream_t st) {
   const dim3 blk(256);
   const dim3 gl((unsigned)((total_l + 255) / 256)), gn((unsigned)((total_n + 255) / 256));
   if (t_f64) {
@@ -430,12 +477,23 @@ hipError_t launch_backward(const Plan &plan, const BwdWork &b, const void *T, bo
   hipLaunchKernelGGL(k_bwd_rank, gl, blk, 0, st, b, total_l);
   hipLaunchKernelGGL(k_bwd_bigsort, dim3(256), blk, 0, st, b);
   hipLaunchKernelGGL(k_bwd_window, gl, blk, 0, st, b, total_l);
-  if (t_f64)
-    hipLaunchKernelGGL((k_bwd_gather<double, double>), gn, blk, 0, st, plan, b, (const double *)T,
-                       (double *)gT, total_n);
-  else
-    hipLaunchKernelGGL((k_bwd_gather<float, float>), gn, blk, 0, st, plan, b, (const float *)T, (float *)gT,
-                       total_n);
+  // buffer loads while the sample array's byte offsets fit in 31 bits
+  const bool buf = !flat_loads && total_n * (int64_t)(t_f64 ? sizeof(double) : sizeof(float)) < ((int64_t)1 << 31);
+  if (t_f64) {
+    if (buf)
+      hipLaunchKernelGGL((k_bwd_gather<double, double, true>), gn, blk, 0, st, plan, b, (const double *)T,
+                         (double *)gT, total_n);
+    else
+      hipLaunchKernelGGL((k_bwd_gather<double, double, false>), gn, blk, 0, st, plan, b, (const double *)T,
+                         (double *)gT, total_n);
+  } else {
+    if (buf)
+      hipLaunchKernelGGL((k_bwd_gather<float, float, true>), gn, blk, 0, st, plan, b, (const float *)T,
+                         (float *)gT, total_n);
+    else
+      hipLaunchKernelGGL((k_bwd_gather<float, float, false>), gn, blk, 0, st, plan, b, (const float *)T,
+                         (float *)gT, total_n);
+  }
   return hipGetLastError();
 }
 

@@ -160,9 +160,11 @@ hipError_t launch_recheck(const void *T, bool t_f64, int64_t n, int32_t m, const
                           bool p_f64, const int64_t *I, int32_t km, int32_t kd, int64_t *out_idx,
                           double *out_dist, uint8_t *ws, hipStream_t st);
 size_t recheck_state_bytes();
+// flat_loads: the gather reads samples with flat loads even where buffer
+// loads apply (sample arrays under 2 GiB)
 hipError_t launch_backward(const Plan &plan, const BwdWork &b, const void *T, bool t_f64,
                            const int64_t *I, const void *gP, void *gT, int64_t total_l,
-                           int64_t total_n, hipStream_t st);
+                           int64_t total_n, bool flat_loads, hipStream_t st);
 
 // Exclusive prefix sum: out[0..n] (out[n] = total) of in[0..n); `partial`
 // holds ceil(n / 1024) + 1 entries of scratch.

@@ -109,6 +109,46 @@ def test_backward_hub_constant_and_nan_windows():
     assert bad.size == 0, (bad[:70].tolist(), g[bad[:8]].tolist(), ref[bad[:8]].tolist())
 
 
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_gather_flat_and_buffer_loads_agree(dtype):
+    """The gather reads source samples with buffer loads (arrays under 2 GiB,
+    out-of-window lanes may read past either end of the array) or flat loads
+    (forced here; the path of larger arrays): bitwise the same gradient, on a
+    ragged batch whose first and last series put window edges at both ends
+    of the array, with a NaN sample, a constant stretch and a hub."""
+    import paper_1904_12626_amd as mpx
+    lengths, ms = [700, 90, 1300, 400], [24, 10, 40, 16]
+    zs = [m // 4 for m in ms]
+    series = _batch(lengths, ms, 31, dtype)
+    series[2][500:560] = 1.25
+    series[2][900] = np.nan
+    Tc = np.concatenate(series)
+    Tg = torch.from_numpy(Tc).to(DEV)
+    tdt = torch.float64 if dtype == np.float64 else torch.float32
+    prec = "f64" if dtype == np.float64 else "f32"
+    buf = mpx.BatchPlan(lengths, ms, zs, dtype=tdt, device=DEV, precision=prec)
+    flat = mpx.BatchPlan(lengths, ms, zs, dtype=tdt, device=DEV, precision=prec, flat_loads=True)
+    P, I = buf.run(Tg)
+    I = I.clone()
+    Ih = I.cpu().numpy()
+    off = 0
+    for n, m in zip(lengths, ms):   # a hub in every series: the first window
+        Ih[off:off + n - m + 1:3] = 0
+        off += n - m + 1
+    I = torch.from_numpy(Ih).to(DEV)
+    gP = torch.from_numpy(np.random.default_rng(32).uniform(0.5, 1.5, P.shape).astype(dtype)).to(DEV)
+    g_buf = buf.backward(Tg, I, gP).clone()
+    g_flat = flat.backward(Tg, I, gP)
+    torch.cuda.synchronize()
+    assert torch.equal(g_buf, g_flat)
+    if dtype == np.float64:
+        gs = np.split(g_buf.cpu().numpy(), np.cumsum(lengths)[:-1])
+        Is, gPs = buf.split(Ih), buf.split(gP.cpu().numpy())
+        for s in range(len(lengths)):
+            ref = O.reference_gradient(series[s], ms[s], Is[s], gPs[s])
+            np.testing.assert_allclose(gs[s], ref, rtol=1e-9, atol=1e-9 * max(1.0, np.abs(ref).max()))
+
+
 @pytest.mark.parametrize("precision,dtype", [("f64", np.float64), ("f32", np.float32)])
 def test_abjoin_plan_and_backward(precision, dtype):
     """AB-join as a plan: profiles equal mp_abjoin's; the backward gives
