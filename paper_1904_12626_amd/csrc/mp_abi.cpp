@@ -167,7 +167,7 @@ void finish_job(Job &j) {
 
 struct Layout {
   size_t mu, sig, keys, flags, nc, nv, rc, special, counters, segp, segs, segq, rescan, sdesc, wdesc, kmask;
-  size_t b_mu, b_isig, b_wpos, b_coef, b_nbr, b_count, b_fill, b_off, b_tmp, b_erec, b_wrec, b_chunk, b_big,
+  size_t b_mu, b_isig, b_wpos, b_coef, b_nbr, b_count, b_fill, b_off, b_tmp, b_erec, b_egam, b_wrec, b_chunk, b_big,
       b_nbig;
   size_t total;
 };
@@ -205,6 +205,7 @@ Layout layout_of(const Job &j, bool with_batch_tables) {
     L.b_off = take(8 * (tl + 1));
     L.b_tmp = take(8 * 2 * tl);  // indexed like erec
     L.b_erec = take(sizeof(mpx::BwdEdge) * 2 * tl);
+    L.b_egam = take(8 * 2 * tl);
     L.b_wrec = take(sizeof(mpx::BwdWin) * tl);
     L.b_chunk = take(8 * ((tl + 1023) / 1024 + 1));
     L.b_big = take(8 * (tl / (size_t)mpx::kBwdSmallBucket + 1));
@@ -249,6 +250,7 @@ mpx::BwdWork bwd_work_of(const Layout &L, void *ws) {
   w.off = (int64_t *)(b + L.b_off);
   w.tmp = (int64_t *)(b + L.b_tmp);
   w.erec = (mpx::BwdEdge *)(b + L.b_erec);
+  w.egam = (double *)(b + L.b_egam);
   w.wrec = (mpx::BwdWin *)(b + L.b_wrec);
   w.chunk = (int64_t *)(b + L.b_chunk);
   w.big = (int64_t *)(b + L.b_big);

@@ -201,7 +201,7 @@ __global__ void __launch_bounds__(256) k_bwd_place(BwdWork b, int64_t total_l) {
   const int64_t jw = b.nbr[wi];
   if (jw < 0) return;
   const Double4 c = reinterpret_cast<const Double4 *>(b.coef)[wi];
-  b.erec[b.off[wi]] = BwdEdge{c.y * b.isig[jw], b.mu[jw], b.wpos[jw] - b.wpos[wi], 0.0};
+  b.erec[b.off[wi]] = BwdEdge{c.y * b.isig[jw], b.mu[jw], b.wpos[jw] - b.wpos[wi], wi};
   const int64_t base = b.off[jw] + (b.nbr[jw] >= 0 ? 1 : 0);
   const unsigned long long pos = atomicAdd(&b.fill[jw], 1ull);
   b.tmp[base + (int64_t)pos] = wi;
@@ -209,11 +209,12 @@ __global__ void __launch_bounds__(256) k_bwd_place(BwdWork b, int64_t total_l) {
   if (pos == 0 && b.off[jw + 1] - base > kBwdSmallBucket) b.big[atomicAdd(b.nbig, 1ull)] = jw;
 }
 
-// Edge record of bucket row wi (neighbour window jw): the row's multiple of
-// its own window's z, applied on window jw.
-__device__ __forceinline__ BwdEdge bucket_edge(const BwdWork &b, int64_t wi, int64_t jw) {
+// Edge slot p of bucket row wi (neighbour window jw): the row's multiple of
+// its own window's z, applied on window jw, and its multiple of jw's z.
+__device__ __forceinline__ void put_bucket_edge(const BwdWork &b, int64_t p, int64_t wi, int64_t jw) {
   const Double4 c = reinterpret_cast<const Double4 *>(b.coef)[wi];
-  return BwdEdge{c.w * b.isig[wi], b.mu[wi], b.wpos[wi] - b.wpos[jw], c.z};
+  b.erec[p] = BwdEdge{c.w * b.isig[wi], b.mu[wi], b.wpos[wi] - b.wpos[jw], jw};
+  b.egam[p] = c.z;
 }
 
 // Bucket edges in increasing row order.  In a bucket of at most
@@ -228,7 +229,7 @@ __global__ void __launch_bounds__(256) k_bwd_rank(BwdWork b, int64_t total_l) {
   if (e - a > kBwdSmallBucket) return;
   int64_t r = 0;
   for (int64_t p = a; p < e; ++p) r += b.tmp[p] < wi;
-  b.erec[a + r] = bucket_edge(b, wi, jw);
+  put_bucket_edge(b, a + r, wi, jw);
 }
 
 // Large buckets: one workgroup sorts a bucket's row indices (a bitonic
@@ -278,7 +279,7 @@ __global__ void __launch_bounds__(256) k_bwd_bigsort(BwdWork b) {
     } else {
       sort_rows(v, h);
     }
-    for (int64_t t = threadIdx.x; t < h; t += blockDim.x) b.erec[a + t] = bucket_edge(b, v[t], jw);
+    for (int64_t t = threadIdx.x; t < h; t += blockDim.x) put_bucket_edge(b, a + t, v[t], jw);
     __syncthreads();
   }
 }
@@ -290,10 +291,8 @@ __global__ void __launch_bounds__(256) k_bwd_window(BwdWork b, int64_t total_l) 
   const bool own = b.nbr[w] >= 0;
   double s = own ? b.coef[4 * w] : 0.0;
   const int64_t e = b.off[w + 1];
-  for (int64_t p = b.off[w] + (own ? 1 : 0); p < e; ++p) s += b.erec[p].gam;
+  for (int64_t p = b.off[w] + (own ? 1 : 0); p < e; ++p) s += b.egam[p];
   b.wrec[w] = BwdWin{s * b.isig[w], b.mu[w]};
-  // from here on each edge carries its destination window instead of gamma
-  for (int64_t p = b.off[w]; p < e; ++p) b.erec[p].gam = __longlong_as_double((long long)w);
 }
 
 // Lane k's value, wave-uniform (k is uniform).
@@ -426,7 +425,7 @@ __global__ void __launch_bounds__(256) k_bwd_gather(Plan plan, BwdWork b, const 
       const BwdEdge e = erec[c + lane];
       q.c = e.c;
       q.mu = e.mu;
-      q.rel = (int32_t)(__double_as_longlong(e.gam) - lo_w);
+      q.rel = (int32_t)(e.dest - lo_w);
       q.dbytes = (int32_t)(e.delta * (int64_t)sizeof(Tin));
       q.delta = e.delta;
     }

@@ -109,8 +109,7 @@ struct BwdEdge {
   double c;      // coefficient on (x[t + delta] - mu)
   double mu;     // mean of the source window
   int64_t delta; // source window start - destination window start (samples)
-  double gam;    // (bucket edges) the row's multiple of the destination z; after
-                 // the per-window sums, the destination window (int64 bits)
+  int64_t dest;  // destination window (global index)
 };
 struct BwdWin {
   double sc;     // summed multiple of this window's z, times 1/sigma
@@ -127,6 +126,7 @@ struct BwdWork {
   int64_t *off;        // [total_l + 1] edge offsets (exclusive prefix of count)
   int64_t *tmp;        // [2 total_l] bucket rows in placement order (edge slots)
   BwdEdge *erec;       // [2 total_l] edges
+  double *egam;        // [2 total_l] per bucket-edge slot: the row's multiple of the destination z
   BwdWin *wrec;        // [total_l] per-window self coefficient
   int64_t *chunk;      // [ceil(total_l / 1024) + 1] scan partials
   int64_t *big;        // [total_l / kBwdSmallBucket + 1] buckets with more than kBwdSmallBucket rows

@@ -34,19 +34,17 @@ __global__ void __launch_bounds__(1024) k_scan_totals(int64_t *chunk_tot, int64_
   const int64_t a = min(nchunks, (int64_t)tid * per), e = min(nchunks, a + per);
   int64_t s = 0;
   for (int64_t c = a; c < e; ++c) s += chunk_tot[c];
+  // inclusive log-step scan of the per-thread sums, then exclusive
   part[tid] = s;
   __syncthreads();
-  if (tid == 0) {
-    int64_t run = 0;
-    for (int q = 0; q < 1024; ++q) {
-      const int64_t v = part[q];
-      part[q] = run;
-      run += v;
-    }
-    out[n] = run;
+  for (int d = 1; d < 1024; d <<= 1) {
+    const int64_t add = tid >= d ? part[tid - d] : 0;
+    __syncthreads();
+    part[tid] += add;
+    __syncthreads();
   }
-  __syncthreads();
-  int64_t run = part[tid];
+  if (tid == 1023) out[n] = part[tid];
+  int64_t run = part[tid] - s;
   for (int64_t c = a; c < e; ++c) {
     const int64_t v = chunk_tot[c];
     chunk_tot[c] = run;
