@@ -167,7 +167,7 @@ void finish_job(Job &j) {
 
 struct Layout {
   size_t mu, sig, keys, flags, nc, nv, rc, special, counters, segp, segs, segq, rescan, sdesc, wdesc, kmask;
-  size_t b_mu, b_isig, b_wpos, b_coef, b_nbr, b_count, b_fill, b_off, b_tmp, b_erec, b_egam, b_wrec, b_chunk, b_big,
+  size_t b_mu, b_isig, b_nbr, b_wrec, b_bedge, b_bgam, b_count, b_fill, b_off, b_tmp, b_erec, b_egam, b_chunk, b_big,
       b_nbig;
   size_t total;
 };
@@ -197,16 +197,16 @@ Layout layout_of(const Job &j, bool with_batch_tables) {
   if (with_batch_tables) {
     L.b_mu = take(8 * tl);
     L.b_isig = take(8 * tl);
-    L.b_wpos = take(8 * tl);
-    L.b_coef = take(32 * tl);
     L.b_nbr = take(8 * tl);
+    L.b_wrec = take(sizeof(mpx::BwdWin) * tl);
+    L.b_bedge = take(sizeof(mpx::BwdEdge) * tl);
+    L.b_bgam = take(8 * tl);
     L.b_count = take(8 * tl);
     L.b_fill = take(8 * tl);
     L.b_off = take(8 * (tl + 1));
-    L.b_tmp = take(8 * 2 * tl);  // indexed like erec
-    L.b_erec = take(sizeof(mpx::BwdEdge) * 2 * tl);
-    L.b_egam = take(8 * 2 * tl);
-    L.b_wrec = take(sizeof(mpx::BwdWin) * tl);
+    L.b_tmp = take(8 * tl);  // indexed like erec
+    L.b_erec = take(sizeof(mpx::BwdEdge) * tl);
+    L.b_egam = take(8 * tl);
     L.b_chunk = take(8 * ((tl + 1023) / 1024 + 1));
     L.b_big = take(8 * (tl / (size_t)mpx::kBwdSmallBucket + 1));
     L.b_nbig = take(8);
@@ -242,16 +242,16 @@ mpx::BwdWork bwd_work_of(const Layout &L, void *ws) {
   mpx::BwdWork w{};
   w.mu = (double *)(b + L.b_mu);
   w.isig = (double *)(b + L.b_isig);
-  w.wpos = (int64_t *)(b + L.b_wpos);
-  w.coef = (double *)(b + L.b_coef);
   w.nbr = (int64_t *)(b + L.b_nbr);
+  w.wrec = (mpx::BwdWin *)(b + L.b_wrec);
+  w.bedge = (mpx::BwdEdge *)(b + L.b_bedge);
+  w.bgam = (double *)(b + L.b_bgam);
   w.count = (unsigned long long *)(b + L.b_count);
   w.fill = (unsigned long long *)(b + L.b_fill);
   w.off = (int64_t *)(b + L.b_off);
   w.tmp = (int64_t *)(b + L.b_tmp);
   w.erec = (mpx::BwdEdge *)(b + L.b_erec);
   w.egam = (double *)(b + L.b_egam);
-  w.wrec = (mpx::BwdWin *)(b + L.b_wrec);
   w.chunk = (int64_t *)(b + L.b_chunk);
   w.big = (int64_t *)(b + L.b_big);
   w.nbig = (unsigned long long *)(b + L.b_nbig);

@@ -12,13 +12,13 @@
 //   on window i:  alpha z_i + beta z_j,   alpha = g rho/(sigma_i d), beta = -g/(sigma_i d)
 //   on window j:  gamma z_j + delta z_i,  gamma = g rho/(sigma_j d), delta = -g/(sigma_j d)
 // Per destination window w, the multiples of z_w (its own alpha and the
-// gammas of the rows whose neighbour is w) are summed in a fixed order; the
-// multiples of other windows' z are edges grouped by w (the row's own beta
-// edge, then the rows naming w as neighbour, in increasing row order).  A
-// wave then produces 64 consecutive gradient samples by walking the windows
-// that cover them in order, with the window and edge records uniform across
-// the wave and the source samples loaded contiguously.  No floating-point
-// atomics: reruns are bitwise identical.
+// gammas of the rows whose neighbour is w) are summed in a fixed order; its
+// row's beta term is the window's own edge, and the delta terms of the rows
+// naming w are its bucket edges, in increasing row order.  A wave then
+// produces 64 consecutive gradient samples by walking the windows that cover
+// them in order, with the window and edge records uniform across the wave
+// and the source samples loaded contiguously.  No floating-point atomics:
+// reruns are bitwise identical.
 #include <cmath>
 
 #include "mp_internal.h"
@@ -127,12 +127,13 @@ __global__ void __launch_bounds__(256) k_bwd_stats(Plan plan, BwdWork b, const T
   }
   b.mu[wi] = ok ? mu : 0.0;
   b.isig[wi] = (ok && !same && sg > 0.0) ? 1.0 / sg : 0.0;
-  b.wpos[wi] = S.t_off + (wi - S.w_off);
   b.count[wi] = 0ull;
   b.fill[wi] = 0ull;
 }
 
-// Per-row coefficients; counts rows per neighbour window.
+// Per-row coefficients: the window record of row i (alpha, its mean, its own
+// edge) and, for a contributing row, its bucket edge and gamma on the
+// neighbour window, whose bucket count it raises.
 template <typename Tin, typename Tg>
 __global__ void __launch_bounds__(256) k_bwd_coef(Plan plan, BwdWork b, const Tin *__restrict__ Tb,
                                                   const int64_t *__restrict__ I,
@@ -151,15 +152,18 @@ __global__ void __launch_bounds__(256) k_bwd_coef(Plan plan, BwdWork b, const Ti
   const int64_t i = wi - S.w_off;
   const int64_t j = I[wi];
   const double g = (double)gP[wi];
+  const double mi = b.mu[wi];
   Double4 c{0.0, 0.0, 0.0, 0.0};
   int64_t jw = -1;
+  double isi = 0.0, isj = 0.0, mj = 0.0;
   if (j >= 0 && j < Q.l && !(S.partner == si && j == i) && g != 0.0 && isfinite(g)) {
     jw = Q.w_off + j;
-    const double isi = b.isig[wi], isj = b.isig[jw];
+    isi = b.isig[wi];
+    isj = b.isig[jw];
     if (isi > 0.0 && isj > 0.0) {
       const Tin *xi = series_samples(plan, Tb, S) + i;
       const Tin *xj = series_samples(plan, Tb, Q) + j;
-      const double mi = b.mu[wi], mj = b.mu[jw];
+      mj = b.mu[jw];
       double d2 = 0.0, dot = 0.0;
       const int m = S.m;
       // terms summed in sample order; the neighbour's window is read in
@@ -184,37 +188,36 @@ __global__ void __launch_bounds__(256) k_bwd_coef(Plan plan, BwdWork b, const Ti
       }
     }
   }
-  reinterpret_cast<Double4 *>(b.coef)[wi] = c;
   const bool live = (c.x != 0.0 || c.y != 0.0 || c.z != 0.0 || c.w != 0.0);
   b.nbr[wi] = live ? jw : -1;
+  // source offset of the own edge: neighbour start - window start
+  const int64_t delta = live ? (Q.t_off + j) - (S.t_off + i) : 0;
+  b.wrec[wi] = BwdWin{c.x, mi, live ? c.y * isj : 0.0, live ? mj : 0.0, delta, 0};
   if (live) {
-    atomicAdd(&b.count[jw], 1ull);  // bucket edge on the neighbour window
-    atomicAdd(&b.count[wi], 1ull);  // own edge
+    b.bedge[wi] = BwdEdge{c.w * isi, mi, -delta, jw};
+    b.bgam[wi] = c.z;
+    atomicAdd(&b.count[jw], 1ull);
   }
 }
 
-// Own edge of each live row (first slot of its window) and its bucket entry
-// on the neighbour window (after that window's own edge, arbitrary order).
+// Bucket entry of each contributing row on its neighbour window (arbitrary
+// order; k_bwd_rank and k_bwd_bigsort order it).
 __global__ void __launch_bounds__(256) k_bwd_place(BwdWork b, int64_t total_l) {
   const int64_t wi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (wi >= total_l) return;
   const int64_t jw = b.nbr[wi];
   if (jw < 0) return;
-  const Double4 c = reinterpret_cast<const Double4 *>(b.coef)[wi];
-  b.erec[b.off[wi]] = BwdEdge{c.y * b.isig[jw], b.mu[jw], b.wpos[jw] - b.wpos[wi], wi};
-  const int64_t base = b.off[jw] + (b.nbr[jw] >= 0 ? 1 : 0);
+  const int64_t base = b.off[jw];
   const unsigned long long pos = atomicAdd(&b.fill[jw], 1ull);
   b.tmp[base + (int64_t)pos] = wi;
   // the first row placed in a large bucket lists it for the workgroup sort
   if (pos == 0 && b.off[jw + 1] - base > kBwdSmallBucket) b.big[atomicAdd(b.nbig, 1ull)] = jw;
 }
 
-// Edge slot p of bucket row wi (neighbour window jw): the row's multiple of
-// its own window's z, applied on window jw, and its multiple of jw's z.
-__device__ __forceinline__ void put_bucket_edge(const BwdWork &b, int64_t p, int64_t wi, int64_t jw) {
-  const Double4 c = reinterpret_cast<const Double4 *>(b.coef)[wi];
-  b.erec[p] = BwdEdge{c.w * b.isig[wi], b.mu[wi], b.wpos[wi] - b.wpos[jw], jw};
-  b.egam[p] = c.z;
+// Edge slot p holds the bucket edge of row wi.
+__device__ __forceinline__ void put_bucket_edge(const BwdWork &b, int64_t p, int64_t wi) {
+  b.erec[p] = b.bedge[wi];
+  b.egam[p] = b.bgam[wi];
 }
 
 // Bucket edges in increasing row order.  In a bucket of at most
@@ -225,11 +228,11 @@ __global__ void __launch_bounds__(256) k_bwd_rank(BwdWork b, int64_t total_l) {
   if (wi >= total_l) return;
   const int64_t jw = b.nbr[wi];
   if (jw < 0) return;
-  const int64_t a = b.off[jw] + (b.nbr[jw] >= 0 ? 1 : 0), e = b.off[jw + 1];
+  const int64_t a = b.off[jw], e = b.off[jw + 1];
   if (e - a > kBwdSmallBucket) return;
   int64_t r = 0;
   for (int64_t p = a; p < e; ++p) r += b.tmp[p] < wi;
-  put_bucket_edge(b, a + r, wi, jw);
+  put_bucket_edge(b, a + r, wi);
 }
 
 // Large buckets: one workgroup sorts a bucket's row indices (a bitonic
@@ -269,7 +272,7 @@ __global__ void __launch_bounds__(256) k_bwd_bigsort(BwdWork b) {
   const unsigned long long nb = *b.nbig;
   for (unsigned long long q = blockIdx.x; q < nb; q += gridDim.x) {
     const int64_t jw = b.big[q];
-    const int64_t a = b.off[jw] + (b.nbr[jw] >= 0 ? 1 : 0), h = b.off[jw + 1] - a;
+    const int64_t a = b.off[jw], h = b.off[jw + 1] - a;
     int64_t *v = b.tmp + a;
     if (h <= kSortLds) {
       for (int64_t t = threadIdx.x; t < h; t += blockDim.x) ks[t] = v[t];
@@ -279,32 +282,23 @@ __global__ void __launch_bounds__(256) k_bwd_bigsort(BwdWork b) {
     } else {
       sort_rows(v, h);
     }
-    for (int64_t t = threadIdx.x; t < h; t += blockDim.x) put_bucket_edge(b, a + t, v[t], jw);
+    for (int64_t t = threadIdx.x; t < h; t += blockDim.x) put_bucket_edge(b, a + t, v[t]);
     __syncthreads();
   }
 }
 
-// Per window: its own alpha plus the gammas of its bucket, in edge order.
+// Per window: its own alpha plus the gammas of its bucket, in edge order,
+// times 1/sigma.
 __global__ void __launch_bounds__(256) k_bwd_window(BwdWork b, int64_t total_l) {
   const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (w >= total_l) return;
-  const bool own = b.nbr[w] >= 0;
-  double s = own ? b.coef[4 * w] : 0.0;
+  double s = b.wrec[w].sc;
   const int64_t e = b.off[w + 1];
-  for (int64_t p = b.off[w] + (own ? 1 : 0); p < e; ++p) s += b.egam[p];
-  b.wrec[w] = BwdWin{s * b.isig[w], b.mu[w]};
+  for (int64_t p = b.off[w]; p < e; ++p) s += b.egam[p];
+  b.wrec[w].sc = s * b.isig[w];
 }
 
-// Lane k's value, wave-uniform (k is uniform).
-__device__ __forceinline__ int64_t lane_i(int64_t v, int k) {
-  const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, k);
-  const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)((uint64_t)v >> 32), k);
-  return (int64_t)(((uint64_t)hi << 32) | lo);
-}
-__device__ __forceinline__ double lane_d(double v, int k) {
-  return __longlong_as_double(lane_i(__double_as_longlong(v), k));
-}
-
+// A wave-uniform 64-bit value in scalar registers.
 __device__ __forceinline__ int64_t uni64(int64_t v) {
   const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
   const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
@@ -351,9 +345,15 @@ struct GatherSrc<Tin, false> {
   }
 };
 
-// Staged edge: c and mu (one 16-byte read), then the destination window
-// relative to the wave's first covering window, the source offset in bytes
-// (buffer loads) and in samples (flat loads).
+// Staged records.  A window: sc and mu, then its own edge's c and mu (one
+// 16-byte read each) and source offset in bytes (buffer loads) and in
+// samples (flat loads).  A bucket edge: c and mu, then its destination
+// window relative to the wave's first covering window and the source offset.
+struct GatherWin {
+  double sc, mu, oc, omu;
+  int64_t odelta;
+  int32_t dbytes, pad_;
+};
 struct GatherEdge {
   double c, mu;
   int32_t rel, dbytes;
@@ -366,11 +366,14 @@ struct GatherEdge {
 // Records are fetched 64 at a time, one per lane (coalesced, all in flight
 // together), staged in the wave's own LDS slots and read back by the whole
 // wave as broadcasts.  Window ranges are tested in 32 bits relative to the
-// wave's first covering window: lane-local (rel - lt) <= span, unsigned.
+// wave's first covering window: lane-local (rel - lt) <= span, unsigned.  A
+// lane outside a term's window adds c * 0 (its sample, which may be any
+// value, is replaced before the product).
 template <typename Tin, typename Tg, bool kBuf>
 __global__ void __launch_bounds__(256) k_bwd_gather(Plan plan, BwdWork b, const Tin *__restrict__ Tb,
                                                     Tg *gT, int64_t total_n) {
-  __shared__ GatherEdge stage[4][64];  // per wave: 64 window or edge records
+  __shared__ GatherWin stage_w[4][64];   // per wave: 64 window records
+  __shared__ GatherEdge stage_e[4][64];  // per wave: 64 bucket edges
   const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t x0 = uni64(x - (int64_t)(threadIdx.x & 63));
   if (x0 >= total_n) return;
@@ -393,43 +396,57 @@ __global__ void __launch_bounds__(256) k_bwd_gather(Plan plan, BwdWork b, const 
   const BwdEdge *__restrict__ erec = b.erec;
   const int64_t *__restrict__ off = b.off;
   const int lane = threadIdx.x & 63;
-  GatherEdge *const st = stage[threadIdx.x >> 6];
+  GatherWin *const sw = stage_w[threadIdx.x >> 6];
+  GatherEdge *const se = stage_e[threadIdx.x >> 6];
   double acc = 0.0;
-  // First the multiples of each covering window's own z ...
+  // First each covering window's multiple of its own z and its own edge
+  // (four windows per step: their source loads are issued together).  A
+  // window without an own edge (oc = 0) keeps its source sample out: that
+  // sample may lie in a non-finite window.  Slots past the last window are
+  // zero and lie beyond every lane's range.
   for (int64_t c = lo_w; c <= hi_w; c += 64) {
-    GatherEdge q{0.0, 0.0, 0, 0, 0};
+    GatherWin q{0.0, 0.0, 0.0, 0.0, 0, 0, 0};
     if (c + lane <= hi_w) {
       const BwdWin w = wrec[c + lane];
-      q.c = w.sc;
-      q.mu = w.mu;
+      q = GatherWin{w.sc, w.mu, w.oc, w.omu, w.odelta, (int32_t)(w.odelta * (int64_t)sizeof(Tin)), 0};
     }
-    st[lane] = q;
+    sw[lane] = q;
     __builtin_amdgcn_wave_barrier();
-    const int cnt = (int)min((int64_t)64, hi_w - c + 1);
+    const int cnt = ((int)min((int64_t)64, hi_w - c + 1) + 3) & ~3;
     const uint32_t base = (uint32_t)(c - lo_w) - lt;
-    for (int k = 0; k < cnt; ++k) {
-      const double2 r = *reinterpret_cast<const double2 *>(&st[k]);
-      const double dv = xt - r.y;
-      acc = fma(r.x, base + (uint32_t)k <= span ? dv : 0.0, acc);
+    for (int k = 0; k < cnt; k += 4) {
+      double v[4];
+      bool in[4], io[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const GatherWin &g = sw[k + u];
+        const double oc = g.oc;
+        in[u] = base + (uint32_t)(k + u) <= span;
+        io[u] = in[u] & (oc != 0.0);
+        v[u] = src.load(g.dbytes, g.odelta, io[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double2 sm = *reinterpret_cast<const double2 *>(&sw[k + u].sc);
+        const double2 om = *reinterpret_cast<const double2 *>(&sw[k + u].oc);
+        const double dt = xt - sm.y, dv = v[u] - om.y;
+        acc = fma(sm.x, in[u] ? dt : 0.0, acc);
+        acc = fma(om.x, io[u] ? dv : 0.0, acc);
+      }
     }
     __builtin_amdgcn_wave_barrier();
   }
-  // ... then the edges of the covering windows, one flat run of the edge
-  // array (each edge carries its destination window).  Eight edges per
-  // step: their sample loads are issued together and summed afterwards in
-  // edge order.  Fetch slots past the run get a destination no lane covers.
+  // ... then the bucket edges of the covering windows, one flat run of the
+  // edge array (each edge carries its destination window).  Eight edges per
+  // step.  Fetch slots past the run get a destination no lane covers.
   const int64_t eb = uni64(off[lo_w]), ee = uni64(off[hi_w + 1]);
   for (int64_t c = eb; c < ee; c += 64) {
     GatherEdge q{0.0, 0.0, INT32_MIN, 0, 0};
     if (c + lane < ee) {
       const BwdEdge e = erec[c + lane];
-      q.c = e.c;
-      q.mu = e.mu;
-      q.rel = (int32_t)(e.dest - lo_w);
-      q.dbytes = (int32_t)(e.delta * (int64_t)sizeof(Tin));
-      q.delta = e.delta;
+      q = GatherEdge{e.c, e.mu, (int32_t)(e.dest - lo_w), (int32_t)(e.delta * (int64_t)sizeof(Tin)), e.delta};
     }
-    st[lane] = q;
+    se[lane] = q;
     __builtin_amdgcn_wave_barrier();
     const int cnt = ((int)min((int64_t)64, ee - c) + 7) & ~7;
     for (int k = 0; k < cnt; k += 8) {
@@ -437,15 +454,13 @@ __global__ void __launch_bounds__(256) k_bwd_gather(Plan plan, BwdWork b, const 
       bool in[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        const GatherEdge &g = st[k + u];
+        const GatherEdge &g = se[k + u];
         in[u] = (uint32_t)g.rel - lt <= span;
         v[u] = src.load(g.dbytes, g.delta, in[u]);
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        // a lane outside the window adds c * 0 (its sample, which may be
-        // any value, is replaced before the product)
-        const double2 cm = *reinterpret_cast<const double2 *>(&st[k + u]);
+        const double2 cm = *reinterpret_cast<const double2 *>(&se[k + u]);
         const double dv = v[u] - cm.y;
         acc = fma(cm.x, in[u] ? dv : 0.0, acc);
       }
