@@ -135,7 +135,7 @@ __global__ void __launch_bounds__(256) k_bwd_stats(Plan plan, BwdWork b, const T
 // edge) and, for a contributing row, its bucket edge and gamma on the
 // neighbour window, whose bucket count it raises.
 template <typename Tin, typename Tg>
-__global__ void __launch_bounds__(256) k_bwd_coef(Plan plan, BwdWork b, const Tin *__restrict__ Tb,
+__global__ void __launch_bounds__(256, sizeof(Tin) == 4 ? 8 : 6) k_bwd_coef(Plan plan, BwdWork b, const Tin *__restrict__ Tb,
                                                   const int64_t *__restrict__ I,
                                                   const Tg *__restrict__ gP, int64_t total_l) {
   // z_i - z_j must be exactly 0 for identical windows (d == 0 takes the
@@ -167,9 +167,10 @@ __global__ void __launch_bounds__(256) k_bwd_coef(Plan plan, BwdWork b, const Ti
       double d2 = 0.0, dot = 0.0;
       const int m = S.m;
       // terms summed in sample order; the neighbour's window is read in
-      // 16-byte chunks (for_each_sample)
+      // 16-byte chunks, two in flight (with eight waves per SIMD for float
+      // input, six for double, to hide the rest of the latency)
       auto row = [&](auto xi_at) {
-        for_each_sample(xj, m, [&](int u, double vj) {
+        for_each_sample<Tin, 2>(xj, m, [&](int u, double vj) {
           const double zi = (xi_at(u) - mi) * isi, zj = (vj - mj) * isj;
           d2 = fma(zi - zj, zi - zj, d2);
           dot = fma(zi, zj, dot);

@@ -144,12 +144,13 @@ __device__ __forceinline__ void store_out(const Outputs &o, const SeriesDesc &S,
 // The FP64 distance of the chosen pair reads the row's own window from a
 // workgroup tile of the series (staged once when the workgroup's 256
 // windows lie in one series and m <= kFinTileM) and the partner's window in
-// 16-byte chunks; the terms are summed in sample order either way.
+// 16-byte chunks, two in flight, at eight waves per SIMD; the terms are
+// summed in sample order either way.
 constexpr int kFinTile = 256;
 constexpr int kFinTileM = 2048;
 
 template <typename Tin, typename Tout>
-__global__ void __launch_bounds__(256) k_finalize(Plan plan, Work wk, const Tin *__restrict__ Tb,
+__global__ void __launch_bounds__(256, 8) k_finalize(Plan plan, Work wk, const Tin *__restrict__ Tb,
                                                   Outputs o, int fp64_finalize, double kappa,
                                                   int64_t total_l) {
   // z_a - z_b must be exactly 0 for windows that are offset copies (as in
@@ -229,7 +230,7 @@ __global__ void __launch_bounds__(256) k_finalize(Plan plan, Work wk, const Tin 
       const Tin *xl = xs + threadIdx.x;
       double s2 = 0.0;
       auto pass = [&](auto a_at) {
-        for_each_sample(series_samples(plan, Tb, Q) + idx, S.m, [&](int u, double vb) {
+        for_each_sample<Tin, 2>(series_samples(plan, Tb, Q) + idx, S.m, [&](int u, double vb) {
           const double za = (a_at(u) - muA) * ia;
           const double zb = (vb - muB) * ib;
           const double d = za - zb;

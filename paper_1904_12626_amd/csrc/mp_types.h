@@ -62,12 +62,12 @@ struct __attribute__((aligned(sizeof(T)))) Chunk16 {
 
 // f(u, (double)x[u]) for u = 0 .. m-1, in that order.  Meant for a window at
 // an arbitrary offset per lane (a neighbour picked by the profile index):
-// it is read as 16-byte chunks, four in flight, so a wave touches a quarter
+// it is read as 16-byte chunks, D in flight, so a wave touches a quarter
 // of the cache lines per load instruction and never waits on the load it is
 // about to use.  Reads stay inside x[0 .. m-1].
-template <typename Tin, typename Fn>
+template <typename Tin, int D = 4, typename Fn>
 __device__ __forceinline__ void for_each_sample(const Tin *__restrict__ x, int m, Fn &&f) {
-  constexpr int E = 16 / sizeof(Tin), D = 4;
+  constexpr int E = 16 / sizeof(Tin);
   using C = Chunk16<Tin>;
   const int nch = m / E;
   auto chunk = [&](int q) { return *reinterpret_cast<const C *>(x + (int64_t)min(q, nch - 1) * E); };
