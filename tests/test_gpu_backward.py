@@ -109,6 +109,24 @@ def test_backward_hub_constant_and_nan_windows():
     assert bad.size == 0, (bad[:70].tolist(), g[bad[:8]].tolist(), ref[bad[:8]].tolist())
 
 
+def test_backward_long_window():
+    """m = 2100 is past the LDS tile of the window statistics and the
+    coefficients: both read the series from global memory.  Against the FP64
+    reference gradient."""
+    import paper_1904_12626_amd as mpx
+    B, n, m, ez = 2, 5200, 2100, 525
+    T = walk_batch(B, n, 41, np.float64)
+    Tg = torch.from_numpy(T).to(DEV).requires_grad_(True)
+    P, I = mpx.matrix_profile(Tg, m, ez, precision="f64")
+    w = torch.from_numpy(np.random.default_rng(42).uniform(0.5, 1.5, P.shape)).to(DEV)
+    (P * w).sum().backward()
+    g = Tg.grad.cpu().numpy()
+    Ih, wh = I.cpu().numpy(), w.cpu().numpy()
+    for b in range(B):
+        ref = O.reference_gradient(T[b], m, Ih[b], wh[b])
+        np.testing.assert_allclose(g[b], ref, rtol=1e-9, atol=1e-9 * np.abs(ref).max())
+
+
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 def test_gather_flat_and_buffer_loads_agree(dtype):
     """The gather reads source samples with buffer loads (arrays under 2 GiB,

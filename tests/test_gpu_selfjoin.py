@@ -175,12 +175,15 @@ def test_paper_walk_with_exact_ties(m, precision):
 
 
 @pytest.mark.parametrize("precision", ["f64", "f32"])
-def test_long_window(precision):
-    """A window of 2048 samples (eight times the largest elsewhere): long
-    FP64 seeds, and in the FP32 sweep a cross product of size ~m sigma^2
-    carried over whole tiles.  Sampled rows against the oracle; every row
-    admissible and consistent with its reported pair."""
-    n, m, ez = 24000, 2048, 512
+@pytest.mark.parametrize("m", [2048, 2304])
+def test_long_window(precision, m):
+    """Windows of 2048 and 2304 samples (eight and nine times the largest
+    elsewhere): long FP64 seeds, and in the FP32 sweep a cross product of
+    size ~m sigma^2 carried over whole tiles; 2304 is past the window
+    statistics' and the finalize's LDS tile, so they read the series from
+    global memory.  Sampled rows against the oracle; every row admissible
+    and consistent with its reported pair."""
+    n, ez = 24000, m // 4
     T = random_walk(n, 91, np.float32)
     Th = T.astype(np.float64)
     # the FP64 path on float64 input (P comes back in the input's type)
