@@ -167,7 +167,8 @@ void finish_job(Job &j) {
 
 struct Layout {
   size_t mu, sig, keys, flags, nc, nv, rc, special, counters, segp, segs, segq, rescan, sdesc, wdesc, kmask;
-  size_t b_mu, b_isig, b_nbr, b_wrec, b_bedge, b_bgam, b_count, b_fill, b_off, b_tmp, b_erec, b_egam, b_chunk, b_big,
+  size_t b_mu, b_isig, b_nbr, b_wrec, b_alpha, b_wsc, b_bedge, b_bgam, b_bpos, b_count, b_off, b_tmp, b_erec, b_egam,
+      b_chunk, b_big,
       b_nbig;
   size_t total;
 };
@@ -199,10 +200,12 @@ Layout layout_of(const Job &j, bool with_batch_tables) {
     L.b_isig = take(8 * tl);
     L.b_nbr = take(8 * tl);
     L.b_wrec = take(sizeof(mpx::BwdWin) * tl);
+    L.b_alpha = take(8 * tl);
+    L.b_wsc = take(8 * tl);
     L.b_bedge = take(sizeof(mpx::BwdEdge) * tl);
     L.b_bgam = take(8 * tl);
+    L.b_bpos = take(4 * tl);
     L.b_count = take(8 * tl);
-    L.b_fill = take(8 * tl);
     L.b_off = take(8 * (tl + 1));
     L.b_tmp = take(8 * tl);  // indexed like erec
     L.b_erec = take(sizeof(mpx::BwdEdge) * tl);
@@ -244,10 +247,12 @@ mpx::BwdWork bwd_work_of(const Layout &L, void *ws) {
   w.isig = (double *)(b + L.b_isig);
   w.nbr = (int64_t *)(b + L.b_nbr);
   w.wrec = (mpx::BwdWin *)(b + L.b_wrec);
+  w.alpha = (double *)(b + L.b_alpha);
+  w.wsc = (double *)(b + L.b_wsc);
   w.bedge = (mpx::BwdEdge *)(b + L.b_bedge);
   w.bgam = (double *)(b + L.b_bgam);
+  w.bpos = (uint32_t *)(b + L.b_bpos);
   w.count = (unsigned long long *)(b + L.b_count);
-  w.fill = (unsigned long long *)(b + L.b_fill);
   w.off = (int64_t *)(b + L.b_off);
   w.tmp = (int64_t *)(b + L.b_tmp);
   w.erec = (mpx::BwdEdge *)(b + L.b_erec);

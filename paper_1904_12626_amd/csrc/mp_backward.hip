@@ -128,14 +128,13 @@ __global__ void __launch_bounds__(256) k_bwd_stats(Plan plan, BwdWork b, const T
   b.mu[wi] = ok ? mu : 0.0;
   b.isig[wi] = (ok && !same && sg > 0.0) ? 1.0 / sg : 0.0;
   b.count[wi] = 0ull;
-  b.fill[wi] = 0ull;
 }
 
-// Per-row coefficients: the window record of row i (alpha, its mean, its own
+// Per-row coefficients: row i's alpha and window record (its mean, its own
 // edge) and, for a contributing row, its bucket edge and gamma on the
-// neighbour window, whose bucket count it raises.
+// neighbour window, and its arrival position in that window's bucket.
 template <typename Tin, typename Tg>
-__global__ void __launch_bounds__(256, sizeof(Tin) == 4 ? 8 : 6) k_bwd_coef(Plan plan, BwdWork b, const Tin *__restrict__ Tb,
+__global__ void __launch_bounds__(256, sizeof(Tin) == 4 ? 7 : 6) k_bwd_coef(Plan plan, BwdWork b, const Tin *__restrict__ Tb,
                                                   const int64_t *__restrict__ I,
                                                   const Tg *__restrict__ gP, int64_t total_l) {
   // z_i - z_j must be exactly 0 for identical windows (d == 0 takes the
@@ -167,7 +166,7 @@ __global__ void __launch_bounds__(256, sizeof(Tin) == 4 ? 8 : 6) k_bwd_coef(Plan
       double d2 = 0.0, dot = 0.0;
       const int m = S.m;
       // terms summed in sample order; the neighbour's window is read in
-      // 16-byte chunks, two in flight (with eight waves per SIMD for float
+      // 16-byte chunks, two in flight (with seven waves per SIMD for float
       // input, six for double, to hide the rest of the latency)
       auto row = [&](auto xi_at) {
         for_each_sample<Tin, 2>(xj, m, [&](int u, double vj) {
@@ -193,23 +192,24 @@ __global__ void __launch_bounds__(256, sizeof(Tin) == 4 ? 8 : 6) k_bwd_coef(Plan
   b.nbr[wi] = live ? jw : -1;
   // source offset of the own edge: neighbour start - window start
   const int64_t delta = live ? (Q.t_off + j) - (S.t_off + i) : 0;
-  b.wrec[wi] = BwdWin{c.x, mi, live ? c.y * isj : 0.0, live ? mj : 0.0, delta, 0};
+  b.wrec[wi] = BwdWin{mi, live ? c.y * isj : 0.0, live ? mj : 0.0, delta};
+  b.alpha[wi] = c.x;
   if (live) {
     b.bedge[wi] = BwdEdge{c.w * isi, mi, -delta, jw};
     b.bgam[wi] = c.z;
-    atomicAdd(&b.count[jw], 1ull);
+    b.bpos[wi] = (uint32_t)atomicAdd(&b.count[jw], 1ull);
   }
 }
 
-// Bucket entry of each contributing row on its neighbour window (arbitrary
-// order; k_bwd_rank and k_bwd_bigsort order it).
+// Bucket entry of each contributing row on its neighbour window, at its
+// arrival position (arbitrary order; k_bwd_rank and k_bwd_bigsort order it).
 __global__ void __launch_bounds__(256) k_bwd_place(BwdWork b, int64_t total_l) {
   const int64_t wi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (wi >= total_l) return;
   const int64_t jw = b.nbr[wi];
   if (jw < 0) return;
   const int64_t base = b.off[jw];
-  const unsigned long long pos = atomicAdd(&b.fill[jw], 1ull);
+  const uint32_t pos = b.bpos[wi];
   b.tmp[base + (int64_t)pos] = wi;
   // the first row placed in a large bucket lists it for the workgroup sort
   if (pos == 0 && b.off[jw + 1] - base > kBwdSmallBucket) b.big[atomicAdd(b.nbig, 1ull)] = jw;
@@ -293,10 +293,10 @@ __global__ void __launch_bounds__(256) k_bwd_bigsort(BwdWork b) {
 __global__ void __launch_bounds__(256) k_bwd_window(BwdWork b, int64_t total_l) {
   const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (w >= total_l) return;
-  double s = b.wrec[w].sc;
+  double s = b.alpha[w];
   const int64_t e = b.off[w + 1];
   for (int64_t p = b.off[w]; p < e; ++p) s += b.egam[p];
-  b.wrec[w].sc = s * b.isig[w];
+  b.wsc[w] = s * b.isig[w];
 }
 
 // A wave-uniform 64-bit value in scalar registers.
@@ -394,6 +394,7 @@ __global__ void __launch_bounds__(256) k_bwd_gather(Plan plan, BwdWork b, const 
   double xt = (double)Tb[xs];
   xt = isfinite(xt) ? xt : 0.0;
   const BwdWin *__restrict__ wrec = b.wrec;
+  const double *__restrict__ wsc = b.wsc;
   const BwdEdge *__restrict__ erec = b.erec;
   const int64_t *__restrict__ off = b.off;
   const int lane = threadIdx.x & 63;
@@ -409,7 +410,7 @@ __global__ void __launch_bounds__(256) k_bwd_gather(Plan plan, BwdWork b, const 
     GatherWin q{0.0, 0.0, 0.0, 0.0, 0, 0, 0};
     if (c + lane <= hi_w) {
       const BwdWin w = wrec[c + lane];
-      q = GatherWin{w.sc, w.mu, w.oc, w.omu, w.odelta, (int32_t)(w.odelta * (int64_t)sizeof(Tin)), 0};
+      q = GatherWin{wsc[c + lane], w.mu, w.oc, w.omu, w.odelta, (int32_t)(w.odelta * (int64_t)sizeof(Tin)), 0};
     }
     sw[lane] = q;
     __builtin_amdgcn_wave_barrier();

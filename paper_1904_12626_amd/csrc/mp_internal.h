@@ -101,9 +101,8 @@ struct Work {
 // Backward workspace (batch plans).  The gradient of one row i -> j is a
 // multiple of z_i plus a multiple of z_j on window i, and the same on window
 // j.  Per window w: the multiples of its own z (its row's alpha and the
-// gammas of the rows naming w as neighbour) are summed into one coefficient,
-// and its row's multiple of z_j is the window's own edge; these sit in the
-// window record (`wrec`).  The multiple of z_i that a row puts on its
+// gammas of the rows naming w as neighbour) are summed into one coefficient
+// (`wsc`), and its row's multiple of z_j is the window's own edge (`wrec`).  The multiple of z_i that a row puts on its
 // neighbour j is a bucket edge of j (`erec`): coefficient, source mean,
 // source offset and destination.  Bucket edges are grouped by destination
 // window (CSR `off`), in increasing row order.
@@ -114,25 +113,24 @@ struct BwdEdge {
   int64_t dest;  // destination window (global index)
 };
 struct BwdWin {
-  double sc;     // summed multiple of this window's z, times 1/sigma (its row's
-                 // alpha alone until the per-window pass)
   double mu;     // mean of this window
   double oc;     // own edge: coefficient on (x[t + odelta] - omu), 0 if none
   double omu;    // own edge: mean of the neighbour window
   int64_t odelta;// own edge: neighbour start - window start (samples)
-  int64_t pad_;
 };
 struct BwdWork {
   double *mu;          // [total_l] window mean
   double *isig;        // [total_l] 1/sigma, 0 for constant or non-finite windows
   int64_t *nbr;        // [total_l] neighbour window (global), -1 if the row contributes nothing
   BwdWin *wrec;        // [total_l] window records
+  double *alpha;       // [total_l] per row: its multiple of its own window's z
+  double *wsc;         // [total_l] per window: alpha plus its bucket's gammas, times 1/sigma
   BwdEdge *bedge;      // [total_l] per row: its bucket edge on the neighbour window
   double *bgam;        // [total_l] per row: its multiple of the neighbour's z (gamma)
+  uint32_t *bpos;      // [total_l] per row: its position in the neighbour's bucket (arrival order)
   unsigned long long *count;  // [total_l] bucket rows per window
-  unsigned long long *fill;   // [total_l] placement cursor per bucket
   int64_t *off;        // [total_l + 1] bucket offsets (exclusive prefix of count)
-  int64_t *tmp;        // [total_l] bucket rows in placement order (edge slots)
+  int64_t *tmp;        // [total_l] bucket rows in arrival order (edge slots)
   BwdEdge *erec;       // [total_l] bucket edges in CSR order
   double *egam;        // [total_l] gamma of each bucket edge, same order
   int64_t *chunk;      // [ceil(total_l / 1024) + 1] scan partials
