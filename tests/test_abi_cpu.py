@@ -98,6 +98,27 @@ def test_bad_options():
                            None) == B.MP_EUNSUPPORTED
 
 
+def test_option_flags():
+    """Known flags (FP64 finalize, flat loads) are accepted, any other bit is
+    refused before anything is enqueued."""
+    lib = B.lib()
+    for flags in (0, B.MP_FLAG_FP64_FINALIZE, B.MP_FLAG_FLAT_LOADS,
+                  B.MP_FLAG_FP64_FINALIZE | B.MP_FLAG_FLAT_LOADS):
+        opt = B.mp_options(1, 0, 0, flags)
+        assert lib.mp_selfjoin_workspace(1000, 10, B.MP_F32, ctypes.byref(opt)) > 0
+    off = (ctypes.c_int64 * 3)(0, 100, 350)
+    m = (ctypes.c_int32 * 2)(8, 16)
+    ez = (ctypes.c_int32 * 2)(2, 4)
+    h = ctypes.c_void_p()
+    opt = B.mp_options(1, 0, 0, B.MP_FLAG_FLAT_LOADS)
+    assert lib.mp_batch_plan_create(2, off, m, ez, B.MP_F32, ctypes.byref(opt), ctypes.byref(h)) == 0
+    lib.mp_batch_plan_destroy(h)
+    for bad in (4, 8, 1 << 30):
+        opt = B.mp_options(1, 0, 0, bad)
+        assert lib.mp_selfjoin_workspace(1000, 10, B.MP_F32, ctypes.byref(opt)) == 0
+        assert lib.mp_batch_plan_create(2, off, m, ez, B.MP_F32, ctypes.byref(opt), ctypes.byref(h)) == B.MP_EINVAL
+
+
 def test_batch_plan_host_side():
     lib = B.lib()
     off = (ctypes.c_int64 * 4)(0, 100, 350, 1000)
