@@ -109,6 +109,35 @@ def test_backward_hub_constant_and_nan_windows():
     assert bad.size == 0, (bad[:70].tolist(), g[bad[:8]].tolist(), ref[bad[:8]].tolist())
 
 
+def test_backward_degenerate_series():
+    """A batch mixing a one-window series, a series with no admissible
+    neighbour (l = ez + 1), an all-constant series and an ordinary walk:
+    the forward gives (+inf, -1) on the first three, and the backward gives
+    exact zeros there (no row, no bucket edge, no own edge) and the
+    reference gradient on the walk."""
+    import paper_1904_12626_amd as mpx
+    m = 16
+    lengths = [m, m + 4, 60, 700]
+    zs = [4, 4, 4, 4]
+    rng = np.random.default_rng(51)
+    series = [np.cumsum(rng.standard_normal(lengths[0])), np.cumsum(rng.standard_normal(lengths[1])),
+              np.full(lengths[2], 3.25), np.cumsum(rng.standard_normal(lengths[3]))]
+    Tg = torch.from_numpy(np.concatenate(series)).to(DEV)
+    plan = mpx.BatchPlan(lengths, [m] * 4, zs, dtype=torch.float64, device=DEV, precision="f64")
+    P, I = plan.run(Tg)
+    Ps, Is = plan.split(P.cpu().numpy()), plan.split(I.cpu().numpy())
+    assert np.all(np.isinf(Ps[0])) and np.all(Is[0] == -1)
+    assert np.all(np.isinf(Ps[1])) and np.all(Is[1] == -1)
+    gP = torch.from_numpy(np.random.default_rng(52).uniform(0.5, 1.5, P.shape)).to(DEV)
+    g = plan.backward(Tg, I, gP).cpu().numpy()
+    gs = np.split(g, np.cumsum(lengths)[:-1])
+    for s in range(3):
+        assert np.all(gs[s] == 0.0), s
+    Ih, gPs = Is[3], plan.split(gP.cpu().numpy())[3]
+    ref = O.reference_gradient(series[3], m, Ih, gPs)
+    np.testing.assert_allclose(gs[3], ref, rtol=1e-9, atol=1e-9 * np.abs(ref).max())
+
+
 def test_backward_long_window():
     """m = 2100 is past the LDS tile of the window statistics and the
     coefficients: both read the series from global memory.  Against the FP64
