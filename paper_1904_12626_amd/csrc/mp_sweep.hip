@@ -450,7 +450,9 @@ __global__ void __launch_bounds__(64, (SweepMinWaves<F, DT>::value))
     // which are never used), so their latency overlaps a pair's arithmetic.
     V4 nrd0 = ldu(rowd + i0), nrd1 = ldu(rowd + i0 + 1), nnc0 = ldu(newcol), nnc1 = ldu(newcol + 1);
     for (int64_t sb = 0; sb < nsteps; sb += TP) {
-      const int nb = (int)min((int64_t)TP, nsteps - sb);  // a multiple of DT (even)
+      // a multiple of DT (even); wave-uniform, kept in a scalar register so
+      // that the per-pair guard below is a scalar branch
+      const int nb = __builtin_amdgcn_readfirstlane((int)min((int64_t)TP, nsteps - sb));
       static_for<TP / 2>([&](auto qc) {
         constexpr int u0 = 2 * decltype(qc)::value, u1 = u0 + 1;
         constexpr int r0 = u0 % DT, r1 = u1 % DT;  // register of slot 0 in each row
