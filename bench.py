@@ -467,12 +467,16 @@ def rec_diff(steps, warmup, dev, log):
     sweep_ms, fwd_ms = lib_sweep_ms(lambda: plan.run(flat), 5)
     Pf, If = plan.run(flat)
     gP = torch.ones(plan.profile_length, dtype=torch.float32, device=dev)
-    _, bwd_ms, _ = ev_steps(lambda: plan.backward(flat, If, gP), steps, warmup)
+    # the step's backward (autograd reuses the forward's window statistics
+    # and distances), and the standalone one that recomputes them
+    _, bwd_ms, _ = ev_steps(lambda: plan.backward_after_forward(flat, If, Pf, gP), steps, warmup)
+    _, bwd_full_ms, _ = ev_steps(lambda: plan.backward(flat, If, gP), steps, warmup)
     rec = {"workload": f"differentiable profile: {Bn} float32 random walks n={n}, m={m}, ez={ez}; forward + "
                        "backward of L = sum(P) replayed as one captured graph",
            "cells": cells, "dtype": "f32", "steps": steps, "warmup": warmup, "ms_per_step_median": med,
            "cells_per_s": cells / (med / 1e3), "roofline": roofline_of(cells, sweep_ms, "k_sweep<float>"),
-           "forward_ms": fwd_ms, "backward_ms_median": bwd_ms, "graph_replay_equals_eager": same,
+           "forward_ms": fwd_ms, "backward_ms_median": bwd_ms, "backward_recomputing_ms_median": bwd_full_ms,
+           "graph_replay_equals_eager": same,
            "note": "cells_per_s counts forward cells per second of forward+backward steps",
            "autotune": {"space": entry["space"], "choice": choice, "budget": entry["budget"],
                         "trials": [{k: t[k] for k in ("tile_slots", "reseed_rows", "sweep_ms", "within_budget")

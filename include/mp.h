@@ -241,11 +241,32 @@ mp_status mp_anytime_order(int64_t count, uint64_t seed, int64_t *order_host);
  * h > 64 rows (their order is settled by a sort).
  * Uses the batch plan's layout: T_cat / I_cat / gP_cat as for mp_batch,
  * gT_cat (n values per series, `dtype`) is overwritten.  The workspace is
- * the plan's workspace (its forward contents are overwritten).
+ * the plan's workspace; the backward writes only its own tables there (what
+ * the last mp_batch left, P's window statistics, stays).
  */
 mp_status mp_backward(const mp_batch_plan *plan, const void *T_cat, const int64_t *I_cat,
                       const void *gP_cat, void *gT_cat, void *ws, size_t ws_bytes,
                       void *stream);
+
+/* The same gradient for a call that follows mp_batch on the same plan,
+ * workspace and T_cat, with P_cat / I_cat that mp_batch wrote (a training
+ * step: forward, then backward).  It reuses what the forward left in the
+ * workspace instead of recomputing it: the window means and standard
+ * deviations (the same two-pass FP64 values mp_backward computes), and
+ * each row's distance d = P[i] (the forward's FP64 recompute of
+ * d(i, I[i]), which mp_backward forms the same way), with
+ * rho = 1 - d^2/(2m) in place of the dot product; no window is read.  The
+ * result equals mp_backward's up to the rounding of rho (and, for float
+ * data, of d stored in a float P).
+ * Requires the plan's MP_FLAG_FP64_FINALIZE (else MP_EUNSUPPORTED) and
+ * MP_SIDES_BOTH.  The caller guarantees that no other mp_batch ran on this
+ * workspace since the one that produced P_cat, and that T_cat is unchanged;
+ * the library cannot check either.  Same layouts, ownership, errors and
+ * determinism as mp_backward (it too writes only the backward tables).
+ */
+mp_status mp_backward_after_forward(const mp_batch_plan *plan, const void *T_cat, const int64_t *I_cat,
+                                    const void *P_cat, const void *gP_cat, void *gT_cat, void *ws,
+                                    size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------- multidimensional joins
  * A series with D dimensions sampled together (1 <= D <= 8), stored

@@ -36,6 +36,7 @@ EXPORTS = (
     "mp_fluss_workspace", "mp_fluss", "mp_chains_workspace", "mp_chains", "mp_abjoin_plan_create",
     "mp_mdjoin_workspace", "mp_mdjoin", "mp_mdjoin_cells",
     "mp_stream_workspace", "mp_stream_init", "mp_stream_append", "mp_selfjoin_noalloc",
+    "mp_backward_after_forward",
 )
 
 
@@ -79,6 +80,7 @@ def lib():
         "mp_batch": (ctypes.c_int, [vp, vp, vp, vp, vp, sz, vp]),
         "mp_batch_plan_destroy": (None, [vp]),
         "mp_backward": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, sz, vp]),
+        "mp_backward_after_forward": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, vp, sz, vp]),
         "mp_recheck_workspace": (sz, [i64, i32]),
         "mp_recheck": (ctypes.c_int, [vp, i64, i32, i32, vp, vp, i32, i32, vp, vp, vp, sz, vp]),
         "mp_strerror": (ctypes.c_char_p, [ctypes.c_int]),
@@ -276,6 +278,7 @@ class BatchPlan:
     def _setup(self, h):
         L = lib()
         self._h = h
+        self.forward_count = 0   # mp_batch calls on this plan's workspace so far
         self.profile_length = int(L.mp_batch_plan_profile_length(h))
         self.cells = int(L.mp_batch_plan_cells(h))
         self.ws_bytes = int(L.mp_batch_plan_workspace(h))
@@ -297,7 +300,29 @@ class BatchPlan:
             I_cat = torch.empty(self.profile_length, dtype=torch.int64, device=T_cat.device)
         _check("mp_batch", lib().mp_batch(self._h, _ptr(T_cat), _ptr(P_cat), _ptr(I_cat), _ptr(self.workspace),
                                           self.ws_bytes, _stream(stream)))
+        self.forward_count += 1
         return P_cat, I_cat
+
+    @property
+    def reuses_forward(self) -> bool:
+        """Whether backward_after_forward applies: the plan finalizes P in
+        FP64 and gives the plain profile (not left/right)."""
+        return bool(self._opt.flags & MP_FLAG_FP64_FINALIZE) and getattr(self, "sides", "both") == "both"
+
+    def backward_after_forward(self, T_cat, I_cat, P_cat, gP_cat, gT_cat=None, stream=None):
+        """mp_backward_after_forward: the backward of the last `run` on this
+        plan (same T_cat, its P_cat and I_cat), reusing the forward's window
+        statistics and distances.  The caller guarantees no other `run`
+        happened in between (`forward_count` tells)."""
+        T_cat = _series(T_cat, "T_cat")
+        gP_cat = gP_cat.contiguous().to(self.dtype)
+        if gT_cat is None:
+            gT_cat = torch.empty_like(T_cat)
+        _check("mp_backward_after_forward",
+               lib().mp_backward_after_forward(self._h, _ptr(T_cat), _ptr(I_cat.contiguous()), _ptr(P_cat.contiguous()),
+                                               _ptr(gP_cat), _ptr(gT_cat), _ptr(self.workspace), self.ws_bytes,
+                                               _stream(stream)))
+        return gT_cat
 
     def backward(self, T_cat, I_cat, gP_cat, gT_cat=None, stream=None):
         T_cat = _series(T_cat, "T_cat")

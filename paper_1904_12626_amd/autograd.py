@@ -20,7 +20,8 @@ class MatrixProfileFn(torch.autograd.Function):
         P, I = plan.run(Tc)
         ctx.plan = plan
         ctx.shape = T.shape
-        ctx.save_for_backward(Tc, I)
+        ctx.forward_id = plan.forward_count
+        ctx.save_for_backward(Tc, I, P)
         ctx.mark_non_differentiable(I)
         if T.dim() == 2:
             B = T.shape[0]
@@ -29,9 +30,16 @@ class MatrixProfileFn(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, gP, gI):
-        Tc, I = ctx.saved_tensors
+        # (autograd refuses saved tensors modified in place, so T is the
+        # forward's; the plan's workspace still holds this forward's window
+        # statistics while no other forward has run on it)
+        Tc, I, P = ctx.saved_tensors
         gP = torch.nan_to_num(gP.reshape(-1), nan=0.0, posinf=0.0, neginf=0.0)
-        gT = ctx.plan.backward(Tc, I, gP)
+        plan = ctx.plan
+        if plan.reuses_forward and plan.forward_count == ctx.forward_id:
+            gT = plan.backward_after_forward(Tc, I, P, gP)
+        else:
+            gT = plan.backward(Tc, I, gP)
         return gT.view(ctx.shape), None
 
 

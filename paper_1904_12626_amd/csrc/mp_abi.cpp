@@ -260,6 +260,9 @@ mpx::BwdWork bwd_work_of(const Layout &L, void *ws) {
   w.chunk = (int64_t *)(b + L.b_chunk);
   w.big = (int64_t *)(b + L.b_big);
   w.nbig = (unsigned long long *)(b + L.b_nbig);
+  w.fmu = (const double *)(b + L.mu);
+  w.fsig = (const double *)(b + L.sig);
+  w.fflags = (const uint8_t *)(b + L.flags);
   return w;
 }
 
@@ -820,6 +823,26 @@ mp_status mp_backward(const mp_batch_plan *pl, const void *T_cat, const int64_t 
   const mpx::Plan p = plan_of(pl->job, pl->lay, ws, true);
   if (mpx::launch_backward(p, w, T_cat, pl->job.t_f64, I_cat, gP_cat, gT_cat, pl->job.total_l,
                            pl->job.total_n, pl->job.opt.flat_loads, (hipStream_t)stream) != hipSuccess)
+    return MP_ELAUNCH;
+  return MP_OK;
+}
+
+mp_status mp_backward_after_forward(const mp_batch_plan *pl, const void *T_cat, const int64_t *I_cat,
+                                    const void *P_cat, const void *gP_cat, void *gT_cat, void *ws,
+                                    size_t ws_bytes, void *stream) {
+  if (!pl || !T_cat || !I_cat || !P_cat || !gP_cat || !gT_cat) return MP_EINVAL;
+  if (pl->job.lr || !pl->job.opt.fp64_finalize) return MP_EUNSUPPORTED;
+  const size_t es = pl->job.t_f64 ? 8 : 4;
+  if (!aligned(T_cat, es) || !aligned(P_cat, es) || !aligned(gP_cat, es) || !aligned(gT_cat, es) ||
+      !aligned(I_cat, 8))
+    return MP_EINVAL;
+  mp_status s = check_ws(ws, ws_bytes, pl->lay.total);
+  if (s != MP_OK) return s;
+  const mpx::BwdWork w = bwd_work_of(pl->lay, ws);
+  const mpx::Plan p = plan_of(pl->job, pl->lay, ws, true);
+  if (mpx::launch_backward_after_forward(p, w, T_cat, pl->job.t_f64, I_cat, P_cat, gP_cat, gT_cat,
+                                         pl->job.total_l, pl->job.total_n, pl->job.opt.flat_loads,
+                                         (hipStream_t)stream) != hipSuccess)
     return MP_ELAUNCH;
   return MP_OK;
 }

@@ -201,6 +201,74 @@ __global__ void __launch_bounds__(256, sizeof(Tin) == 4 ? 7 : 6) k_bwd_coef(Plan
   }
 }
 
+// ------------------------------------------- backward after the forward
+// Window statistics as k_bwd_stats computes them, read from the forward's
+// (the same two-pass FP64 arithmetic, so the same values): mean (0 for a
+// non-finite window) and 1/sigma (0 for constant or non-finite windows).
+__device__ __forceinline__ void fwd_window(const BwdWork &b, int64_t w, double &mu, double &isig) {
+  const uint8_t f = b.fflags[w];
+  const double sg = b.fsig[w];
+  const bool ok = (f & 1) != 0;
+  mu = ok ? b.fmu[w] : 0.0;
+  isig = (ok && !(f & 2) && sg > 0.0) ? 1.0 / sg : 0.0;
+}
+
+// Clears the bucket counts and the large-bucket list (k_bwd_stats does it
+// on the other path).
+__global__ void __launch_bounds__(256) k_bwd_zero(BwdWork b, int64_t total_l) {
+  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w == 0) *b.nbig = 0ull;
+  if (w < total_l) b.count[w] = 0ull;
+}
+
+// k_bwd_coef without reading any sample: the row's distance d is its entry
+// of the forward's FP64-finalized profile (the direct-difference sum that
+// k_bwd_coef forms itself), and rho = 1 - d^2/(2m) (d^2 = 2m(1 - rho) for
+// z-normalised windows).  Also writes the row's window statistics for the
+// kernels that follow.
+template <typename Tp, typename Tg>
+__global__ void __launch_bounds__(256) k_bwd_coef_fwd(Plan plan, BwdWork b, const int64_t *__restrict__ I,
+                                                      const Tp *__restrict__ P, const Tg *__restrict__ gP,
+                                                      int64_t total_l) {
+  const int64_t w0 = (int64_t)blockIdx.x * blockDim.x;
+  const int s0 = find_series_by_w(plan, w0);
+  const bool one = s0 == find_series_by_w(plan, min(w0 + (int64_t)blockDim.x, total_l) - 1);
+  const int64_t wi = w0 + threadIdx.x;
+  if (wi >= total_l) return;
+  const int si = one ? s0 : find_series_by_w(plan, wi);
+  const SeriesDesc S = plan.series(si);
+  const SeriesDesc Q = plan.series(S.partner);
+  const int64_t i = wi - S.w_off;
+  const int64_t j = I[wi];
+  const double g = (double)gP[wi];
+  double mi, isi;
+  fwd_window(b, wi, mi, isi);
+  b.mu[wi] = mi;
+  b.isig[wi] = isi;
+  Double4 c{0.0, 0.0, 0.0, 0.0};
+  int64_t jw = -1;
+  double isj = 0.0, mj = 0.0;
+  if (j >= 0 && j < Q.l && !(S.partner == si && j == i) && g != 0.0 && isfinite(g)) {
+    jw = Q.w_off + j;
+    fwd_window(b, jw, mj, isj);
+    const double d = (double)P[wi];
+    if (isi > 0.0 && isj > 0.0 && d > 0.0 && isfinite(d)) {
+      const double rho = 1.0 - d * d / (2.0 * S.m);
+      c = Double4{g * rho * isi / d, -g * isi / d, g * rho * isj / d, -g * isj / d};
+    }
+  }
+  const bool live = (c.x != 0.0 || c.y != 0.0 || c.z != 0.0 || c.w != 0.0);
+  b.nbr[wi] = live ? jw : -1;
+  const int64_t delta = live ? (Q.t_off + j) - (S.t_off + i) : 0;
+  b.wrec[wi] = BwdWin{mi, live ? c.y * isj : 0.0, live ? mj : 0.0, delta};
+  b.alpha[wi] = c.x;
+  if (live) {
+    b.bedge[wi] = BwdEdge{c.w * isi, mi, -delta, jw};
+    b.bgam[wi] = c.z;
+    b.bpos[wi] = (uint32_t)atomicAdd(&b.count[jw], 1ull);
+  }
+}
+
 // Bucket entry of each contributing row on its neighbour window, at its
 // arrival position (arbitrary order; k_bwd_rank and k_bwd_bigsort order it).
 __global__ void __launch_bounds__(256) k_bwd_place(BwdWork b, int64_t total_l) {
@@ -472,20 +540,14 @@ __global__ void __launch_bounds__(256) k_bwd_gather(Plan plan, BwdWork b, const 
   if (act) gT[x] = (Tg)acc;
 }
 
-hipError_t launch_backward(const Plan &plan, const BwdWork &b, const void *T, bool t_f64,
-                           const int64_t *I, const void *gP, void *gT, int64_t total_l,
-                           int64_t total_n, bool flat_loads, hipStream_t st) {
+namespace {
+
+// Everything after the per-row coefficients: bucket offsets, placement,
+// ordering, per-window sums and the gather.
+hipError_t launch_backward_tail(const Plan &plan, const BwdWork &b, const void *T, bool t_f64, void *gT,
+                                int64_t total_l, int64_t total_n, bool flat_loads, hipStream_t st) {
   const dim3 blk(256);
   const dim3 gl((unsigned)((total_l + 255) / 256)), gn((unsigned)((total_n + 255) / 256));
-  if (t_f64) {
-    hipLaunchKernelGGL((k_bwd_stats<double>), gl, blk, 0, st, plan, b, (const double *)T, total_l);
-    hipLaunchKernelGGL((k_bwd_coef<double, double>), gl, blk, 0, st, plan, b, (const double *)T, I,
-                       (const double *)gP, total_l);
-  } else {
-    hipLaunchKernelGGL((k_bwd_stats<float>), gl, blk, 0, st, plan, b, (const float *)T, total_l);
-    hipLaunchKernelGGL((k_bwd_coef<float, float>), gl, blk, 0, st, plan, b, (const float *)T, I,
-                       (const float *)gP, total_l);
-  }
   const hipError_t e = launch_exclusive_scan(reinterpret_cast<const int64_t *>(b.count), b.off, b.chunk,
                                              total_l, st);
   if (e != hipSuccess) return e;
@@ -511,6 +573,40 @@ hipError_t launch_backward(const Plan &plan, const BwdWork &b, const void *T, bo
                          (float *)gT, total_n);
   }
   return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_backward(const Plan &plan, const BwdWork &b, const void *T, bool t_f64,
+                           const int64_t *I, const void *gP, void *gT, int64_t total_l,
+                           int64_t total_n, bool flat_loads, hipStream_t st) {
+  const dim3 blk(256);
+  const dim3 gl((unsigned)((total_l + 255) / 256));
+  if (t_f64) {
+    hipLaunchKernelGGL((k_bwd_stats<double>), gl, blk, 0, st, plan, b, (const double *)T, total_l);
+    hipLaunchKernelGGL((k_bwd_coef<double, double>), gl, blk, 0, st, plan, b, (const double *)T, I,
+                       (const double *)gP, total_l);
+  } else {
+    hipLaunchKernelGGL((k_bwd_stats<float>), gl, blk, 0, st, plan, b, (const float *)T, total_l);
+    hipLaunchKernelGGL((k_bwd_coef<float, float>), gl, blk, 0, st, plan, b, (const float *)T, I,
+                       (const float *)gP, total_l);
+  }
+  return launch_backward_tail(plan, b, T, t_f64, gT, total_l, total_n, flat_loads, st);
+}
+
+hipError_t launch_backward_after_forward(const Plan &plan, const BwdWork &b, const void *T, bool t_f64,
+                                         const int64_t *I, const void *P, const void *gP, void *gT,
+                                         int64_t total_l, int64_t total_n, bool flat_loads, hipStream_t st) {
+  const dim3 blk(256);
+  const dim3 gl((unsigned)((total_l + 255) / 256));
+  hipLaunchKernelGGL(k_bwd_zero, gl, blk, 0, st, b, total_l);
+  if (t_f64)
+    hipLaunchKernelGGL((k_bwd_coef_fwd<double, double>), gl, blk, 0, st, plan, b, I, (const double *)P,
+                       (const double *)gP, total_l);
+  else
+    hipLaunchKernelGGL((k_bwd_coef_fwd<float, float>), gl, blk, 0, st, plan, b, I, (const float *)P,
+                       (const float *)gP, total_l);
+  return launch_backward_tail(plan, b, T, t_f64, gT, total_l, total_n, flat_loads, st);
 }
 
 }  // namespace mpx

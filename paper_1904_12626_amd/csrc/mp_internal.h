@@ -136,6 +136,11 @@ struct BwdWork {
   int64_t *chunk;      // [ceil(total_l / 1024) + 1] scan partials
   int64_t *big;        // [total_l / kBwdSmallBucket + 1] buckets with more than kBwdSmallBucket rows
   unsigned long long *nbig;  // [1] entries of `big`
+  // the forward's window statistics in the same workspace (mean, sigma,
+  // flags bit0 valid / bit1 constant), read by the backward that follows it
+  const double *fmu;
+  const double *fsig;
+  const uint8_t *fflags;
 };
 // Buckets of at most this many rows are ordered by a per-row count; larger
 // ones (hub windows named by many rows) are sorted by one workgroup each.
@@ -170,6 +175,13 @@ size_t recheck_state_bytes();
 hipError_t launch_backward(const Plan &plan, const BwdWork &b, const void *T, bool t_f64,
                            const int64_t *I, const void *gP, void *gT, int64_t total_l,
                            int64_t total_n, bool flat_loads, hipStream_t st);
+// The backward right after the forward on the same workspace and samples:
+// window statistics from the forward (b.fmu / b.fsig / b.fflags), each
+// row's distance from the forward's FP64-finalized profile P (P's dtype is
+// the samples' dtype).
+hipError_t launch_backward_after_forward(const Plan &plan, const BwdWork &b, const void *T, bool t_f64,
+                                         const int64_t *I, const void *P, const void *gP, void *gT,
+                                         int64_t total_l, int64_t total_n, bool flat_loads, hipStream_t st);
 
 // Exclusive prefix sum: out[0..n] (out[n] = total) of in[0..n); `partial`
 // holds ceil(n / 1024) + 1 entries of scratch.

@@ -138,6 +138,90 @@ def test_backward_degenerate_series():
     np.testing.assert_allclose(gs[3], ref, rtol=1e-9, atol=1e-9 * np.abs(ref).max())
 
 
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_backward_after_forward_matches_backward(dtype):
+    """mp_backward_after_forward (window statistics and distances taken from
+    the forward) against mp_backward (both recomputed from the samples) on a
+    ragged batch with a NaN sample and a constant stretch: equal up to the
+    rounding of rho = 1 - d^2/(2m) (and of d stored in a float P), and
+    bitwise repeatable."""
+    import paper_1904_12626_amd as mpx
+    lengths, ms = [900, 333, 1500, 64], [24, 16, 40, 8]
+    zs = [m // 4 for m in ms]
+    series = _batch(lengths, ms, 61, dtype)
+    series[2][400:470] = 0.75
+    series[0][500] = np.nan
+    Tg = torch.from_numpy(np.concatenate(series)).to(DEV)
+    tdt = torch.float64 if dtype == np.float64 else torch.float32
+    plan = mpx.BatchPlan(lengths, ms, zs, dtype=tdt, device=DEV, precision="f64" if dtype == np.float64 else "f32")
+    assert plan.reuses_forward
+    P, I = plan.run(Tg)
+    gP = torch.from_numpy(np.random.default_rng(62).uniform(-1, 2, P.shape).astype(dtype)).to(DEV)
+    full = plan.backward(Tg, I, gP).clone()
+    fast = plan.backward_after_forward(Tg, I, P, gP).clone()
+    again = plan.backward_after_forward(Tg, I, P, gP)
+    torch.cuda.synchronize()
+    assert torch.equal(fast, again)
+    a, b = full.double().cpu().numpy(), fast.double().cpu().numpy()
+    assert np.all(np.isfinite(b))
+    tol = 1e-11 if dtype == np.float64 else 2e-5
+    np.testing.assert_allclose(b, a, rtol=tol, atol=tol * np.abs(a).max())
+
+
+def test_abjoin_backward_after_forward():
+    """The AB-join plan's layout: dL/dA and dL/dB from the forward's state
+    equal the full backward's."""
+    import paper_1904_12626_amd as mpx
+    rng = np.random.default_rng(63)
+    A, Bs, m = np.cumsum(rng.standard_normal(1500)), np.cumsum(rng.standard_normal(900)), 32
+    plan = mpx.ABJoinPlan(A.size, Bs.size, m, dtype=torch.float64, device=DEV, precision="f64")
+    Tg = torch.from_numpy(np.concatenate([A, Bs])).to(DEV)
+    P, I = plan.run(Tg)
+    gP = torch.from_numpy(rng.uniform(0.5, 1.5, P.shape)).to(DEV)
+    full = plan.backward(Tg, I, gP).clone()
+    fast = plan.backward_after_forward(Tg, I, P, gP)
+    a, b = full.cpu().numpy(), fast.cpu().numpy()
+    np.testing.assert_allclose(b, a, rtol=1e-11, atol=1e-11 * np.abs(a).max())
+
+
+def test_autograd_falls_back_when_another_forward_intervened():
+    """Two forwards on one plan before the first one's backward: the
+    workspace then holds the second forward's statistics, so the first
+    backward recomputes them (and is still the reference gradient); the
+    second backward may reuse them."""
+    import paper_1904_12626_amd as mpx
+    B, n, m, ez = 2, 600, 20, 5
+    T1 = walk_batch(B, n, 64, np.float64)
+    T2 = walk_batch(B, n, 65, np.float64)
+    plan = mpx.BatchPlan([n] * B, [m] * B, [ez] * B, dtype=torch.float64, device=DEV, precision="f64")
+    x1 = torch.from_numpy(T1).to(DEV).requires_grad_(True)
+    x2 = torch.from_numpy(T2).to(DEV).requires_grad_(True)
+    P1, I1 = mpx.matrix_profile(x1, m, ez, plan=plan)
+    P2, I2 = mpx.matrix_profile(x2, m, ez, plan=plan)
+    P1.sum().backward()
+    P2.sum().backward()
+    for x, T, Ih in ((x1, T1, I1), (x2, T2, I2)):
+        g = x.grad.cpu().numpy()
+        Ih = Ih.cpu().numpy()
+        for b in range(B):
+            ref = O.reference_gradient(T[b], m, Ih[b], np.ones(Ih.shape[1]))
+            np.testing.assert_allclose(g[b], ref, rtol=1e-9, atol=1e-9 * np.abs(ref).max())
+
+
+def test_backward_after_forward_needs_fp64_finalize():
+    import paper_1904_12626_amd as mpx
+    plan = mpx.BatchPlan([500], [16], [4], dtype=torch.float32, device=DEV, fp64_finalize=False)
+    assert not plan.reuses_forward
+    T = torch.from_numpy(walk_batch(1, 500, 66, np.float32).reshape(-1)).to(DEV)
+    P, I = plan.run(T)
+    with pytest.raises(mpx.MPError):
+        plan.backward_after_forward(T, I, P, torch.ones_like(P))
+    x = T.view(1, -1).clone().requires_grad_(True)
+    Pa, _ = mpx.matrix_profile(x, 16, 4, plan=plan)
+    Pa.sum().backward()           # takes mp_backward
+    assert torch.isfinite(x.grad).all()
+
+
 def test_backward_long_window():
     """m = 2100 is past the LDS tile of the window statistics and the
     coefficients: both read the series from global memory.  Against the FP64
