@@ -202,30 +202,26 @@ __global__ void __launch_bounds__(256, sizeof(Tin) == 4 ? 7 : 6) k_bwd_coef(Plan
 }
 
 // ------------------------------------------- backward after the forward
-// Window statistics as k_bwd_stats computes them, read from the forward's
-// (the same two-pass FP64 arithmetic, so the same values): mean (0 for a
-// non-finite window) and 1/sigma (0 for constant or non-finite windows).
-__device__ __forceinline__ void fwd_window(const BwdWork &b, int64_t w, double &mu, double &isig) {
+// k_bwd_stats from the forward's window statistics (the same two-pass FP64
+// arithmetic, so the same values): each window's mean (0 for a non-finite
+// window) and 1/sigma (0 for constant or non-finite windows) into the
+// backward's arrays; the bucket counts and the large-bucket list cleared.
+__global__ void __launch_bounds__(256) k_bwd_stats_fwd(BwdWork b, int64_t total_l) {
+  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w == 0) *b.nbig = 0ull;
+  if (w >= total_l) return;
   const uint8_t f = b.fflags[w];
   const double sg = b.fsig[w];
   const bool ok = (f & 1) != 0;
-  mu = ok ? b.fmu[w] : 0.0;
-  isig = (ok && !(f & 2) && sg > 0.0) ? 1.0 / sg : 0.0;
-}
-
-// Clears the bucket counts and the large-bucket list (k_bwd_stats does it
-// on the other path).
-__global__ void __launch_bounds__(256) k_bwd_zero(BwdWork b, int64_t total_l) {
-  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (w == 0) *b.nbig = 0ull;
-  if (w < total_l) b.count[w] = 0ull;
+  b.mu[w] = ok ? b.fmu[w] : 0.0;
+  b.isig[w] = (ok && !(f & 2) && sg > 0.0) ? 1.0 / sg : 0.0;
+  b.count[w] = 0ull;
 }
 
 // k_bwd_coef without reading any sample: the row's distance d is its entry
 // of the forward's FP64-finalized profile (the direct-difference sum that
 // k_bwd_coef forms itself), and rho = 1 - d^2/(2m) (d^2 = 2m(1 - rho) for
-// z-normalised windows).  Also writes the row's window statistics for the
-// kernels that follow.
+// z-normalised windows).
 template <typename Tp, typename Tg>
 __global__ void __launch_bounds__(256) k_bwd_coef_fwd(Plan plan, BwdWork b, const int64_t *__restrict__ I,
                                                       const Tp *__restrict__ P, const Tg *__restrict__ gP,
@@ -241,16 +237,14 @@ __global__ void __launch_bounds__(256) k_bwd_coef_fwd(Plan plan, BwdWork b, cons
   const int64_t i = wi - S.w_off;
   const int64_t j = I[wi];
   const double g = (double)gP[wi];
-  double mi, isi;
-  fwd_window(b, wi, mi, isi);
-  b.mu[wi] = mi;
-  b.isig[wi] = isi;
+  const double mi = b.mu[wi], isi = b.isig[wi];
   Double4 c{0.0, 0.0, 0.0, 0.0};
   int64_t jw = -1;
   double isj = 0.0, mj = 0.0;
   if (j >= 0 && j < Q.l && !(S.partner == si && j == i) && g != 0.0 && isfinite(g)) {
     jw = Q.w_off + j;
-    fwd_window(b, jw, mj, isj);
+    mj = b.mu[jw];
+    isj = b.isig[jw];
     const double d = (double)P[wi];
     if (isi > 0.0 && isj > 0.0 && d > 0.0 && isfinite(d)) {
       const double rho = 1.0 - d * d / (2.0 * S.m);
@@ -599,7 +593,7 @@ hipError_t launch_backward_after_forward(const Plan &plan, const BwdWork &b, con
                                          int64_t total_l, int64_t total_n, bool flat_loads, hipStream_t st) {
   const dim3 blk(256);
   const dim3 gl((unsigned)((total_l + 255) / 256));
-  hipLaunchKernelGGL(k_bwd_zero, gl, blk, 0, st, b, total_l);
+  hipLaunchKernelGGL(k_bwd_stats_fwd, gl, blk, 0, st, b, total_l);
   if (t_f64)
     hipLaunchKernelGGL((k_bwd_coef_fwd<double, double>), gl, blk, 0, st, plan, b, I, (const double *)P,
                        (const double *)gP, total_l);
