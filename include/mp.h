@@ -243,6 +243,10 @@ mp_status mp_anytime_order(int64_t count, uint64_t seed, int64_t *order_host);
  * gT_cat (n values per series, `dtype`) is overwritten.  The workspace is
  * the plan's workspace; the backward writes only its own tables there (what
  * the last mp_batch left, P's window statistics, stays).
+ * MP_EUNSUPPORTED for left/right plans and for windows longer than 2^30
+ * samples; MP_EINVAL for null or misaligned pointers; MP_EWORKSPACE for a
+ * workspace that is null, misaligned or smaller than the plan's; MP_ELAUNCH
+ * when a kernel launch fails.
  */
 mp_status mp_backward(const mp_batch_plan *plan, const void *T_cat, const int64_t *I_cat,
                       const void *gP_cat, void *gT_cat, void *ws, size_t ws_bytes,

@@ -266,6 +266,16 @@ mpx::BwdWork bwd_work_of(const Layout &L, void *ws) {
   return w;
 }
 
+// The backward covers self-join and AB-join plans whose windows are at most
+// 2^30 samples long (the gather tests window ranges in 32 bits relative to
+// a wave's first covering window: fewer than 64 + m of them).
+bool backward_supported(const Job &j) {
+  if (j.lr) return false;
+  for (const SeriesDesc &s : j.series)
+    if (s.m > (1 << 30)) return false;
+  return true;
+}
+
 mpx::Plan plan_of(const Job &j, const Layout &L, void *ws, bool external) {
   mpx::Plan p{};
   p.nseries = (int32_t)j.series.size();
@@ -813,7 +823,7 @@ mp_status mp_timing_query(double *sweep_ms, double *total_ms, int64_t *calls) {
 mp_status mp_backward(const mp_batch_plan *pl, const void *T_cat, const int64_t *I_cat,
                       const void *gP_cat, void *gT_cat, void *ws, size_t ws_bytes, void *stream) {
   if (!pl || !T_cat || !I_cat || !gP_cat || !gT_cat) return MP_EINVAL;
-  if (pl->job.lr) return MP_EUNSUPPORTED;
+  if (!backward_supported(pl->job)) return MP_EUNSUPPORTED;
   const size_t es = pl->job.t_f64 ? 8 : 4;
   if (!aligned(T_cat, es) || !aligned(gP_cat, es) || !aligned(gT_cat, es) || !aligned(I_cat, 8))
     return MP_EINVAL;
@@ -831,7 +841,7 @@ mp_status mp_backward_after_forward(const mp_batch_plan *pl, const void *T_cat, 
                                     const void *P_cat, const void *gP_cat, void *gT_cat, void *ws,
                                     size_t ws_bytes, void *stream) {
   if (!pl || !T_cat || !I_cat || !P_cat || !gP_cat || !gT_cat) return MP_EINVAL;
-  if (pl->job.lr || !pl->job.opt.fp64_finalize) return MP_EUNSUPPORTED;
+  if (!backward_supported(pl->job) || !pl->job.opt.fp64_finalize) return MP_EUNSUPPORTED;
   const size_t es = pl->job.t_f64 ? 8 : 4;
   if (!aligned(T_cat, es) || !aligned(P_cat, es) || !aligned(gP_cat, es) || !aligned(gT_cat, es) ||
       !aligned(I_cat, 8))

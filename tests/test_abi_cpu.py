@@ -228,6 +228,12 @@ def test_new_entry_points_reject_bad_arguments():
     assert lib.mp_selfjoin_plan_create(4096, 64, 16, B.MP_F32, None, 1, 0, None, ctypes.byref(h)) == 0
     assert lib.mp_backward(h, ok, ok, ok, ok, ok, 1 << 40, None) == B.MP_EUNSUPPORTED
     lib.mp_batch_plan_destroy(h)
+    # the backward's window limit (2^30 samples), checked before any device call
+    m = (1 << 30) + 1
+    assert lib.mp_selfjoin_plan_create(m + 9, m, 0, B.MP_F32, None, 0, 0, None, ctypes.byref(h)) == 0
+    assert lib.mp_backward(h, ok, ok, ok, ok, ok, 1 << 40, None) == B.MP_EUNSUPPORTED
+    assert lib.mp_backward_after_forward(h, ok, ok, ok, ok, ok, ok, 1 << 40, None) == B.MP_EUNSUPPORTED
+    lib.mp_batch_plan_destroy(h)
 
 
 def test_noalloc_selfjoin_host_checks():
