@@ -135,6 +135,12 @@ def ceilings(vc, sweep32_cells_s, sweep64_ms, cells):
                    "one_instruction_per_cu_clock_cells_per_s": nominal, "frac_one_instruction": sweep32_cells_s / nominal,
                    "measured_mix_cells_per_s": mix32, "frac_measured_mix": sweep32_cells_s / mix32,
                    "measured_fma_only_cells_per_s": fp32, "frac_measured_fma_only": sweep32_cells_s / fp32}
+    w4 = vc.get("fp32_sweep_mix_4_waves_per_simd")
+    if w4:
+        # the same mix at the sweep's own occupancy (4 waves per SIMD)
+        mix32_w4 = w4["lane_instructions_per_s"] / MIX_F32_PER_CELL
+        out["fp32"]["measured_mix_4_waves_cells_per_s"] = mix32_w4
+        out["fp32"]["frac_measured_mix_4_waves"] = sweep32_cells_s / mix32_w4
     if sweep64_ms:
         s64 = cells / (sweep64_ms / 1e3)
         mix64 = vc["fp64_sweep_mix"]["lane_instructions_per_s"] / MIX_F64_PER_CELL

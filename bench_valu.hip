@@ -12,7 +12,11 @@
 //
 // Each kernel runs `iters` iterations of a fully unrolled body of
 // independent register chains (no memory traffic), 256-thread workgroups,
-// 8 per CU.  Timing: HIP events around each launch; the shader clock during
+// 8 per CU (8 waves per SIMD); the FP32 mix runs a second time at 4 per CU,
+// the occupancy of the FP32 sweep.  Three ways of writing one lane of a
+// register other than v_writelane_b32 (a move from a scalar register, a
+// select against a lane mask, a move under a one-lane exec mask that the
+// same asm statement saves and restores) are timed beside it.  Timing: HIP events around each launch; the shader clock during
 // the launch is taken from the core-clock counter (clock64) against the
 // constant-rate wall clock (wall_clock64) over the same interval.
 // Output: one JSON object on stdout.
@@ -27,12 +31,13 @@ namespace {
 enum Kind {
   kFmacF32, kMulF32, kFmaF32, kAndOr, kMin3I32, kMinI32, kDpp, kWritelane,
   kFmaF64, kMulF64, kMinF64, kMixF32, kMixF64,
-  kAddF32, kMinF32, kMin3F32, kDppAddF32, kAddU32, kOrB32, kCount
+  kAddF32, kMinF32, kMin3F32, kDppAddF32, kAddU32, kOrB32, kMovS, kCndmask, kMovExec, kCount
 };
 const char *kName[kCount] = {"v_fmac_f32", "v_mul_f32", "v_fma_f32", "v_and_or_b32", "v_min3_i32",
                              "v_min_i32", "v_mov_b32_dpp", "v_writelane_b32", "v_fma_f64", "v_mul_f64",
                              "v_min_f64", "fp32_sweep_mix", "fp64_sweep_mix", "v_add_f32", "v_min_f32",
-                             "v_min3_f32", "v_add_f32_dpp", "v_add_u32", "v_or_b32"};
+                             "v_min3_f32", "v_add_f32_dpp", "v_add_u32", "v_or_b32", "v_mov_b32_from_sgpr",
+                             "v_cndmask_b32_lane_mask", "v_mov_b32_exec_one_lane"};
 
 // Instructions per unrolled body, per kind.
 constexpr int kBodyFp32Mix = 48 + 24 + 24 + 24 + 21 + 4 + 8 + 8;   // 161 for 24 cells
@@ -64,6 +69,9 @@ int body_len(int k) {
 #define DPPADD(r) asm volatile("v_add_f32_dpp %0, %1, %2 wave_shl:1 row_mask:0xf bank_mask:0xf" : "=v"(g[r]) : "v"(g[((r) + 1) & 15]), "v"(y))
 #define ADDU(r) asm volatile("v_add_u32 %0, %0, %1" : "+v"(u[r]) : "v"(p))
 #define ORB(r) asm volatile("v_or_b32 %0, %0, %1" : "+v"(u[r]) : "v"(p))
+#define MOVS(r) asm volatile("v_mov_b32 %0, %1" : "=v"(w[r]) : "s"(fill))
+#define CNDM(r) asm volatile("v_cndmask_b32_e64 %0, %0, %1, %2" : "+v"(w[r]) : "v"(fillv), "s"(m63))
+#define MOVX(r) asm volatile("s_mov_b64 %1, exec\n s_mov_b64 exec, %2\n v_mov_b32 %0, %3\n s_mov_b64 exec, %1" : "+v"(w[r]), "=&s"(sv) : "s"(m63), "s"(fill))
 #define MOVB(r) asm volatile("v_mov_b32 %0, %1" : "=v"(w[r]) : "v"(w[(r) - 8]))
 
 #define R16(M) M(0); M(1); M(2); M(3); M(4); M(5); M(6); M(7); M(8); M(9); M(10); M(11); M(12); M(13); M(14); M(15)
@@ -89,6 +97,9 @@ __global__ void __launch_bounds__(256) k_probe(float *out, unsigned long long *c
   const float x = seed * 0.5f, y = 1.0f - seed * 1e-3f;
   const int mask = ~1023, code = (int)(threadIdx.x & 1023), p = (int)threadIdx.x, q = 7;
   const double dx = (double)x, dy = (double)y;
+  const unsigned long long m63 = 1ull << 63;  // lane 63
+  const int fillv = (int)threadIdx.x + fill;
+  unsigned long long sv;
   const unsigned long long c0 = clock64(), t0 = wall_clock64();
   for (int it = 0; it < iters; ++it) {
     if constexpr (K == kFmacF32) { R16(FMAC); }
@@ -108,6 +119,9 @@ __global__ void __launch_bounds__(256) k_probe(float *out, unsigned long long *c
     if constexpr (K == kDppAddF32) { R16(DPPADD); }
     if constexpr (K == kAddU32) { R16(ADDU); }
     if constexpr (K == kOrB32) { R16(ORB); }
+    if constexpr (K == kMovS) { R16(MOVS); }
+    if constexpr (K == kCndmask) { R16(CNDM); }
+    if constexpr (K == kMovExec) { R16(MOVX); }
     if constexpr (K == kMixF32) {
       // 24 cells of the FP32 sweep's loop: 48 v_fmac + 24 v_fma + 24 v_mul
       // (cross products and keys), 24 v_and_or (codes), 21 v_min3 + 4 v_min
@@ -150,7 +164,7 @@ __global__ void __launch_bounds__(256) k_probe(float *out, unsigned long long *c
 
 template <int K>
 void run(int cus, int iters, int blocks_per_cu, float *out, unsigned long long *clk, double wall_mhz, FILE *js,
-         bool last) {
+         bool last, const char *label = nullptr) {
   const int grid = cus * blocks_per_cu;
   hipEvent_t a, b;
   (void)hipEventCreate(&a);
@@ -178,7 +192,7 @@ void run(int cus, int iters, int blocks_per_cu, float *out, unsigned long long *
   const double lane_rate = winst * 64.0 / secs;
   std::fprintf(js, "  \"%s\": {\"ms\": %.4f, \"wave_instructions\": %.6e, \"lane_instructions_per_s\": %.6e, "
                    "\"core_clock_mhz\": %.1f, \"wave_instructions_per_cu_clock\": %.4f}%s\n",
-               kName[K], ms, winst, lane_rate, mhz, per_cu_clk, last ? "" : ",");
+               label ? label : kName[K], ms, winst, lane_rate, mhz, per_cu_clk, last ? "" : ",");
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
 }
@@ -223,7 +237,11 @@ int main(int argc, char **argv) {
   run<kMin3F32>(cus, iters, bpc, out, clk, wall_mhz, js, false);
   run<kDppAddF32>(cus, iters, bpc, out, clk, wall_mhz, js, false);
   run<kAddU32>(cus, iters, bpc, out, clk, wall_mhz, js, false);
-  run<kOrB32>(cus, iters, bpc, out, clk, wall_mhz, js, true);
+  run<kOrB32>(cus, iters, bpc, out, clk, wall_mhz, js, false);
+  run<kMovS>(cus, iters, bpc, out, clk, wall_mhz, js, false);
+  run<kCndmask>(cus, iters, bpc, out, clk, wall_mhz, js, false);
+  run<kMovExec>(cus, iters, bpc, out, clk, wall_mhz, js, false);
+  run<kMixF32>(cus, iters / 8, 4, out, clk, wall_mhz, js, true, "fp32_sweep_mix_4_waves_per_simd");
   std::printf("}\n");
   (void)hipFree(out);
   (void)hipFree(clk);
