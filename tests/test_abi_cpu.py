@@ -46,6 +46,36 @@ def test_cell_counts():
     assert B.selfjoin_cells(64, 64, 0) == 0
 
 
+def test_cell_counts_by_enumeration():
+    """The library's pair counts (self-join, AB-join, batch plans) equal a
+    direct enumeration of the admissible pairs on small random shapes."""
+    import numpy as np
+    rng = np.random.default_rng(11)
+    lib = B.lib()
+    for _ in range(60):
+        m = int(rng.integers(2, 20))
+        n = int(rng.integers(m, m + 80))
+        ez = int(rng.integers(0, 30))
+        l = n - m + 1
+        i, j = np.triu_indices(l, 1)
+        assert B.selfjoin_cells(n, m, ez) == int(np.count_nonzero(j - i > ez)), (n, m, ez)
+        nB = int(rng.integers(m, m + 60))
+        assert B.abjoin_cells(n, nB, m) == l * (nB - m + 1)
+    lengths, windows, zones = [50, 120, 33, 7, 90], [8, 16, 4, 7, 30], [2, 4, 1, 0, 40]
+    want = 0
+    for n, m, ez in zip(lengths, windows, zones):
+        l = n - m + 1
+        i, j = np.triu_indices(l, 1)
+        want += int(np.count_nonzero(j - i > ez))
+    h = ctypes.c_void_p()
+    off = (ctypes.c_int64 * (len(lengths) + 1))(*np.concatenate([[0], np.cumsum(lengths)]).tolist())
+    m_arr = (ctypes.c_int32 * len(lengths))(*windows)
+    z_arr = (ctypes.c_int32 * len(lengths))(*zones)
+    assert lib.mp_batch_plan_create(len(lengths), off, m_arr, z_arr, B.MP_F32, None, ctypes.byref(h)) == 0
+    assert lib.mp_batch_plan_cells(h) == want
+    lib.mp_batch_plan_destroy(h)
+
+
 def test_workspace_queries():
     lib = B.lib()
     opt = B.make_options("f32")
