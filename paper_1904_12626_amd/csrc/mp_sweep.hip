@@ -337,15 +337,17 @@ __global__ void __launch_bounds__(64, (SweepMinWaves<F, DT>::value))
       // reads its record as an LDS broadcast and the entering column as the
       // DPP fallback operand.  A row's 64 lane minima are halved by a DPP
       // exchange within lane pairs before they go to LDS; the 32 partials of
-      // row u sit in a row-rotated order (pair p at position p ^ u), so the
-      // writes of a row and the flush's reads (lane r reads row r) each touch
-      // 32 distinct banks.  Lane 0's column minimum rides in the spare slot
-      // of the entering-column record.  10 KB of LDS per wave.
+      // row u sit in order in a row of 33 doubles, so a row's writes are
+      // contiguous and the flush's reads (lane r reads row r, partial q at
+      // dword 66 r + 2 q: banks 2 (r + q) mod 64) touch distinct banks with
+      // every address an immediate offset from the lane's row.  Lane 0's
+      // column minimum rides in the spare slot of the entering-column
+      // record.  10 KB of LDS per wave.
       static_assert(TP <= 32, "row-rotated partials");
       __shared__ double lrec[TP][4];   // a_i, g_i, s_i, u_i of row sb + u
       __shared__ double lent[TP][4];   // a, g, s of the column entering after row sb + u;
                                        // [3]: the column minimum leaving through lane 0
-      __shared__ double lhalf[TP][32]; // row minima of lane pairs
+      __shared__ double lhalf[TP][33]; // row minima of lane pairs (rows padded to 33)
       V4 prow = {0.0, 0.0, 0.0, 0.0}, pcol = {0.0, 0.0, 0.0, 0.0};
       auto prefetch = [&](int64_t sb2) {
         if (lane < TP && sb2 + lane < nsteps) {
@@ -386,7 +388,7 @@ __global__ void __launch_bounds__(64, (SweepMinWaves<F, DT>::value))
           });
           K r = IK::rowmin(k);
           r = IK::kmin(r, swap_pair(r));
-          if (!(lane & 1)) lhalf[u][(lane >> 1) ^ u] = r;
+          if (!(lane & 1)) lhalf[u][lane >> 1] = r;
           // register p met slot p - r0
           static_for<DT>([&](auto pc) {
             constexpr int q = decltype(pc)::value;
@@ -402,9 +404,9 @@ __global__ void __launch_bounds__(64, (SweepMinWaves<F, DT>::value))
         // (every read of this block's is done)
         __syncthreads();
         if (lane < nb) {
-          K best = lhalf[lane][lane];
-#pragma unroll 8
-          for (int q = 1; q < 32; ++q) best = IK::kmin(best, lhalf[lane][q ^ lane]);
+          K best = lhalf[lane][0];
+#pragma unroll
+          for (int q = 1; q < 32; ++q) best = IK::kmin(best, lhalf[lane][q]);
           const int64_t s = sb + lane;
           if (s < nr) emit_row(i0 + s, best);
           emit_col(i0 + s + k0, lent[lane][3]);
