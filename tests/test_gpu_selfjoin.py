@@ -239,3 +239,31 @@ def test_exact_tie_order_of_the_fp64_sweep():
     P, I = _run(T, m, ez, "f64", reseed=4096)
     assert P[a] == 0.0 and P[a2] == 0.0 and P[c] == 0.0
     assert (I[a], I[a2]) == (a2, a) and I[c] in (a, a2)
+
+
+def test_joins_in_flight_on_two_streams():
+    """Two self-joins in flight at once on two streams, each call with its own
+    workspace and outputs, return bitwise what the same joins return one after
+    the other: nothing is shared between calls."""
+    import paper_1904_12626_amd as mpx
+    TA, TB = random_walk(6000, 21, np.float32), random_walk(5000, 22, np.float64)
+    a, b = torch.from_numpy(TA).to(DEV), torch.from_numpy(TB).to(DEV)
+    PA0, IA0 = mpx.selfjoin(a, 50, 12)
+    PB0, IB0 = mpx.selfjoin(b, 64, 16, precision="f64")
+    torch.cuda.synchronize()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    s1.wait_stream(torch.cuda.current_stream())
+    s2.wait_stream(torch.cuda.current_stream())
+    outs = []
+    for _ in range(4):
+        with torch.cuda.stream(s1):
+            ra = mpx.selfjoin(a, 50, 12, stream=s1)
+        with torch.cuda.stream(s2):
+            rb = mpx.selfjoin(b, 64, 16, precision="f64", stream=s2)
+        outs.append((ra, rb))
+    torch.cuda.synchronize()
+    for (PA, IA), (PB, IB) in outs:
+        assert torch.equal(PA, PA0) and torch.equal(IA, IA0)
+        assert torch.equal(PB, PB0) and torch.equal(IB, IB0)
+    Po, Io = cimpl.selfjoin(TB, 64, 16)
+    compare_profile(TB, 64, PB0.cpu().numpy(), IB0.cpu().numpy(), Po, Io, 1e-9, ez=16, where="two streams")
