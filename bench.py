@@ -530,7 +530,7 @@ def extra_workloads(steps, warmup, dev, log):
     return out
 
 
-def main():
+def parse_args():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
@@ -551,245 +551,242 @@ def main():
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (a known-traffic reference "
                          "for hardware byte counters)")
-    args = ap.parse_args()
+    return ap.parse_args()
 
-    world = int(os.environ.get("WORLD_SIZE", "1"))
-    if args.gpus != 1 or world != 1:
-        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}, "
-              f"WORLD_SIZE={world}); the self-join would shard by diagonal ranges with one min-reduction "
-              "of the packed keys (see the design notes)", file=sys.stderr)
-        sys.exit(2)
 
+def copy_calibration(mib, dev):
+    """One plain device copy of `mib` MiB: a known-traffic reference for the
+    hardware byte counters of a profiled run."""
+    import torch
+    nb = mib << 20
+    src = torch.ones(nb // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"[bench] copy calibration: {nb} bytes read, {nb} bytes written")
+
+
+def setup(wl, args, dev):
+    """The inputs of a workload on the device, its cell count and `step`, one
+    pass of its hot path in a given precision ("f32" or "f64")."""
+    import types
     import torch
     import paper_1904_12626_amd as mpx
-
-    if not torch.cuda.is_available():
-        raise SystemExit("bench.py needs a GPU")
-    dev = torch.device("cuda:0")
-    if args.copy_calib_mib > 0:
-        nb = args.copy_calib_mib << 20
-        src = torch.ones(nb // 4, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        log(f"[bench] copy calibration: {nb} bytes read, {nb} bytes written")
-        del src, dst
-    wl = workload(args.workload, args.n)
-    m = wl["m"]
-    stream = torch.cuda.current_stream()
-
-    if wl["kind"] == "self":
-        T = wl["T"]
-        ez = wl["ez"]
-        Tg = torch.from_numpy(T).to(dev)
-        n = T.size
-        cells = mpx.selfjoin_cells(n, m, ez)
+    w = types.SimpleNamespace(kind=wl["kind"], m=wl["m"], plans={})
+    m, slots, reseed = wl["m"], args.slots, args.reseed
+    if w.kind in ("self", "anytime", "lr", "stream", "md", "diff"):
+        w.T, w.ez = wl["T"], wl["ez"]
+        w.Tg = torch.from_numpy(w.T).to(dev)
+    if w.kind == "self":
+        w.n = w.T.size
+        w.cells = mpx.selfjoin_cells(w.n, m, w.ez)
         km, kd = (8, 4) if wl["planted"] is not None else (3, 1)
 
         def step(precision):
-            P, I = mpx.selfjoin(Tg, m, ez, precision=precision, tile_slots=args.slots, reseed_rows=args.reseed)
-            idx, dist = mpx.recheck(Tg, m, P, I, km, kd)
+            P, I = mpx.selfjoin(w.Tg, m, w.ez, precision=precision, tile_slots=args.slots, reseed_rows=args.reseed)
+            idx, dist = mpx.recheck(w.Tg, m, P, I, km, kd)
             return P, I, idx, dist
-    elif wl["kind"] == "anytime":
-        T, ez = wl["T"], wl["ez"]
-        Tg = torch.from_numpy(T).to(dev)
-        n = T.size
-        nchunk, cwidth = mpx.selfjoin_chunks(n, m, ez, tile_slots=args.slots)
-        order = mpx.anytime_order(nchunk, 0)
-        plans = {}
+    elif w.kind == "anytime":
+        w.n = w.T.size
+        w.nchunk, w.cwidth = mpx.selfjoin_chunks(w.n, m, w.ez, tile_slots=slots)
+        order = mpx.anytime_order(w.nchunk, 0)
 
         def anytime_plan(frac, precision="f32"):
-            k = min(nchunk, max(1, int(np.ceil(frac * nchunk))))
-            if (k, precision) not in plans:
-                plans[(k, precision)] = mpx.SelfJoinPlan(n, m, ez, dtype=torch.float32, device=dev,
-                                                         chunks=order[:k], precision=precision,
-                                                         tile_slots=args.slots, reseed_rows=args.reseed)
-            return plans[(k, precision)]
-        cells = anytime_plan(args.fraction).cells
-        km, kd = 8, 4
+            k = min(w.nchunk, max(1, int(np.ceil(frac * w.nchunk))))
+            if (k, precision) not in w.plans:
+                w.plans[(k, precision)] = mpx.SelfJoinPlan(w.n, m, w.ez, dtype=torch.float32, device=dev,
+                                                           chunks=order[:k], precision=precision,
+                                                           tile_slots=slots, reseed_rows=reseed)
+            return w.plans[(k, precision)]
+        w.anytime_plan = anytime_plan
+        w.cells = anytime_plan(args.fraction).cells
 
         def step(precision):
-            P, I = anytime_plan(args.fraction, precision).run(Tg)
-            idx, dist = mpx.recheck(Tg, m, P, I, km, kd)
+            P, I = anytime_plan(args.fraction, precision).run(w.Tg)
+            idx, dist = mpx.recheck(w.Tg, m, P, I, 8, 4)
             return P, I, idx, dist
-    elif wl["kind"] == "lr":
-        T, ez = wl["T"], wl["ez"]
-        Tg = torch.from_numpy(T).to(dev)
-        n = T.size
-        l = n - m + 1
-        lr_plans = {}
+    elif w.kind == "lr":
+        w.n = w.T.size
+        l = w.n - m + 1
 
         def step(precision):
-            if precision not in lr_plans:
-                lr_plans[precision] = mpx.SelfJoinPlan(n, m, ez, dtype=torch.float32, device=dev, sides="lr",
-                                                       precision=precision, tile_slots=args.slots,
-                                                       reseed_rows=args.reseed)
-            P, I = lr_plans[precision].run(Tg)
+            if precision not in w.plans:
+                w.plans[precision] = mpx.SelfJoinPlan(w.n, m, w.ez, dtype=torch.float32, device=dev, sides="lr",
+                                                      precision=precision, tile_slots=slots, reseed_rows=reseed)
+            P, I = w.plans[precision].run(w.Tg)
             cac, seg = mpx.fluss(I[:l], m, k=2)
             ch = mpx.chains(I[l:2 * l], I[2 * l:])
             return P, I, cac, seg, ch
-        cells = mpx.selfjoin_cells(n, m, ez)
-    elif wl["kind"] == "stream":
-        T, ez = wl["T"], wl["ez"]
-        n = T.size
-        n0 = n - 8192
-        Tg = torch.from_numpy(T).to(dev)
+        w.cells = mpx.selfjoin_cells(w.n, m, w.ez)
+    elif w.kind == "stream":
+        w.n = w.T.size
+        n0 = w.n - 8192
         l0 = n0 - m + 1
         # pairs scored by the appends: every new window against its admissible earlier windows
-        cells = sum(max(0, w - ez) for w in range(l0, n - m + 1))
-        state = {}
+        w.cells = sum(max(0, i - w.ez) for i in range(l0, w.n - m + 1))
+        w.state = {}
 
         def step(precision):
-            st = mpx.SelfJoinStream(Tg[:n0], m, ez, n_max=n)
+            st = mpx.SelfJoinStream(w.Tg[:n0], m, w.ez, n_max=w.n)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            for b in range(n0, n, 512):
-                st.append(Tg[b:b + 512])
+            for b in range(n0, w.n, 512):
+                st.append(w.Tg[b:b + 512])
             torch.cuda.synchronize()
-            state["append_ms"] = (time.perf_counter() - t0) * 1e3
-            state["last"] = st
+            w.state["append_ms"] = (time.perf_counter() - t0) * 1e3
+            w.state["last"] = st
             return st.P, st.I
-    elif wl["kind"] == "md":
-        T, ez = wl["T"], wl["ez"]
-        Tg = torch.from_numpy(T).to(dev)
-        D, n = T.shape
-        cells = mpx.selfjoin_cells(n, m, ez)
+    elif w.kind == "md":
+        w.n = w.T.shape[1]
+        w.cells = mpx.selfjoin_cells(w.n, m, w.ez)
 
         def step(precision):
-            return mpx.mdjoin(Tg, m, ez, mode=wl["mode"])
-    elif wl["kind"] == "ab":
-        A, B = wl["A"], wl["B"]
-        Ag, Bg = torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev)
-        cells = mpx.abjoin_cells(A.size, B.size, m)
+            return mpx.mdjoin(w.Tg, m, w.ez, mode=wl["mode"])
+    elif w.kind == "ab":
+        w.Ag, w.Bg = torch.from_numpy(wl["A"]).to(dev), torch.from_numpy(wl["B"]).to(dev)
+        w.cells = mpx.abjoin_cells(wl["A"].size, wl["B"].size, m)
 
         def step(precision):
-            return mpx.abjoin(Ag, Bg, m, precision=precision, tile_slots=args.slots, reseed_rows=args.reseed)
-    elif wl["kind"] == "batch":
+            return mpx.abjoin(w.Ag, w.Bg, m, precision=precision, tile_slots=args.slots, reseed_rows=args.reseed)
+    elif w.kind == "batch":
         rb = wl["rb"]
         Tc, _ = rb.concat()
-        Tg = torch.from_numpy(Tc).to(dev)
-        plans = {}
+        w.Tg = torch.from_numpy(Tc).to(dev)
 
         def plan_for(precision):
-            if precision not in plans:
-                plans[precision] = mpx.BatchPlan([s.size for s in rb.series], rb.m, rb.ez, dtype=torch.float32,
-                                                 device=dev, precision=precision, tile_slots=args.slots,
-                                                 reseed_rows=args.reseed)
-            return plans[precision]
-        cells = plan_for("f32").cells
+            if precision not in w.plans:
+                w.plans[precision] = mpx.BatchPlan([s.size for s in rb.series], rb.m, rb.ez, dtype=torch.float32,
+                                                   device=dev, precision=precision, tile_slots=args.slots,
+                                                   reseed_rows=args.reseed)
+            return w.plans[precision]
+        w.plan_for = plan_for
+        w.cells = plan_for("f32").cells
 
         def step(precision):
-            return plan_for(precision).run(Tg)
-    else:
-        T, ez = wl["T"], wl["ez"]
-        Tg = torch.from_numpy(T).to(dev)
-        cells = T.shape[0] * mpx.selfjoin_cells(T.shape[1], m, ez)
-        plans = {}
+            return plan_for(precision).run(w.Tg)
+    else:  # "diff": forward + backward of L = sum(P) through the autograd function
+        B, n = w.T.shape
+        w.cells = B * mpx.selfjoin_cells(n, m, w.ez)
 
         def step(precision):
-            if precision not in plans:
-                plans[precision] = mpx.BatchPlan([T.shape[1]] * T.shape[0], [m] * T.shape[0], [ez] * T.shape[0],
-                                                 dtype=torch.float32, device=dev, precision=precision,
-                                                 tile_slots=args.slots, reseed_rows=args.reseed)
-            x = Tg.clone().requires_grad_(True)
-            P, I = mpx.MatrixProfileFn.apply(x, plans[precision])
+            if precision not in w.plans:
+                w.plans[precision] = mpx.BatchPlan([n] * B, [m] * B, [w.ez] * B, dtype=torch.float32, device=dev,
+                                                   precision=precision, tile_slots=args.slots,
+                                                   reseed_rows=args.reseed)
+            x = w.Tg.clone().requires_grad_(True)
+            P, I = mpx.MatrixProfileFn.apply(x, w.plans[precision])
             P.sum().backward()
             return P, I, x.grad
+    w.step = step
+    return w
 
-    if args.autotune and wl["kind"] in ("self", "ab", "batch"):
-        from paper_1904_12626_amd import autotune as AT
-        if wl["kind"] == "self":
-            ch = AT.tune_selfjoin(Tg, m, ez, log=log)
-        elif wl["kind"] == "ab":
-            ch = AT.tune_abjoin(Ag, Bg, m, log=log)
-        else:
-            rb = wl["rb"]
-            ch = AT.tune_batch(Tg, [s.size for s in rb.series], rb.m, rb.ez, log=log)
-        args.slots, args.reseed = ch["tile_slots"], ch["reseed_rows"]
-        plans.clear() if wl["kind"] == "batch" else None
 
-    step_med = {}
+def autotune(w, wl, args):
+    """Replace the tile shape of args by the autotuner's choice for this job
+    (self-joins, AB-joins and batches; the search is logged)."""
+    from paper_1904_12626_amd import autotune as AT
+    if w.kind == "self":
+        ch = AT.tune_selfjoin(w.Tg, w.m, w.ez, log=log)
+    elif w.kind == "ab":
+        ch = AT.tune_abjoin(w.Ag, w.Bg, w.m, log=log)
+    else:
+        rb = wl["rb"]
+        ch = AT.tune_batch(w.Tg, [s.size for s in rb.series], rb.m, rb.ez, log=log)
+    args.slots, args.reseed = ch["tile_slots"], ch["reseed_rows"]
+    if w.kind == "batch":
+        w.plans.clear()
 
-    def timed(precision, steps, warmup):
-        for _ in range(warmup):
-            step(precision)
-        torch.cuda.synchronize()
-        mpx.timing_query()                      # drop earlier records
-        mpx.timing_enable(True)
-        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
-        torch.cuda.synchronize()
+
+def timed(step, precision, steps, warmup):
+    """`warmup` untimed steps, then `steps` steps between two synchronisations.
+    Returns the last output, wall-clock ms per step, the median of the steps'
+    event-timed ms, and the library's mean sweep and launch-sequence ms."""
+    import torch
+    import paper_1904_12626_amd as mpx
+    for _ in range(warmup):
+        step(precision)
+    torch.cuda.synchronize()
+    mpx.timing_query()                      # drop earlier records
+    mpx.timing_enable(True)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record()
+        out = step(precision)
+        b.record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    mpx.timing_enable(False)
+    sweep_ms, total_ms, calls = mpx.timing_query()
+    med = float(np.median([a.elapsed_time(b) for a, b in ev]))
+    return out, (t1 - t0) * 1e3 / steps, med, sweep_ms / max(calls, 1), total_ms / max(calls, 1)
+
+
+def run_stream(w, wl, args):
+    """The streaming workload: 8192 windows appended to the n = 2^20 profile
+    in batches of 512 samples; the timed unit is the appends."""
+    for _ in range(args.warmup):
+        w.step("f64")
+    times = []
+    for _ in range(args.steps):
+        w.step("f64")
+        times.append(w.state["append_ms"])
+    ms = float(np.median(times))
+    st = w.state["last"]
+    m, cells = w.m, w.cells
+    l = w.n - m + 1
+    result = {
+        "metric": METRIC, "value": cells / (ms / 1e3), "unit": "cells/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": wl["desc"] + "; FP64 state, new windows in batches of up to 63",
+                   "cells": cells, "windows_appended": 8192, "appended_windows_per_s": 8192 / (ms / 1e3)},
+        # a batch of up to 63 new windows reads each column's terms once, so the scored pairs
+        # cost FP64 arithmetic: 2 FMA (cross product), MUL + FMA + MAX (key), the column
+        # compare and the row minimum = 7 operations
+        "roofline": {"bound": "alu", "achieved": cells * 7 / (ms / 1e3) / 1e12, "peak": PEAK_LANE_OPS / 1e12,
+                     "unit": "TOP/s", "frac": cells * 7 / (ms / 1e3) / 1e12 / (PEAK_LANE_OPS / 1e12),
+                     "traffic": None, "kernel": "k_stream_batch", "ops_per_cell": 7,
+                     "note": "per batch of up to 63 windows: ~13 us reading and writing the state of every "
+                             "earlier window, then ~0.66 us per window"},
+    }
+    if args.cpu_rows > 0:
+        from oracle import cimpl
+        rng = np.random.default_rng(0)
+        rows = np.sort(rng.choice(l, 64, replace=False))
+        T64 = w.T.astype(np.float64)
         t0 = time.perf_counter()
-        for a, b in ev:
-            a.record()
-            out = step(precision)
-            b.record()
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        mpx.timing_enable(False)
-        sweep_ms, total_ms, calls = mpx.timing_query()
-        step_med["ms"] = float(np.median([a.elapsed_time(b) for a, b in ev]))
-        return out, (t1 - t0) * 1e3 / steps, sweep_ms / max(calls, 1), total_ms / max(calls, 1)
+        Po, Io = cimpl.selfjoin_rows(T64, m, w.ez, rows)
+        dt = time.perf_counter() - t0
+        pairs = int(sum(l - (min(l - 1, r + w.ez) - max(0, r - w.ez) + 1) for r in rows))
+        Pg = st.P.double().cpu().numpy()[rows]
+        result["cpu_baseline"] = {"value": pairs / dt, "unit": "cells/s", "cores": cimpl.max_threads(),
+                                  "kind": "oracle",
+                                  "sample": f"{rows.size} full rows of the grown series' self-join, {pairs} pairs, "
+                                            f"{dt:.1f} s",
+                                  "host": host_cpu()}
+        result["oracle_check"] = {"rows": int(rows.size), "max_abs_dP_vs_oracle": float(np.max(np.abs(Pg - Po)))}
+    return result
 
-    log(f"[bench] workload: {wl['desc']}; cells={cells}")
-    if wl["kind"] == "stream":
-        for _ in range(args.warmup):
-            step("f64")
-        times = []
-        for _ in range(args.steps):
-            out = step("f64")
-            times.append(state["append_ms"])
-        ms = float(np.median(times))
-        st = state["last"]
-        l = n - m + 1
-        result = {
-            "metric": METRIC, "value": cells / (ms / 1e3), "unit": "cells/s", "n_gpus": 1, "steps": args.steps,
-            "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
-            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-            "config": {"workload": wl["desc"] + "; FP64 state, new windows in batches of up to 63",
-                       "cells": cells, "windows_appended": 8192, "appended_windows_per_s": 8192 / (ms / 1e3)},
-            # a batch of up to 63 new windows reads each column's terms once, so the scored pairs
-            # cost FP64 arithmetic: 2 FMA (cross product), MUL + FMA + MAX (key), the column
-            # compare and the row minimum = 7 operations
-            "roofline": {"bound": "alu", "achieved": cells * 7 / (ms / 1e3) / 1e12, "peak": PEAK_LANE_OPS / 1e12,
-                         "unit": "TOP/s", "frac": cells * 7 / (ms / 1e3) / 1e12 / (PEAK_LANE_OPS / 1e12),
-                         "traffic": None, "kernel": "k_stream_batch", "ops_per_cell": 7,
-                         "note": "per batch of up to 63 windows: ~13 us reading and writing the state of every "
-                                 "earlier window, then ~0.66 us per window"},
-        }
-        if args.cpu_rows > 0:
-            from oracle import cimpl
-            rng = np.random.default_rng(0)
-            rows = np.sort(rng.choice(l, 64, replace=False))
-            T64 = T.astype(np.float64)
-            t0 = time.perf_counter()
-            Po, Io = cimpl.selfjoin_rows(T64, m, ez, rows)
-            dt = time.perf_counter() - t0
-            pairs = int(sum(l - (min(l - 1, r + ez) - max(0, r - ez) + 1) for r in rows))
-            Pg = st.P.double().cpu().numpy()[rows]
-            result["cpu_baseline"] = {"value": pairs / dt, "unit": "cells/s", "cores": cimpl.max_threads(),
-                                      "kind": "oracle",
-                                      "sample": f"{rows.size} full rows of the grown series' self-join, {pairs} pairs, "
-                                                f"{dt:.1f} s"}
-            result["oracle_check"] = {"rows": int(rows.size), "max_abs_dP_vs_oracle": float(np.max(np.abs(Pg - Po)))}
-        if "cpu_baseline" in result:
-            result["cpu_baseline"]["host"] = host_cpu()
-        print(json.dumps(result), flush=True)
-        return
-    out32, ms32, sweep32, tot32 = timed("f32", args.steps, args.warmup)
-    log(f"[bench] f32: {ms32:.2f} ms/step, sweep {sweep32:.2f} ms, launch sequence {tot32:.2f} ms")
-    value = cells / (ms32 / 1e3)
+
+def fp32_result(w, wl, args, ms32, med32, sweep32):
+    """The line of the FP32 run: whole-step rate and the sweep's roofline."""
+    cells = w.cells
     achieved = cells * OPS_PER_CELL / (sweep32 / 1e3) / 1e12
     peak32 = PEAK_CELLS["f32"] * OPS_PER_CELL / 1e12
-    result = {
+    default = (w.kind == "self" and args.n is None and not args.slots and not args.reseed
+               and args.workload == "selfjoin_large")
+    return {
         "metric": METRIC,
-        "value": value,
+        "value": cells / (ms32 / 1e3),
         "unit": "cells/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms32,
-        "ms_per_step_median": step_med.get("ms"),
+        "ms_per_step_median": med32,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -800,8 +797,7 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak32, "unit": "TOP/s",
                      "frac": achieved / peak32, "peak_model": PEAK_NOTE,
                      "frac_one_instruction_per_cu_clock": achieved / (PEAK_LANE_OPS / 1e12),
-                     "traffic": measured_traffic() if (wl["kind"] == "self" and args.n is None and not args.slots
-                                                       and not args.reseed and args.workload == "selfjoin_large") else None,
+                     "traffic": measured_traffic() if default else None,
                      "traffic_source": "rocprofv3 FETCH_SIZE + WRITE_SIZE of the FP32 sweep on this workload "
                                        "(copy-calibrated), profiles/k_sweep_f32_traffic.json; reported only "
                                        "while the built sweep's gfx950 assembly hash equals the counted one, "
@@ -810,247 +806,335 @@ def main():
                      "sweep_ms_per_launch": sweep32, "sweep_cells_per_s": cells / (sweep32 / 1e3)},
     }
 
-    if wl["kind"] == "batch":
-        plan = plan_for("f32")
-        Pg = torch.empty(plan.profile_length, dtype=torch.float32, device=dev)
-        Ig = torch.empty(plan.profile_length, dtype=torch.int64, device=dev)
-        side = torch.cuda.Stream()
-        side.wait_stream(torch.cuda.current_stream())
-        with torch.cuda.stream(side):
-            plan.run(Tg, Pg, Ig)
-        torch.cuda.current_stream().wait_stream(side)
-        torch.cuda.synchronize()
-        graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(graph):
-            plan.run(Tg, Pg, Ig)
-        for _ in range(args.warmup):
-            graph.replay()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            graph.replay()
-        torch.cuda.synchronize()
-        msg = (time.perf_counter() - t0) * 1e3 / args.steps
-        same = bool(torch.equal(Pg, out32[0]) and torch.equal(Ig, out32[1]))
-        log(f"[bench] graph replay: {msg:.2f} ms/step (eager {ms32:.2f}); replay equals eager: {same}")
-        result["eager_ms_per_step"] = ms32
-        result["ms_per_step"] = msg
-        result["value"] = cells / (msg / 1e3)
-        result["graph_replay_equals_eager"] = same
-        result["config"]["series"] = len(wl["rb"].series)
-    if wl["kind"] == "diff":
-        # the same forward + backward step captured once and replayed: dL/dP
-        # = 1 comes from a static ones tensor (torch's multi-block sum would
-        # put a memset into the graph), outputs and gradient are static
-        plan = plans["f32"]
-        ones = torch.ones_like(out32[0])
-        xs = Tg.clone().requires_grad_(True)
-        side = torch.cuda.Stream()
-        side.wait_stream(torch.cuda.current_stream())
-        with torch.cuda.stream(side):
-            mpx.MatrixProfileFn.apply(xs, plan)[0].backward(ones)
-        torch.cuda.current_stream().wait_stream(side)
-        torch.cuda.synchronize()
-        xs.grad = None
-        graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(graph):
-            Pg, Ig = mpx.MatrixProfileFn.apply(xs, plan)
-            Pg.backward(ones)
-        for _ in range(args.warmup):
-            graph.replay()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            graph.replay()
-        torch.cuda.synchronize()
-        msg = (time.perf_counter() - t0) * 1e3 / args.steps
-        same = bool(torch.equal(Pg, out32[0]) and torch.equal(Ig, out32[1]) and torch.equal(xs.grad, out32[2]))
-        log(f"[bench] graph replay: {msg:.2f} ms/step (eager {ms32:.2f}); replay equals eager: {same}")
-        result["eager_ms_per_step"] = ms32
-        result["ms_per_step"] = msg
-        result["value"] = cells / (msg / 1e3)
-        result["graph_replay_equals_eager"] = same
-        result["config"]["note"] = ("value counts forward cells per second of forward+backward steps, "
-                                    "replayed as one captured graph")
-    if wl["kind"] == "md":
-        # algorithmic VALU operations per cell of the multidimensional sweep
-        D = wl["T"].shape[0]
-        ops = 5 * D + 2 if wl["mode"] == "simple" else 6 * D + D * (D - 1) + 4 * D
-        ach = cells * ops / (sweep32 / 1e3) / 1e12
-        result["dtype"] = "f64"
-        result["config"]["workload"] = wl["desc"] + "; FP64 cross products, float candidate keys, FP64 recompute of P"
-        result["config"]["dims"] = D
-        result["roofline"].update({"achieved": ach, "frac": ach / (PEAK_LANE_OPS / 1e12), "kernel": "k_md_sweep",
-                                   "ops_per_cell": ops, "traffic": None})
-    if wl["kind"] == "lr":
-        ch = out32[4]
-        result["config"]["longest_chain"] = len(ch["best"])
-        result["config"]["chains_min3"] = ch["count"]
-        result["config"]["boundaries"] = [int(v) for v in out32[3].cpu().tolist()]
-    if wl["kind"] == "anytime":
-        # convergence of the best-so-far profile towards the exact one as
-        # more chunks (in one fixed random order) are included
-        l = n - m + 1
-        tol = 1e-3 * np.sqrt(m)
-        Pfull, Ifull = anytime_plan(1.0).run(Tg)
-        Pfull = Pfull.double().cpu().numpy()
-        planted = wl["planted"].motif_pairs
-        conv = []
-        for frac in (0.01, 0.02, 0.05, 0.1, 0.25, 0.5, 1.0):
-            plan = anytime_plan(frac)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            P, I = plan.run(Tg)
-            idx, _ = mpx.recheck(Tg, m, P, I, 8, 0)
-            torch.cuda.synchronize()
-            ms = (time.perf_counter() - t0) * 1e3
-            Ph = P.double().cpu().numpy()
-            fin = np.isfinite(Pfull)
-            found = [tuple(sorted(p)) for p in idx.cpu().numpy()[:16].reshape(8, 2)]
-            hits = sum(any(abs(a - x) <= m // 8 and abs(b - y) <= m // 8 for x, y in found) for a, b in planted)
-            conv.append({"fraction_of_chunks": plan.cells / mpx.selfjoin_cells(n, m, ez), "chunks": len(plan.chunks),
-                         "ms": ms, "rows_within_tol_of_exact": float(np.mean(np.abs(Ph[fin] - Pfull[fin]) <= tol)),
-                         "mean_excess_over_exact": float(np.mean(Ph[fin] - Pfull[fin])),
-                         "planted_pairs_in_top8_motifs": int(hits)})
-            log(f"[bench] anytime {conv[-1]}")
-        result["convergence"] = conv
-        result["config"]["chunk_width"] = cwidth
-        result["config"]["chunks_total"] = nchunk
-        result["config"]["chunks_timed"] = len(anytime_plan(args.fraction).chunks)
 
-    if not args.no_fp64 and wl["kind"] in ("self", "ab"):
-        # FP64 GPU path: 3 warm-ups, then the median of at least 5 event-timed steps
-        out64, ms64, _ = ev_steps(lambda: step("f64"), max(5, min(args.steps, 8)), 3)
-        sweep64, _ = lib_sweep_ms(lambda: step("f64"), 3)
-        log(f"[bench] f64: {ms64:.2f} ms/step (median), sweep {sweep64:.2f} ms")
-        P32, I32 = out32[0].double().cpu().numpy(), out32[1].cpu().numpy()
-        P64, I64 = out64[0].double().cpu().numpy(), out64[1].cpu().numpy()
-        if wl["kind"] == "ab":   # both directions
-            P32 = np.concatenate([P32, out32[2].double().cpu().numpy()])
-            I32 = np.concatenate([I32, out32[3].cpu().numpy()])
-            P64 = np.concatenate([P64, out64[2].double().cpu().numpy()])
-            I64 = np.concatenate([I64, out64[3].cpu().numpy()])
-        fin = np.isfinite(P64)
-        raw = None
-        if wl["kind"] == "self":
-            Praw, _ = mpx.selfjoin(Tg, m, ez, precision="f32", fp64_finalize=False)
-            raw = float(np.max(np.abs(Praw.double().cpu().numpy()[fin] - P64[fin])))
-        result["fp64_path"] = {
-            "value": cells / (ms64 / 1e3), "ms_per_step": ms64, "sweep_ms_per_launch": sweep64,
-            "speedup_f32_over_f64": ms64 / ms32, "steps": max(5, min(args.steps, 8)), "warmup": 3,
-            "timing": "median of event-timed steps",
-            "max_abs_dP_f32_vs_f64": float(np.max(np.abs(P32[fin] - P64[fin]))),
-            "max_abs_dP_f32_raw_vs_f64": raw,
-            "index_agreement_f32_vs_f64": float(np.mean(I32 == I64)),
-            "tolerance": 1e-3 * np.sqrt(m),
-            "roofline": roofline_of(cells, sweep64, "k_sweep<double>", "f64"),
-        }
+def replay_graph(capture, outputs_match, result, ms32, args):
+    """Capture `capture()` (already run once eagerly, on a side stream) as
+    one graph, time its replays and record them in `result` as the step."""
+    import torch
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        capture()
+    for _ in range(args.warmup):
+        graph.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        graph.replay()
+    torch.cuda.synchronize()
+    msg = (time.perf_counter() - t0) * 1e3 / args.steps
+    same = outputs_match()
+    log(f"[bench] graph replay: {msg:.2f} ms/step (eager {ms32:.2f}); replay equals eager: {same}")
+    result["eager_ms_per_step"] = ms32
+    result["ms_per_step"] = msg
+    result["value"] = result["config"]["cells"] / (msg / 1e3)
+    result["graph_replay_equals_eager"] = same
 
-    if args.cpu_rows > 0 and wl["kind"] == "self":
-        from oracle import cimpl
-        rng = np.random.default_rng(0)
-        l = n - m + 1
-        rows = list(rng.choice(l, args.cpu_rows, replace=False))
-        if wl["planted"] is not None:
-            for a, b in wl["planted"].motif_pairs:
-                rows += [a, b]
-            rows += list(wl["planted"].discords)
-        rows = np.array(sorted(set(int(r) for r in rows)), dtype=np.int64)
-        T64 = T.astype(np.float64)
-        threads = cimpl.max_threads()
+
+def eager_on_side_stream(fn):
+    """Run `fn` once on a side stream (the warm-up torch's graph capture
+    asks for) and wait for it."""
+    import torch
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        fn()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+
+
+def post_batch(w, wl, args, result, out32, ms32, dev):
+    """The batch replayed from one captured graph is the timed step."""
+    import torch
+    plan = w.plan_for("f32")
+    Pg = torch.empty(plan.profile_length, dtype=torch.float32, device=dev)
+    Ig = torch.empty(plan.profile_length, dtype=torch.int64, device=dev)
+    eager_on_side_stream(lambda: plan.run(w.Tg, Pg, Ig))
+    replay_graph(lambda: plan.run(w.Tg, Pg, Ig),
+                 lambda: bool(torch.equal(Pg, out32[0]) and torch.equal(Ig, out32[1])), result, ms32, args)
+    result["config"]["series"] = len(wl["rb"].series)
+
+
+def post_diff(w, args, result, out32, ms32):
+    """The same forward + backward step captured once and replayed: dL/dP = 1
+    comes from a static ones tensor (torch's multi-block sum would put a
+    memset into the graph), outputs and gradient are static."""
+    import torch
+    import paper_1904_12626_amd as mpx
+    plan = w.plans["f32"]
+    ones = torch.ones_like(out32[0])
+    xs = w.Tg.clone().requires_grad_(True)
+    eager_on_side_stream(lambda: mpx.MatrixProfileFn.apply(xs, plan)[0].backward(ones))
+    xs.grad = None
+    out = {}
+
+    def capture():
+        out["P"], out["I"] = mpx.MatrixProfileFn.apply(xs, plan)
+        out["P"].backward(ones)
+    replay_graph(capture, lambda: bool(torch.equal(out["P"], out32[0]) and torch.equal(out["I"], out32[1])
+                                       and torch.equal(xs.grad, out32[2])), result, ms32, args)
+    result["config"]["note"] = ("value counts forward cells per second of forward+backward steps, "
+                                "replayed as one captured graph")
+
+
+def post_md(w, wl, result, sweep32):
+    """Multidimensional joins: their own algorithmic VALU operations per cell."""
+    D = wl["T"].shape[0]
+    ops = 5 * D + 2 if wl["mode"] == "simple" else 6 * D + D * (D - 1) + 4 * D
+    ach = w.cells * ops / (sweep32 / 1e3) / 1e12
+    result["dtype"] = "f64"
+    result["config"]["workload"] = wl["desc"] + "; FP64 cross products, float candidate keys, FP64 recompute of P"
+    result["config"]["dims"] = D
+    result["roofline"].update({"achieved": ach, "frac": ach / (PEAK_LANE_OPS / 1e12), "kernel": "k_md_sweep",
+                               "ops_per_cell": ops, "traffic": None})
+
+
+def post_lr(result, out32):
+    ch = out32[4]
+    result["config"]["longest_chain"] = len(ch["best"])
+    result["config"]["chains_min3"] = ch["count"]
+    result["config"]["boundaries"] = [int(v) for v in out32[3].cpu().tolist()]
+
+
+def post_anytime(w, wl, args, result):
+    """Convergence of the best-so-far profile towards the exact one as more
+    chunks (in one fixed random order) are included."""
+    import torch
+    import paper_1904_12626_amd as mpx
+    m, n = w.m, w.n
+    tol = 1e-3 * np.sqrt(m)
+    Pfull, _ = w.anytime_plan(1.0).run(w.Tg)
+    Pfull = Pfull.double().cpu().numpy()
+    planted = wl["planted"].motif_pairs
+    conv = []
+    for frac in (0.01, 0.02, 0.05, 0.1, 0.25, 0.5, 1.0):
+        plan = w.anytime_plan(frac)
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
-        Po, Io = cimpl.selfjoin_rows(T64, m, ez, rows)
-        dt = time.perf_counter() - t0
-        pairs = int(sum(l - (min(l - 1, r + ez) - max(0, r - ez) + 1) for r in rows))
-        P32 = out32[0].double().cpu().numpy()[rows]
-        I32 = out32[1].cpu().numpy()[rows]
-        result["cpu_baseline"] = {
-            "value": pairs / dt, "unit": "cells/s", "cores": threads, "kind": "oracle",
-            "sample": f"{rows.size} full rows of the same self-join ({args.cpu_rows} random + the planted motif "
-                      f"members and discords), {pairs} pairs, each O(m) in FP64, {dt:.1f} s",
-        }
-        tol = 1e-3 * np.sqrt(m)
-        dP = float(np.max(np.abs(P32 - Po)))
-        result["oracle_check"] = {
-            "rows": int(rows.size),
-            "max_abs_dP_f32_vs_oracle": dP,
-            "index_agreement": float(np.mean(I32 == Io)),
-            "tolerance": tol,
-        }
-        ok = dP <= tol
-        if not args.no_fp64:
-            P64r = out64[0].double().cpu().numpy()[rows]
-            result["oracle_check"]["max_abs_dP_f64_vs_oracle"] = float(np.max(np.abs(P64r - Po)))
-            ok = ok and result["fp64_path"]["max_abs_dP_f32_vs_f64"] <= tol
-        result["oracle_check"]["pass"] = bool(ok)
-    if args.cpu_rows > 0 and wl["kind"] == "anytime":
-        from oracle import cimpl
-        plan = anytime_plan(args.fraction)
-        l = n - m + 1
-        allowed = np.zeros(l, dtype=bool)
-        for c in plan.chunks:
-            allowed[ez + 1 + c * cwidth:min(ez + (c + 1) * cwidth, l - 1) + 1] = True
-        rng = np.random.default_rng(0)
-        rows = np.sort(rng.choice(l, args.cpu_rows, replace=False)).astype(np.int64)
-        T64 = T.astype(np.float64)
-        t0 = time.perf_counter()
-        Po, Io = cimpl.selfjoin_rows_restricted(T64, m, ez, rows, allowed)
-        dt = time.perf_counter() - t0
-        ks = np.nonzero(allowed)[0]
-        pairs = int(sum(np.count_nonzero(r - ks >= 0) + np.count_nonzero(r + ks < l) for r in rows))
-        result["cpu_baseline"] = {
-            "value": pairs / dt, "unit": "cells/s", "cores": cimpl.max_threads(), "kind": "oracle",
-            "sample": f"{rows.size} random rows of the same chunk-restricted self-join, {pairs} pairs, "
-                      f"each O(m) in FP64, {dt:.1f} s"}
-        result["oracle_check"] = {
-            "rows": int(rows.size),
-            "max_abs_dP_f32_vs_oracle": float(np.max(np.abs(out32[0].double().cpu().numpy()[rows] - Po))),
-            "index_agreement": float(np.mean(out32[1].cpu().numpy()[rows] == Io)),
-        }
-    if args.cpu_rows > 0 and wl["kind"] == "md":
-        from oracle import mp_oracle as O
-        T64 = wl["T"].astype(np.float64)
-        D, n = T64.shape
-        l = n - m + 1
-        rng = np.random.default_rng(0)
-        rows = np.sort(rng.choice(l, max(4, args.cpu_rows // 16), replace=False))
-        t0 = time.perf_counter()
-        if wl["mode"] == "simple":
-            Po, Io = O.simple_join(T64, m, ez, rows=rows)
-            Po, Io = Po[rows], Io[rows]
-            Pg = out32[0].double().cpu().numpy()[rows]
-        else:
-            Po, Io = O.mstomp(T64, m, ez, rows=rows)
-            Po, Io = Po[:, rows], Io[:, rows]
-            Pg = out32[0].double().cpu().numpy()[:, rows]
-        dt = time.perf_counter() - t0
-        pairs = int(sum(l - (min(l - 1, r + ez) - max(0, r - ez) + 1) for r in rows))
-        result["cpu_baseline"] = {
-            "value": pairs / dt, "unit": "cells/s", "cores": 1, "kind": "oracle",
-            "sample": f"{rows.size} full rows of the same join (numpy, {D} dimensions), {pairs} pairs, {dt:.1f} s"}
-        result["oracle_check"] = {"rows": int(rows.size),
-                                  "max_rel_dP_vs_oracle": float(np.max(np.abs(Pg - Po) / np.maximum(1.0, Po)))}
-    if args.cpu_rows > 0 and wl["kind"] == "ab":
-        from oracle import cimpl
-        rng = np.random.default_rng(0)
-        A64, B64 = wl["A"].astype(np.float64), wl["B"].astype(np.float64)
-        lA, lB = A64.size - m + 1, B64.size - m + 1
-        ra = np.sort(rng.choice(lA, args.cpu_rows // 2, replace=False))
-        rb_ = np.sort(rng.choice(lB, args.cpu_rows // 2, replace=False))
-        t0 = time.perf_counter()
-        Pa, Ia = cimpl.abjoin_rows(A64, B64, m, ra)
-        Pb, Ib = cimpl.abjoin_rows(B64, A64, m, rb_)
-        dt = time.perf_counter() - t0
-        pairs = int(ra.size * lB + rb_.size * lA)
-        result["cpu_baseline"] = {
-            "value": pairs / dt, "unit": "cells/s", "cores": cimpl.max_threads(), "kind": "oracle",
-            "sample": f"{ra.size} rows of P_ab and {rb_.size} rows of P_ba, {pairs} pairs, each O(m) in FP64, "
-                      f"{dt:.1f} s"}
-        result["oracle_check"] = {
-            "rows": int(ra.size + rb_.size),
-            "max_abs_dP_f32_vs_oracle": float(max(np.max(np.abs(out32[0].double().cpu().numpy()[ra] - Pa)),
-                                                  np.max(np.abs(out32[2].double().cpu().numpy()[rb_] - Pb)))),
-        }
+        P, I = plan.run(w.Tg)
+        idx, _ = mpx.recheck(w.Tg, m, P, I, 8, 0)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        Ph = P.double().cpu().numpy()
+        fin = np.isfinite(Pfull)
+        found = [tuple(sorted(p)) for p in idx.cpu().numpy()[:16].reshape(8, 2)]
+        hits = sum(any(abs(a - x) <= m // 8 and abs(b - y) <= m // 8 for x, y in found) for a, b in planted)
+        conv.append({"fraction_of_chunks": plan.cells / mpx.selfjoin_cells(n, m, w.ez), "chunks": len(plan.chunks),
+                     "ms": ms, "rows_within_tol_of_exact": float(np.mean(np.abs(Ph[fin] - Pfull[fin]) <= tol)),
+                     "mean_excess_over_exact": float(np.mean(Ph[fin] - Pfull[fin])),
+                     "planted_pairs_in_top8_motifs": int(hits)})
+        log(f"[bench] anytime {conv[-1]}")
+    result["convergence"] = conv
+    result["config"]["chunk_width"] = w.cwidth
+    result["config"]["chunks_total"] = w.nchunk
+    result["config"]["chunks_timed"] = len(w.anytime_plan(args.fraction).chunks)
+
+
+def fp64_leg(w, args, result, out32, ms32):
+    """The FP64 GPU path of a self-join or AB-join: 3 warm-ups, then the
+    median of at least 5 event-timed steps, and the FP32 path's agreement
+    with it.  Returns its last output."""
+    import paper_1904_12626_amd as mpx
+    m, cells = w.m, w.cells
+    out64, ms64, _ = ev_steps(lambda: w.step("f64"), max(5, min(args.steps, 8)), 3)
+    sweep64, _ = lib_sweep_ms(lambda: w.step("f64"), 3)
+    log(f"[bench] f64: {ms64:.2f} ms/step (median), sweep {sweep64:.2f} ms")
+    P32, I32 = out32[0].double().cpu().numpy(), out32[1].cpu().numpy()
+    P64, I64 = out64[0].double().cpu().numpy(), out64[1].cpu().numpy()
+    if w.kind == "ab":   # both directions
+        P32 = np.concatenate([P32, out32[2].double().cpu().numpy()])
+        I32 = np.concatenate([I32, out32[3].cpu().numpy()])
+        P64 = np.concatenate([P64, out64[2].double().cpu().numpy()])
+        I64 = np.concatenate([I64, out64[3].cpu().numpy()])
+    fin = np.isfinite(P64)
+    raw = None
+    if w.kind == "self":
+        Praw, _ = mpx.selfjoin(w.Tg, m, w.ez, precision="f32", fp64_finalize=False)
+        raw = float(np.max(np.abs(Praw.double().cpu().numpy()[fin] - P64[fin])))
+    result["fp64_path"] = {
+        "value": cells / (ms64 / 1e3), "ms_per_step": ms64, "sweep_ms_per_launch": sweep64,
+        "speedup_f32_over_f64": ms64 / ms32, "steps": max(5, min(args.steps, 8)), "warmup": 3,
+        "timing": "median of event-timed steps",
+        "max_abs_dP_f32_vs_f64": float(np.max(np.abs(P32[fin] - P64[fin]))),
+        "max_abs_dP_f32_raw_vs_f64": raw,
+        "index_agreement_f32_vs_f64": float(np.mean(I32 == I64)),
+        "tolerance": 1e-3 * np.sqrt(m),
+        "roofline": roofline_of(cells, sweep64, "k_sweep<double>", "f64"),
+    }
+    return out64
+
+
+def cpu_leg_self(w, wl, args, result, out32, out64):
+    """The oracle on sampled full rows of the same self-join (random rows plus
+    the planted ones), timed, and the GPU rows checked against it."""
+    from oracle import cimpl
+    m, ez, n = w.m, w.ez, w.n
+    rng = np.random.default_rng(0)
+    l = n - m + 1
+    rows = list(rng.choice(l, args.cpu_rows, replace=False))
+    if wl["planted"] is not None:
+        for a, b in wl["planted"].motif_pairs:
+            rows += [a, b]
+        rows += list(wl["planted"].discords)
+    rows = np.array(sorted(set(int(r) for r in rows)), dtype=np.int64)
+    T64 = w.T.astype(np.float64)
+    threads = cimpl.max_threads()
+    t0 = time.perf_counter()
+    Po, Io = cimpl.selfjoin_rows(T64, m, ez, rows)
+    dt = time.perf_counter() - t0
+    pairs = int(sum(l - (min(l - 1, r + ez) - max(0, r - ez) + 1) for r in rows))
+    P32 = out32[0].double().cpu().numpy()[rows]
+    I32 = out32[1].cpu().numpy()[rows]
+    result["cpu_baseline"] = {
+        "value": pairs / dt, "unit": "cells/s", "cores": threads, "kind": "oracle",
+        "sample": f"{rows.size} full rows of the same self-join ({args.cpu_rows} random + the planted motif "
+                  f"members and discords), {pairs} pairs, each O(m) in FP64, {dt:.1f} s",
+    }
+    tol = 1e-3 * np.sqrt(m)
+    dP = float(np.max(np.abs(P32 - Po)))
+    result["oracle_check"] = {
+        "rows": int(rows.size),
+        "max_abs_dP_f32_vs_oracle": dP,
+        "index_agreement": float(np.mean(I32 == Io)),
+        "tolerance": tol,
+    }
+    ok = dP <= tol
+    if out64 is not None:
+        P64r = out64[0].double().cpu().numpy()[rows]
+        result["oracle_check"]["max_abs_dP_f64_vs_oracle"] = float(np.max(np.abs(P64r - Po)))
+        ok = ok and result["fp64_path"]["max_abs_dP_f32_vs_f64"] <= tol
+    result["oracle_check"]["pass"] = bool(ok)
+
+
+def cpu_leg_anytime(w, args, result, out32):
+    """The oracle restricted to the timed chunk set, on sampled rows."""
+    from oracle import cimpl
+    m, ez, n = w.m, w.ez, w.n
+    plan = w.anytime_plan(args.fraction)
+    l = n - m + 1
+    allowed = np.zeros(l, dtype=bool)
+    for c in plan.chunks:
+        allowed[ez + 1 + c * w.cwidth:min(ez + (c + 1) * w.cwidth, l - 1) + 1] = True
+    rng = np.random.default_rng(0)
+    rows = np.sort(rng.choice(l, args.cpu_rows, replace=False)).astype(np.int64)
+    T64 = w.T.astype(np.float64)
+    t0 = time.perf_counter()
+    Po, Io = cimpl.selfjoin_rows_restricted(T64, m, ez, rows, allowed)
+    dt = time.perf_counter() - t0
+    ks = np.nonzero(allowed)[0]
+    pairs = int(sum(np.count_nonzero(r - ks >= 0) + np.count_nonzero(r + ks < l) for r in rows))
+    result["cpu_baseline"] = {
+        "value": pairs / dt, "unit": "cells/s", "cores": cimpl.max_threads(), "kind": "oracle",
+        "sample": f"{rows.size} random rows of the same chunk-restricted self-join, {pairs} pairs, "
+                  f"each O(m) in FP64, {dt:.1f} s"}
+    result["oracle_check"] = {
+        "rows": int(rows.size),
+        "max_abs_dP_f32_vs_oracle": float(np.max(np.abs(out32[0].double().cpu().numpy()[rows] - Po))),
+        "index_agreement": float(np.mean(out32[1].cpu().numpy()[rows] == Io)),
+    }
+
+
+def cpu_leg_md(w, wl, args, result, out32):
+    """The numpy oracle of the multidimensional join on a few sampled rows."""
+    from oracle import mp_oracle as O
+    m, ez = w.m, w.ez
+    T64 = wl["T"].astype(np.float64)
+    D, n = T64.shape
+    l = n - m + 1
+    rng = np.random.default_rng(0)
+    rows = np.sort(rng.choice(l, max(4, args.cpu_rows // 16), replace=False))
+    t0 = time.perf_counter()
+    if wl["mode"] == "simple":
+        Po, Io = O.simple_join(T64, m, ez, rows=rows)
+        Po, Io = Po[rows], Io[rows]
+        Pg = out32[0].double().cpu().numpy()[rows]
+    else:
+        Po, Io = O.mstomp(T64, m, ez, rows=rows)
+        Po, Io = Po[:, rows], Io[:, rows]
+        Pg = out32[0].double().cpu().numpy()[:, rows]
+    dt = time.perf_counter() - t0
+    pairs = int(sum(l - (min(l - 1, r + ez) - max(0, r - ez) + 1) for r in rows))
+    result["cpu_baseline"] = {
+        "value": pairs / dt, "unit": "cells/s", "cores": 1, "kind": "oracle",
+        "sample": f"{rows.size} full rows of the same join (numpy, {D} dimensions), {pairs} pairs, {dt:.1f} s"}
+    result["oracle_check"] = {"rows": int(rows.size),
+                              "max_rel_dP_vs_oracle": float(np.max(np.abs(Pg - Po) / np.maximum(1.0, Po)))}
+
+
+def cpu_leg_ab(w, wl, args, result, out32):
+    """The oracle on sampled rows of both directions of the AB-join."""
+    from oracle import cimpl
+    m = w.m
+    rng = np.random.default_rng(0)
+    A64, B64 = wl["A"].astype(np.float64), wl["B"].astype(np.float64)
+    lA, lB = A64.size - m + 1, B64.size - m + 1
+    ra = np.sort(rng.choice(lA, args.cpu_rows // 2, replace=False))
+    rb_ = np.sort(rng.choice(lB, args.cpu_rows // 2, replace=False))
+    t0 = time.perf_counter()
+    Pa, Ia = cimpl.abjoin_rows(A64, B64, m, ra)
+    Pb, Ib = cimpl.abjoin_rows(B64, A64, m, rb_)
+    dt = time.perf_counter() - t0
+    pairs = int(ra.size * lB + rb_.size * lA)
+    result["cpu_baseline"] = {
+        "value": pairs / dt, "unit": "cells/s", "cores": cimpl.max_threads(), "kind": "oracle",
+        "sample": f"{ra.size} rows of P_ab and {rb_.size} rows of P_ba, {pairs} pairs, each O(m) in FP64, "
+                  f"{dt:.1f} s"}
+    result["oracle_check"] = {
+        "rows": int(ra.size + rb_.size),
+        "max_abs_dP_f32_vs_oracle": float(max(np.max(np.abs(out32[0].double().cpu().numpy()[ra] - Pa)),
+                                              np.max(np.abs(out32[2].double().cpu().numpy()[rb_] - Pb)))),
+    }
+
+
+def main():
+    args = parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}, "
+              f"WORLD_SIZE={world}); the self-join would shard by diagonal ranges with one min-reduction "
+              "of the packed keys (see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    dev = torch.device("cuda:0")
+    if args.copy_calib_mib > 0:
+        copy_calibration(args.copy_calib_mib, dev)
+    wl = workload(args.workload, args.n)
+    w = setup(wl, args, dev)
+    if args.autotune and w.kind in ("self", "ab", "batch"):
+        autotune(w, wl, args)
+    log(f"[bench] workload: {wl['desc']}; cells={w.cells}")
+    if w.kind == "stream":
+        print(json.dumps(run_stream(w, wl, args)), flush=True)
+        return
+
+    out32, ms32, med32, sweep32, tot32 = timed(w.step, "f32", args.steps, args.warmup)
+    log(f"[bench] f32: {ms32:.2f} ms/step, sweep {sweep32:.2f} ms, launch sequence {tot32:.2f} ms")
+    result = fp32_result(w, wl, args, ms32, med32, sweep32)
+    if w.kind == "batch":
+        post_batch(w, wl, args, result, out32, ms32, dev)
+    elif w.kind == "diff":
+        post_diff(w, args, result, out32, ms32)
+    elif w.kind == "md":
+        post_md(w, wl, result, sweep32)
+    elif w.kind == "lr":
+        post_lr(result, out32)
+    elif w.kind == "anytime":
+        post_anytime(w, wl, args, result)
+
+    out64 = None
+    if not args.no_fp64 and w.kind in ("self", "ab"):
+        out64 = fp64_leg(w, args, result, out32, ms32)
+    if args.cpu_rows > 0:
+        if w.kind == "self":
+            cpu_leg_self(w, wl, args, result, out32, out64)
+        elif w.kind == "anytime":
+            cpu_leg_anytime(w, args, result, out32)
+        elif w.kind == "md":
+            cpu_leg_md(w, wl, args, result, out32)
+        elif w.kind == "ab":
+            cpu_leg_ab(w, wl, args, result, out32)
     if "cpu_baseline" in result:
         result["cpu_baseline"]["host"] = host_cpu()
     if (args.workload == "selfjoin_large" and not args.no_workloads and args.n is None and not args.slots
@@ -1059,7 +1143,7 @@ def main():
         if vc is not None:
             result["roofline"]["ceilings"] = ceilings(vc, result["roofline"]["sweep_cells_per_s"],
                                                       result.get("fp64_path", {}).get("sweep_ms_per_launch"),
-                                                      cells)
+                                                      w.cells)
         result["workloads"] = extra_workloads(max(5, min(args.steps, 20)), 3, dev, log)
     print(json.dumps(result), flush=True)
 
