@@ -342,7 +342,7 @@ __global__ void __launch_bounds__(64, (SweepMinWaves<F, DT>::value))
       // dword 66 r + 2 q: banks 2 (r + q) mod 64) touch distinct banks with
       // every address an immediate offset from the lane's row.  Lane 0's
       // column minimum rides in the spare slot of the entering-column
-      // record.  10 KB of LDS per wave.
+      // record.  10.5 KB of LDS per wave.
       static_assert(TP <= 32, "row-rotated partials");
       __shared__ double lrec[TP][4];   // a_i, g_i, s_i, u_i of row sb + u
       __shared__ double lent[TP][4];   // a, g, s of the column entering after row sb + u;
