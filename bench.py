@@ -545,7 +545,9 @@ def parse_args():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU path comparison")
     ap.add_argument("--autotune", action="store_true",
                     help="pick tile slots and reseed rows with the autotuner before timing (search logged)")
-    ap.add_argument("--cpu-rows", type=int, default=256, help="oracle rows timed for the CPU baseline (0 = skip)")
+    ap.add_argument("--cpu-rows", type=int, default=600,
+                    help="random oracle rows timed for the CPU baseline, about 10-30 s of host work on the default "
+                         "workload (0 = skip)")
     ap.add_argument("--no-workloads", action="store_true",
                     help="default workload only: skip the records of the other workloads")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
