@@ -1091,7 +1091,7 @@ def main():
     args = parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}, "
+        print(f"bench.py measures one GPU: the library has no multi-GPU path (asked for --gpus {args.gpus}, "
               f"WORLD_SIZE={world}); the self-join would shard by diagonal ranges with one min-reduction "
               "of the packed keys (see the design notes)", file=sys.stderr)
         sys.exit(2)

@@ -71,7 +71,7 @@ typedef enum {
   MP_EINVAL = -1,        /* bad size, pointer, alignment or option      */
   MP_EWORKSPACE = -2,    /* workspace null, misaligned or too small     */
   MP_ELAUNCH = -3,       /* a kernel launch failed                      */
-  MP_EUNSUPPORTED = -4,  /* valid request this build does not support   */
+  MP_EUNSUPPORTED = -4,  /* valid request the library does not support  */
   MP_ETOOLARGE = -5      /* job exceeds the fixed scratch of
                             mp_selfjoin_noalloc                         */
 } mp_status;
