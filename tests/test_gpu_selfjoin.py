@@ -267,3 +267,17 @@ def test_joins_in_flight_on_two_streams():
         assert torch.equal(PB, PB0) and torch.equal(IB, IB0)
     Po, Io = cimpl.selfjoin(TB, 64, 16)
     compare_profile(TB, 64, PB0.cpu().numpy(), IB0.cpu().numpy(), Po, Io, 1e-9, ez=16, where="two streams")
+
+
+@pytest.mark.parametrize("scale", [1e-18, 1e-10, 1e10, 1e18, 1e19])
+def test_scale_invariance_fp32(scale):
+    """The z-normalised profile does not depend on the scale of the series.
+    The FP32 sweep carries raw cross products (about m sigma^2), so this
+    checks both ends of its range: tiny scales stay in FP32's normal range,
+    and at 1e19 the cross products overflow, every key is non-finite and
+    every row is re-found by the exact FP64 rescan."""
+    T = random_walk(3000, 43, np.float64)
+    m, ez = 64, 16
+    P, I = _run(T * scale, m, ez, "f32")
+    Po, Io = cimpl.selfjoin(T, m, ez)
+    compare_profile(T, m, P, I, Po, Io, 1e-3 * np.sqrt(m), ez=ez, where=f"scale {scale:g}")
