@@ -84,12 +84,10 @@ typedef enum {
 /* precision of the diagonal sweep */
 #define MP_PREC_F64 0    /* FP64 sweep (the reference GPU path)          */
 #define MP_PREC_F32 1    /* FP32 sweep, FP64 stats/seeds, reseeded       */
-/* The FP32 sweep carries cross products of about m * sigma^2 (sigma: a
- * window's standard deviation) in FP32, so it suits series whose windows
- * have sigma between about 1e-19 and 1e18.  Below that its keys lose
- * precision; above it they overflow, and every row is then re-found by an
- * exact FP64 scan, O(l * m) per row: the result stays exact, the cost
- * grows to O(l^2 * m).  Outside that range use MP_PREC_F64. */
+/* The FP32 sweep carries cross products of windows in FP32; each series'
+ * records are scaled by a power of two chosen from its samples, so series of
+ * any magnitude that FP64 holds stay inside FP32's range (the keys are the
+ * same as without the scaling). */
 
 /* flags */
 #define MP_FLAG_FP64_FINALIZE 1u  /* recompute P[i] = dist(i, I[i]) in FP64 */

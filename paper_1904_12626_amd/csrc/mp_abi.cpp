@@ -166,7 +166,7 @@ void finish_job(Job &j) {
 }
 
 struct Layout {
-  size_t mu, sig, keys, flags, nc, nv, rc, special, counters, segp, segs, segq, rescan, sdesc, wdesc, kmask;
+  size_t mu, sig, keys, flags, nc, nv, rc, special, scale, counters, segp, segs, segq, rescan, sdesc, wdesc, kmask;
   size_t b_mu, b_isig, b_nbr, b_wrec, b_alpha, b_wsc, b_bedge, b_bgam, b_bpos, b_count, b_off, b_tmp, b_erec, b_egam,
       b_chunk, b_big,
       b_nbig;
@@ -190,6 +190,7 @@ Layout layout_of(const Job &j, bool with_batch_tables) {
   L.nv = take(4 * (size_t)j.total_x);
   L.rc = take((j.opt.f64 ? 32 : 16) * (size_t)j.total_rc);
   L.special = take(4 * j.series.size());
+  L.scale = take(8 * j.series.size());
   L.counters = take(8 * 4);
   L.segp = take(8 * ((size_t)j.nseg + 1));
   L.segs = take(4 * std::max<size_t>(1, (size_t)j.nseg));
@@ -232,6 +233,7 @@ mpx::Work work_of(const Layout &L, void *ws) {
   w.next_valid = (int32_t *)(b + L.nv);
   w.rc = (void *)(b + L.rc);
   w.special = (int32_t *)(b + L.special);
+  w.scale = (double *)(b + L.scale);
   w.counters = (unsigned long long *)(b + L.counters);
   w.seg_prefix = (int64_t *)(b + L.segp);
   w.seg_sweep = (int32_t *)(b + L.segs);

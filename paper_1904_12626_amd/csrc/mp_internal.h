@@ -88,6 +88,7 @@ struct Work {
   int32_t *next_valid; // [total_x] smallest valid window >= x (l if none)
   void *rc;            // [total_rc] row/column data {a, g, s, u} (F4)
   int32_t *special;    // [nseries] bit0 has invalid windows, bit1 has constant
+  double *scale;       // [nseries] power of two the series' sweep records carry
   unsigned long long *counters;  // [4]: 0 tile counter, 1 rescan count
   int64_t *seg_prefix; // [nseg + 1] first tile of each strip; with seg_part,
                        // the full-height tiles before each strip

@@ -100,6 +100,30 @@ hipError_t launch_plan(const Plan &plan, const Work &w, int W, int R, int64_t ns
 // obeys C(i+1,j+1) = C(i,j) + a_j g_i + a_i g_j exactly (expand
 // x[i+m] = x[i] + a_i and mu_{i+1} = mu_i + a_i/m), and the sweep's key
 // u_i - C s_i s_j equals 1 - rho(i,j) for valid windows.
+// The records store a and g times the series' power of two k and s divided
+// by it (the sweep multiplies its seeds of C by the k of both series): no key
+// changes, since power-of-two factors commute with rounding, but the cross
+// products of series with very large or very small values stay well inside
+// FP32's range.
+
+// The power of two that brings the spread of 32 evenly spaced samples of a
+// series (their largest distance from the first finite one) into [1, 2);
+// 1 when they do not spread.  Every thread that asks gets the same value.
+template <typename Tin>
+__device__ double series_scale(const Tin *x, int64_t n) {
+  double ref = 0.0, spread = 0.0;
+  bool have = false;
+  for (int k = 0; k < 32; ++k) {
+    const double v = (double)x[(n - 1) * k / 31];
+    if (!isfinite(v)) continue;
+    if (!have) {
+      ref = v;
+      have = true;
+    }
+    spread = fmax(spread, fabs(v - ref));
+  }
+  return (spread > 0.0 && isfinite(spread)) ? ldexp(1.0, -ilogb(spread)) : 1.0;
+}
 // Series owning padded row/column entry r.
 __device__ __forceinline__ int series_of_rc(const Plan &plan, int64_t r) {
   if (plan.s_ext) {
@@ -122,6 +146,7 @@ template <typename F, typename Tin>
 __global__ void __launch_bounds__(256) k_stats(Plan plan, Work w, const Tin *__restrict__ Tb,
                                                int64_t total_rc) {
   __shared__ Tin xs[kStatsTile + kStatsTileM + 1];
+  __shared__ double tile_scale;
   const int64_t r0 = (int64_t)blockIdx.x * kStatsTile;
   const int64_t r = r0 + threadIdx.x;
   const int s0 = series_of_rc(plan, r0);
@@ -133,6 +158,7 @@ __global__ void __launch_bounds__(256) k_stats(Plan plan, Work w, const Tin *__r
     const int cnt = (int)min((int64_t)(kStatsTile + S0.m), S0.n - i0);
     for (int t = threadIdx.x; t < cnt; t += blockDim.x) xs[t] = base[t];
   }
+  if (tiled && threadIdx.x == 0) tile_scale = series_scale(series_samples(plan, Tb, S0), S0.n);
   __syncthreads();
   if (r >= total_rc) return;
   const int si = tiled ? s0 : series_of_rc(plan, r);
@@ -212,12 +238,14 @@ __global__ void __launch_bounds__(256) k_stats(Plan plan, Work w, const Tin *__r
   const double g = (x0 - mu) + a * ((double)(m - 1) / (2.0 * m));
   const double sc = (fin && !cst && sig > 0.0) ? 1.0 / (sqrt((double)m) * sig) : 0.0;
   const double uu = fin ? (cst ? 0.5 : 1.0) : 4.0;
+  const double k = tiled ? tile_scale : series_scale(series_samples(plan, Tb, S), S.n);
+  if (i == 0) w.scale[si] = k;
   const int64_t wi = S.w_off + i;
   w.mu[wi] = mu;
   w.sig[wi] = sig;
   w.flags[wi] = (uint8_t)((fin ? 1 : 0) | (cst ? 2 : 0));
   w.keys[wi] = ~0ull;
-  rc[r] = FTraits<F>::make4(a, g, sc, uu);
+  rc[r] = FTraits<F>::make4(a * k, g * k, sc / k, uu);
   const int bits = (fin ? 0 : 1) | (cst ? 2 : 0);
   if (bits) atomicOr(&w.special[si], bits);
 }

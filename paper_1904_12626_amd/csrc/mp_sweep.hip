@@ -208,7 +208,7 @@ __global__ void __launch_bounds__(64, (SweepMinWaves<F, DT>::value))
             const double *__restrict__ mu, const int64_t *__restrict__ seg_prefix,
             const int32_t *__restrict__ seg_sweep, const int64_t *__restrict__ seg_part,
             const SeriesDesc *__restrict__ s_ext,
-            const SweepDesc *__restrict__ w_ext, uint64_t *__restrict__ keys,
+            const SweepDesc *__restrict__ w_ext, const double *__restrict__ scale, uint64_t *__restrict__ keys,
             unsigned long long *__restrict__ counter, const Tin *__restrict__ Tb, const int R,
             const int64_t total_tiles, const int64_t nseg) {
   constexpr int W = 64 * DT;
@@ -291,10 +291,12 @@ __global__ void __launch_bounds__(64, (SweepMinWaves<F, DT>::value))
           for (int t = 0; t < DT; ++t) acc[t] = fma(xr[(u - t + DT) % DT], y, acc[t]);
         }
       }
+      // the records carry each series' power of two (see k_stats)
+      const double kk = ldu(scale + d.rs) * ldu(scale + d.cs);
 #pragma unroll
       for (int t = 0; t < DT; ++t) {
         const int64_t cw = min(c0 + t, lc - 1);
-        C[t] = (F)(acc[t] - mu[CS.w_off + cw] * Sx);
+        C[t] = (F)((acc[t] - mu[CS.w_off + cw] * Sx) * kk);
       }
     }
 
@@ -560,7 +562,7 @@ hipError_t launch_sweep(const Plan &plan, const Work &w, const void *T, bool t_f
                      (const typename FTraits<F>::V4 *)w.rc, (const double *)w.mu,              \
                      (const int64_t *)w.seg_prefix, (const int32_t *)w.seg_sweep,               \
                      (const int64_t *)w.seg_part, plan.s_ext,                                  \
-                     plan.w_ext, w.keys, w.counters, (const TIN *)T, R, total_tiles, nseg)
+                     plan.w_ext, w.scale, w.keys, w.counters, (const TIN *)T, R, total_tiles, nseg)
   if (f64_sweep) {
     if (t_f64) MPX_LAUNCH(double, double, 8, 32);
     else MPX_LAUNCH(double, float, 8, 32);

@@ -272,10 +272,9 @@ def test_joins_in_flight_on_two_streams():
 @pytest.mark.parametrize("scale", [1e-18, 1e-10, 1e10, 1e18, 1e19])
 def test_scale_invariance_fp32(scale):
     """The z-normalised profile does not depend on the scale of the series.
-    The FP32 sweep carries raw cross products (about m sigma^2), so this
-    checks both ends of its range: tiny scales stay in FP32's normal range,
-    and at 1e19 the cross products overflow, every key is non-finite and
-    every row is re-found by the exact FP64 rescan."""
+    The FP32 sweep's cross products (about m sigma^2 unscaled) would leave
+    FP32's range at both ends; each series' records carry a power of two
+    that keeps them near 1."""
     T = random_walk(3000, 43, np.float64)
     m, ez = 64, 16
     P, I = _run(T * scale, m, ez, "f32")
