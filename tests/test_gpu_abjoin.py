@@ -77,3 +77,18 @@ def test_abjoin_degenerate_windows():
     Po, Io, Po2, Io2 = O.abjoin(A, B, m)
     compare_profile(A, m, Pab, Iab, Po, Io, 1e-9, TB=B)
     compare_profile(B, m, Pba, Iba, Po2, Io2, 1e-9, TB=A)
+
+
+def test_abjoin_series_of_opposite_magnitudes():
+    """Each series' sweep records carry their own power of two, and a tile's
+    seeds carry the product of both: an AB-join of a series times 1e19 with
+    one times 1e-15 gives the oracle's profiles of the unscaled pair."""
+    A = random_walk(3000, 51, np.float64)
+    B = random_walk(2600, 52, np.float64)
+    m = 64
+    Pab, Iab, Pba, Iba = _run(A * 1e19, B * 1e-15, m, "f32")
+    tol = 1e-3 * np.sqrt(m)
+    Po, Io = cimpl.abjoin_rows(A, B, m, np.arange(A.size - m + 1))
+    compare_profile(A, m, Pab, Iab, Po, Io, tol, TB=B, where="ab scaled")
+    Po, Io = cimpl.abjoin_rows(B, A, m, np.arange(B.size - m + 1))
+    compare_profile(B, m, Pba, Iba, Po, Io, tol, TB=A, where="ba scaled")
