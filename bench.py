@@ -884,7 +884,7 @@ def post_md(w, wl, result, sweep32):
     ops = 5 * D + 2 if wl["mode"] == "simple" else 6 * D + D * (D - 1) + 4 * D
     ach = w.cells * ops / (sweep32 / 1e3) / 1e12
     result["dtype"] = "f64"
-    result["config"]["workload"] = wl["desc"] + "; FP64 cross products, float candidate keys, FP64 recompute of P"
+    result["config"]["workload"] = wl["desc"] + "; FP64 cross products, 32-bit candidate keys, FP64 recompute of P"
     result["config"]["dims"] = D
     result["roofline"].update({"achieved": ach, "frac": ach / (PEAK_LANE_OPS / 1e12), "kernel": "k_md_sweep",
                                "ops_per_cell": ops, "traffic": None})

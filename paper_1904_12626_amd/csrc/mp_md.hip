@@ -60,9 +60,30 @@ __device__ __forceinline__ T ldu_md(const T *p) {
 #endif
 }
 
-__device__ __forceinline__ unsigned long long pack_md(float v, int64_t idx) {
-  v = v > 0.0f ? v : 0.0f;
-  return ((unsigned long long)__float_as_uint(v) << 32) | (unsigned long long)(uint32_t)idx;
+// Global minima are packed (32-bit value pattern << 32 | index), the
+// pattern ordered like the value it encodes (see MdKey::value).
+__device__ __forceinline__ unsigned long long pack_md(unsigned bits, int64_t idx) {
+  return ((unsigned long long)bits << 32) | (unsigned long long)(uint32_t)idx;
+}
+
+// A 32-bit pattern ordered like the non-negative double v over
+// [2^-511, 2^511): a 10-bit exponent and the top 22 bits of the mantissa.
+// Smaller values map to 0, larger ones (the huge keys of invalid windows
+// included) to the top.  SiMPle's squared distances carry the data's units,
+// so they may lie far outside float's range.
+__device__ __forceinline__ unsigned md_bits(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const int e = (int)(b >> 52) & 0x7ff;  // biased exponent
+  if (e < 1023 - 511) return 0u;
+  if (e >= 1023 + 511) return 0xffffffffu;
+  return ((unsigned)(e - 512) << 22) | (unsigned)((b >> 30) & 0x3fffffull);
+}
+
+// Patterns at or above this are not candidates: float 1e30 for the
+// k-dimensional keys (z-normalised distances are at most 2 sqrt(m) per
+// dimension), a squared distance of 2^500 for SiMPle.
+__device__ __forceinline__ unsigned md_limit(bool f32) {
+  return f32 ? __float_as_uint(1.0e30f) : ((unsigned)(1523 - 512) << 22);
 }
 
 __device__ __forceinline__ int find_series_md(const Plan &plan, int64_t wi) {
@@ -269,11 +290,16 @@ struct MdKey {
   static __device__ __forceinline__ unsigned code(double k) {
     return (unsigned)(__double_as_longlong(k) & 0xffffffffll) & kMask;
   }
-  // the value as the float that goes into the global packed minimum
-  static __device__ __forceinline__ float value(double k, bool f32) {
+  // the pattern of the value that goes into the global packed minimum: the
+  // float (negative rounding residue read as 0) or, for SiMPle's FP64 keys,
+  // md_bits (the code sits in bits md_bits drops)
+  static __device__ __forceinline__ unsigned value(double k, bool f32) {
     const long long b = __double_as_longlong(k);
-    if (f32) return __uint_as_float((unsigned)((unsigned long long)b >> 32));
-    return (float)__longlong_as_double(b & ~(long long)kMask);
+    if (f32) {
+      const float v = __uint_as_float((unsigned)((unsigned long long)b >> 32));
+      return __float_as_uint(v > 0.0f ? v : 0.0f);
+    }
+    return md_bits(__longlong_as_double(b & ~(long long)kMask));
   }
 };
 
@@ -433,15 +459,15 @@ __global__ void __launch_bounds__(64, (MdShape<D, MODE>::kMinWaves)) k_md_sweep(
     __syncthreads();
 
     auto emit_row = [&](int q, int64_t i, double kb) {
-      const float val = K::value(kb, !kSimple);
-      if (val < 1.0e30f) {
+      const unsigned val = K::value(kb, !kSimple);
+      if (val < md_limit(!kSimple)) {
         const int64_t j = i + k0 + (int64_t)K::code(kb);
         if (j < lc) atomicMin(rkeys + q * kstride + i, pack_md(val, j));
       }
     };
     auto emit_col = [&](int q, int64_t c, double kb) {
-      const float val = K::value(kb, !kSimple);
-      if (c < lc && val < 1.0e30f) {
+      const unsigned val = K::value(kb, !kSimple);
+      if (c < lc && val < md_limit(!kSimple)) {
         const int64_t i = c - k0 - (int64_t)K::code(kb);
         atomicMin(ckeys + q * kstride + c, pack_md(val, i));
       }
@@ -593,7 +619,7 @@ __global__ void __launch_bounds__(256) k_md_finalize(Plan plan, int D, const Tin
     const unsigned long long k = keys[p * kstride + wi];
     double P = INFINITY;
     int64_t idx = -1;
-    if (valid && k != ~0ull && __uint_as_float((unsigned)(k >> 32)) < 1.0e30f) {
+    if (valid && k != ~0ull && (unsigned)(k >> 32) < md_limit(MODE != kMdSimple)) {
       idx = (int64_t)(uint32_t)(k & 0xffffffffull);
       if (MODE == kMdSimple) {
         double s = 0.0;

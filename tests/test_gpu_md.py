@@ -206,3 +206,19 @@ def test_multi_hand_worked_case():
     assert np.array_equal(I[~tie], Io[~tie])
     assert I[0, 10] in (0, 5)
     assert I[1, 0] == 5 and abs(P[1, 0] - 2.0) < 1e-9
+
+
+@pytest.mark.parametrize("scale", [1e-25, 1e15, 1e19])
+def test_simple_keys_cover_any_magnitude(scale):
+    """SiMPle distances carry the data's units (P(aT) = a P(T)), and its
+    candidates are merged as 32-bit patterns of the FP64 squared distance
+    that cover 2^-511 .. 2^511, so series far outside float's range still
+    get the oracle's neighbours."""
+    import paper_1904_12626_amd as mpx
+    rng = np.random.default_rng(150)
+    n, m, ez = 1500, 24, 6
+    T = np.cumsum(rng.standard_normal((3, n)), axis=1)
+    P, I = mpx.mdjoin(torch.from_numpy(T * scale).to(DEV), m, ez, mode="simple")
+    Po, Io = O.simple_join(T, m, ez)
+    _compare(P.cpu().numpy() / scale, I.cpu().numpy(), Po, Io, lambda i, j: _simple_dist(T, i, T, j, m), 1e-6, ez,
+             f"scale {scale:g}")
