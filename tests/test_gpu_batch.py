@@ -80,3 +80,20 @@ def test_batch_float64_fp64_sweep():
     for s, (T, m, ez) in enumerate(zip(rb.series, rb.m, rb.ez)):
         Po, Io = cimpl.selfjoin(T, m, ez)
         compare_profile(T, m, Ps[s], Is[s], Po, Io, 1e-9, ez=ez)
+
+
+def test_batch_of_series_at_different_magnitudes():
+    """Series of one batch each carry their own power of two in the sweep's
+    records: a batch of walks scaled by 1e-18, 1 and 1e19 gives each series
+    the oracle's profile."""
+    import paper_1904_12626_amd as mpx
+    from workloads import random_walk
+    lens, ms, ezs, scales = [2000, 1700, 2500], [32, 48, 40], [8, 12, 10], [1e-18, 1.0, 1e19]
+    Ts = [random_walk(n, 60 + k, np.float64) for k, n in enumerate(lens)]
+    plan = mpx.BatchPlan(lens, ms, ezs, dtype=torch.float64, device=DEV)
+    P, I = plan.run(torch.from_numpy(np.concatenate([T * a for T, a in zip(Ts, scales)])).to(DEV))
+    torch.cuda.synchronize()
+    Ps, Is = plan.split(P.cpu().numpy()), plan.split(I.cpu().numpy())
+    for s, (T, m, ez) in enumerate(zip(Ts, ms, ezs)):
+        Po, Io = cimpl.selfjoin(T, m, ez)
+        compare_profile(T, m, Ps[s], Is[s], Po, Io, 1e-3 * np.sqrt(m), ez=ez, where=f"series {s}")
