@@ -107,8 +107,12 @@ hipError_t launch_plan(const Plan &plan, const Work &w, int W, int R, int64_t ns
 // FP32's range.
 
 // The power of two that brings the spread of 32 evenly spaced samples of a
-// series (their largest distance from the first finite one) into [1, 2);
-// 1 when they do not spread.  Every thread that asks gets the same value.
+// series (their largest distance from the first finite one) into
+// [2^48, 2^49); 1 when they do not spread.  A window's spread is at most
+// about that, so its cross products (m sigma^2) stay a thousand times below
+// FP32's maximum for windows up to 2^20 samples, while windows up to 10^33
+// times smaller still keep their increments above FP32's smallest normal
+// number.  Every thread that asks gets the same value.
 template <typename Tin>
 __device__ double series_scale(const Tin *x, int64_t n) {
   double ref = 0.0, spread = 0.0;
@@ -122,7 +126,7 @@ __device__ double series_scale(const Tin *x, int64_t n) {
     }
     spread = fmax(spread, fabs(v - ref));
   }
-  return (spread > 0.0 && isfinite(spread)) ? ldexp(1.0, -ilogb(spread)) : 1.0;
+  return (spread > 0.0 && isfinite(spread)) ? ldexp(1.0, 48 - ilogb(spread)) : 1.0;
 }
 // Series owning padded row/column entry r.
 __device__ __forceinline__ int series_of_rc(const Plan &plan, int64_t r) {

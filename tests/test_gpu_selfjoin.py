@@ -280,3 +280,17 @@ def test_scale_invariance_fp32(scale):
     P, I = _run(T * scale, m, ez, "f32")
     Po, Io = cimpl.selfjoin(T, m, ez)
     compare_profile(T, m, P, I, Po, Io, 1e-3 * np.sqrt(m), ez=ez, where=f"scale {scale:g}")
+
+
+def test_regimes_of_very_different_magnitude():
+    """A series whose first half moves by 1e-12 and second half by 1e10: the
+    FP32 sweep's per-series power of two leaves room for both (the small
+    windows keep their precision, the large ones do not overflow)."""
+    rng = np.random.default_rng(80)
+    n = 4000
+    T = np.concatenate([np.cumsum(rng.standard_normal(n // 2)) * 1e-12,
+                        np.cumsum(rng.standard_normal(n // 2)) * 1e10])
+    m, ez = 48, 12
+    P, I = _run(T, m, ez, "f32")
+    Po, Io = cimpl.selfjoin(T, m, ez)
+    compare_profile(T, m, P, I, Po, Io, 1e-3 * np.sqrt(m), ez=ez, where="regimes")
