@@ -128,6 +128,7 @@ __device__ double series_scale(const Tin *x, int64_t n) {
   }
   return (spread > 0.0 && isfinite(spread)) ? ldexp(1.0, 48 - ilogb(spread)) : 1.0;
 }
+
 // Series owning padded row/column entry r.
 __device__ __forceinline__ int series_of_rc(const Plan &plan, int64_t r) {
   if (plan.s_ext) {
