@@ -359,7 +359,7 @@ mp_status run_job(const Job &j, const mpx::Plan &plan, const mpx::Work &w, const
     for (auto &e : ev) e = g_timing.get();
     if (ev[0]) (void)hipEventRecord(ev[0], st);
   }
-  if (mpx::launch_plan(plan, w, j.W, j.R, j.nseg, st) != hipSuccess) return MP_ELAUNCH;
+  if (mpx::launch_plan(plan, w, T, j.t_f64, j.W, j.R, j.nseg, st) != hipSuccess) return MP_ELAUNCH;
   if (mpx::launch_stats(plan, w, T, j.t_f64, op.f64, j.total_rc, st) != hipSuccess) return MP_ELAUNCH;
   if (ev[1]) (void)hipEventRecord(ev[1], st);
   if (j.tiles > 0) {
@@ -966,7 +966,7 @@ mp_status mp_mdjoin(int32_t mode, int32_t D, const void *A, int64_t nA, const vo
     for (auto &e : ev) e = g_timing.get();
     if (ev[0]) (void)hipEventRecord(ev[0], st);
   }
-  if (mpx::launch_plan(p, w, j.W, j.R, j.nseg, st) != hipSuccess) return MP_ELAUNCH;
+  if (mpx::launch_plan(p, w, A, j.t_f64, j.W, j.R, j.nseg, st) != hipSuccess) return MP_ELAUNCH;
   mpx::Outputs o{};
   o.P[0] = P;
   o.I[0] = I;

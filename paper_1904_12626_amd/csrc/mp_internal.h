@@ -153,7 +153,8 @@ struct Outputs {
 };
 
 // ------------------------------------------------------------- launchers
-hipError_t launch_plan(const Plan &plan, const Work &w, int W, int R, int64_t nseg, hipStream_t st);
+hipError_t launch_plan(const Plan &plan, const Work &w, const void *T, bool t_f64, int W, int R, int64_t nseg,
+                       hipStream_t st);
 hipError_t launch_stats(const Plan &plan, const Work &w, const void *T, bool t_f64, bool f64_sweep,
                         int64_t total_rc, hipStream_t st);
 hipError_t launch_sweep(const Plan &plan, const Work &w, const void *T, bool t_f64, bool f64_sweep,

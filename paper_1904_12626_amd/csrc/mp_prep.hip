@@ -8,6 +8,33 @@
 
 namespace mpx {
 
+// The exponent e of the power of two 2^e that brings the spread of 32
+// evenly spaced samples of a series (their largest distance from the first
+// finite one) into [2^48, 2^49); 0 when they do not spread.  A window's
+// spread is at most about that, so the sweep's cross products (m sigma^2)
+// stay a thousand times below FP32's maximum for windows up to 2^20
+// samples, while windows up to 10^33 times smaller still keep their
+// increments above FP32's smallest normal number.
+template <typename Tin>
+__device__ int series_scale_exp(const Tin *x, int64_t n) {
+  Tin v[32];
+#pragma unroll
+  for (int k = 0; k < 32; ++k) v[k] = x[(n - 1) * k / 31];  // all in flight at once
+  double ref = 0.0, spread = 0.0;
+  bool have = false;
+#pragma unroll
+  for (int k = 0; k < 32; ++k) {
+    const double d = (double)v[k];
+    if (!isfinite(d)) continue;
+    if (!have) {
+      ref = d;
+      have = true;
+    }
+    spread = fmax(spread, fabs(d - ref));
+  }
+  return (spread > 0.0 && isfinite(spread)) ? 48 - ilogb(spread) : 0;
+}
+
 // ------------------------------------------------------------------ plan
 // Strip g of sweep s covers diagonals [k_lo + (g - seg_base) * W, +W); its
 // longest diagonal has min(l_rows, l_cols - k0) cells, cut into tiles of R
@@ -16,11 +43,21 @@ namespace mpx {
 // strip by strip; with it, every full-height tile comes first (strip by
 // strip) and the shorter last tiles of the strips after them, so that the
 // persistent grid ends on short tiles (longest first).
-__global__ void __launch_bounds__(1024) k_plan(Plan plan, Work w, int W, int R, int64_t nseg) {
+// It also sets each series' scale for the sweep's records (when the job has
+// them: w.scale).
+template <typename Tin>
+__global__ void __launch_bounds__(1024) k_plan(Plan plan, Work w, const Tin *__restrict__ Tb, int W, int R,
+                                               int64_t nseg) {
   __shared__ int64_t part[1024], part2[1024];
   const int tid = threadIdx.x;
   if (tid < 4) w.counters[tid] = 0;
-  for (int s = tid; s < plan.nseries; s += blockDim.x) w.special[s] = 0;
+  for (int s = tid; s < plan.nseries; s += blockDim.x) {
+    w.special[s] = 0;
+    if (w.scale) {
+      const SeriesDesc S = plan.series(s);
+      w.scale[s] = ldexp(1.0, series_scale_exp(series_samples(plan, Tb, S), S.n));
+    }
+  }
   const bool lpt = w.seg_part != nullptr;
 
   const int64_t per = (nseg + blockDim.x - 1) / blockDim.x;
@@ -84,8 +121,12 @@ __global__ void __launch_bounds__(1024) k_plan(Plan plan, Work w, int W, int R, 
   }
 }
 
-hipError_t launch_plan(const Plan &plan, const Work &w, int W, int R, int64_t nseg, hipStream_t st) {
-  hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, st, plan, w, W, R, nseg);
+hipError_t launch_plan(const Plan &plan, const Work &w, const void *T, bool t_f64, int W, int R, int64_t nseg,
+                       hipStream_t st) {
+  if (t_f64)
+    hipLaunchKernelGGL((k_plan<double>), dim3(1), dim3(1024), 0, st, plan, w, (const double *)T, W, R, nseg);
+  else
+    hipLaunchKernelGGL((k_plan<float>), dim3(1), dim3(1024), 0, st, plan, w, (const float *)T, W, R, nseg);
   return hipGetLastError();
 }
 
@@ -100,34 +141,11 @@ hipError_t launch_plan(const Plan &plan, const Work &w, int W, int R, int64_t ns
 // obeys C(i+1,j+1) = C(i,j) + a_j g_i + a_i g_j exactly (expand
 // x[i+m] = x[i] + a_i and mu_{i+1} = mu_i + a_i/m), and the sweep's key
 // u_i - C s_i s_j equals 1 - rho(i,j) for valid windows.
-// The records store a and g times the series' power of two k and s divided
-// by it (the sweep multiplies its seeds of C by the k of both series): no key
-// changes, since power-of-two factors commute with rounding, but the cross
-// products of series with very large or very small values stay well inside
-// FP32's range.
-
-// The power of two that brings the spread of 32 evenly spaced samples of a
-// series (their largest distance from the first finite one) into
-// [2^48, 2^49); 1 when they do not spread.  A window's spread is at most
-// about that, so its cross products (m sigma^2) stay a thousand times below
-// FP32's maximum for windows up to 2^20 samples, while windows up to 10^33
-// times smaller still keep their increments above FP32's smallest normal
-// number.  Every thread that asks gets the same value.
-template <typename Tin>
-__device__ double series_scale(const Tin *x, int64_t n) {
-  double ref = 0.0, spread = 0.0;
-  bool have = false;
-  for (int k = 0; k < 32; ++k) {
-    const double v = (double)x[(n - 1) * k / 31];
-    if (!isfinite(v)) continue;
-    if (!have) {
-      ref = v;
-      have = true;
-    }
-    spread = fmax(spread, fabs(v - ref));
-  }
-  return (spread > 0.0 && isfinite(spread)) ? ldexp(1.0, 48 - ilogb(spread)) : 1.0;
-}
+// The records store a and g times the series' power of two k (set by k_plan)
+// and s divided by it (the sweep multiplies its seeds of C by the k of both
+// series): no key changes, since power-of-two factors commute with rounding,
+// but the cross products of series with very large or very small values stay
+// well inside FP32's range.
 
 // Series owning padded row/column entry r.
 __device__ __forceinline__ int series_of_rc(const Plan &plan, int64_t r) {
@@ -151,7 +169,6 @@ template <typename F, typename Tin>
 __global__ void __launch_bounds__(256) k_stats(Plan plan, Work w, const Tin *__restrict__ Tb,
                                                int64_t total_rc) {
   __shared__ Tin xs[kStatsTile + kStatsTileM + 1];
-  __shared__ double tile_scale;
   const int64_t r0 = (int64_t)blockIdx.x * kStatsTile;
   const int64_t r = r0 + threadIdx.x;
   const int s0 = series_of_rc(plan, r0);
@@ -163,7 +180,6 @@ __global__ void __launch_bounds__(256) k_stats(Plan plan, Work w, const Tin *__r
     const int cnt = (int)min((int64_t)(kStatsTile + S0.m), S0.n - i0);
     for (int t = threadIdx.x; t < cnt; t += blockDim.x) xs[t] = base[t];
   }
-  if (tiled && threadIdx.x == 0) tile_scale = series_scale(series_samples(plan, Tb, S0), S0.n);
   __syncthreads();
   if (r >= total_rc) return;
   const int si = tiled ? s0 : series_of_rc(plan, r);
@@ -243,14 +259,13 @@ __global__ void __launch_bounds__(256) k_stats(Plan plan, Work w, const Tin *__r
   const double g = (x0 - mu) + a * ((double)(m - 1) / (2.0 * m));
   const double sc = (fin && !cst && sig > 0.0) ? 1.0 / (sqrt((double)m) * sig) : 0.0;
   const double uu = fin ? (cst ? 0.5 : 1.0) : 4.0;
-  const double k = tiled ? tile_scale : series_scale(series_samples(plan, Tb, S), S.n);
-  if (i == 0) w.scale[si] = k;
+  const double k = w.scale[si], kinv = ldexp(1.0, -ilogb(k));  // the series' power of two (k_plan)
   const int64_t wi = S.w_off + i;
   w.mu[wi] = mu;
   w.sig[wi] = sig;
   w.flags[wi] = (uint8_t)((fin ? 1 : 0) | (cst ? 2 : 0));
   w.keys[wi] = ~0ull;
-  rc[r] = FTraits<F>::make4(a * k, g * k, sc / k, uu);
+  rc[r] = FTraits<F>::make4(a * k, g * k, sc * kinv, uu);
   const int bits = (fin ? 0 : 1) | (cst ? 2 : 0);
   if (bits) atomicOr(&w.special[si], bits);
 }
