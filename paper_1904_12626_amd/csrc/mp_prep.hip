@@ -14,7 +14,8 @@ namespace mpx {
 // spread is at most about that, so the sweep's cross products (m sigma^2)
 // stay a thousand times below FP32's maximum for windows up to 2^20
 // samples, while windows up to 10^33 times smaller still keep their
-// increments above FP32's smallest normal number.
+// increments above FP32's smallest normal number.  Clamped to [-500, 500],
+// so that a scale, its inverse and the product of two stay finite.
 template <typename Tin>
 __device__ int series_scale_exp(const Tin *x, int64_t n) {
   Tin v[32];
@@ -32,7 +33,7 @@ __device__ int series_scale_exp(const Tin *x, int64_t n) {
     }
     spread = fmax(spread, fabs(d - ref));
   }
-  return (spread > 0.0 && isfinite(spread)) ? 48 - ilogb(spread) : 0;
+  return (spread > 0.0 && isfinite(spread)) ? max(-500, min(500, 48 - ilogb(spread))) : 0;
 }
 
 // ------------------------------------------------------------------ plan
