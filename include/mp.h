@@ -85,9 +85,10 @@ typedef enum {
 #define MP_PREC_F64 0    /* FP64 sweep (the reference GPU path)          */
 #define MP_PREC_F32 1    /* FP32 sweep, FP64 stats/seeds, reseeded       */
 /* The FP32 sweep carries cross products of windows in FP32; each series'
- * records are scaled by a power of two chosen from its samples, so series of
- * any magnitude that FP64 holds stay inside FP32's range (the keys are the
- * same as without the scaling). */
+ * records are scaled by a power of two (2^-500 ... 2^500) chosen from its
+ * samples, so any series whose squared window sums are finite in FP64
+ * (|T| up to about 1e150) stays inside FP32's range (the keys are the same
+ * as without the scaling). */
 
 /* flags */
 #define MP_FLAG_FP64_FINALIZE 1u  /* recompute P[i] = dist(i, I[i]) in FP64 */

@@ -282,6 +282,21 @@ def test_scale_invariance_fp32(scale):
     compare_profile(T, m, P, I, Po, Io, 1e-3 * np.sqrt(m), ez=ez, where=f"scale {scale:g}")
 
 
+@pytest.mark.parametrize("precision,tol", [("f32", 1e-3), ("f64", 1e-9)])
+@pytest.mark.parametrize("scale", [1e-150, 1e140])
+def test_magnitudes_near_the_fp64_limits(scale, precision, tol):
+    """Series whose squared window sums are still finite in FP64 (the seeds
+    and the oracle form them from raw samples).  At 1e-150 the spread of the
+    samples asks for a power of two beyond 2^500, which is clamped there; the
+    scaled records are still far inside FP32's range."""
+    T = random_walk(2500, 47, np.float64)
+    m, ez = 40, 10
+    P, I = _run(T * scale, m, ez, precision)
+    Po, Io = cimpl.selfjoin(T, m, ez)
+    compare_profile(T, m, P, I, Po, Io, tol * np.sqrt(m), ez=ez,
+                    where=f"scale {scale:g} {precision}")
+
+
 def test_regimes_of_very_different_magnitude():
     """A series whose first half moves by 1e-12 and second half by 1e10: the
     FP32 sweep's per-series power of two leaves room for both (the small
