@@ -278,17 +278,41 @@ __global__ void __launch_bounds__(64, (SweepMinWaves<F, DT>::value))
       double Sx = 0.0;
       const int vend = m + DT - 1;
       for (int vb = 0; vb < vend; vb += DT) {
+        if constexpr (std::is_same_v<F, double>) {
+          // A block's loads first, at clamped (in-bounds) addresses, so that
+          // they are in flight together (the FP64 sweep of a small join is
+          // bound by this chain's latency); samples past either end are
+          // zeroed below.  The FP32 sweeps keep the guarded loads: the same
+          // change there costs spills in their row loop.
+          Tin xs[DT], ys[DT];
 #pragma unroll
-        for (int u = 0; u < DT; ++u) {
-          const int v = vb + u;
-          double xn = 0.0;
-          if (v < m) xn = clean(ldu(Tr + v)) - mur;
-          Sx += xn;
-          xr[u] = xn;
-          const int64_t ci = c0 + v;
-          const double y = (ci < ncol) ? clean(Tc[ci]) : 0.0;
+          for (int u = 0; u < DT; ++u) {
+            xs[u] = ldu(Tr + min(vb + u, m - 1));
+            ys[u] = Tc[min(c0 + vb + u, ncol - 1)];
+          }
 #pragma unroll
-          for (int t = 0; t < DT; ++t) acc[t] = fma(xr[(u - t + DT) % DT], y, acc[t]);
+          for (int u = 0; u < DT; ++u) {
+            const int v = vb + u;
+            const double xn = (v < m) ? clean(xs[u]) - mur : 0.0;
+            Sx += xn;
+            xr[u] = xn;
+            const double y = (c0 + v < ncol) ? clean(ys[u]) : 0.0;
+#pragma unroll
+            for (int t = 0; t < DT; ++t) acc[t] = fma(xr[(u - t + DT) % DT], y, acc[t]);
+          }
+        } else {
+#pragma unroll
+          for (int u = 0; u < DT; ++u) {
+            const int v = vb + u;
+            double xn = 0.0;
+            if (v < m) xn = clean(ldu(Tr + v)) - mur;
+            Sx += xn;
+            xr[u] = xn;
+            const int64_t ci = c0 + v;
+            const double y = (ci < ncol) ? clean(Tc[ci]) : 0.0;
+#pragma unroll
+            for (int t = 0; t < DT; ++t) acc[t] = fma(xr[(u - t + DT) % DT], y, acc[t]);
+          }
         }
       }
       // the records carry each series' power of two (see k_stats)
