@@ -17,10 +17,12 @@ namespace mpx {
 // increments above FP32's smallest normal number.  Clamped to [-500, 500],
 // so that a scale, its inverse and the product of two stay finite.
 template <typename Tin>
-__device__ int series_scale_exp(const Tin *x, int64_t n) {
-  Tin v[32];
+__device__ __forceinline__ void scale_samples(const Tin *x, int64_t n, Tin (&v)[32]) {
 #pragma unroll
   for (int k = 0; k < 32; ++k) v[k] = x[(n - 1) * k / 31];  // all in flight at once
+}
+template <typename Tin>
+__device__ int scale_exp_of(const Tin (&v)[32]) {
   double ref = 0.0, spread = 0.0;
   bool have = false;
 #pragma unroll
@@ -45,18 +47,28 @@ __device__ int series_scale_exp(const Tin *x, int64_t n) {
 // strip) and the shorter last tiles of the strips after them, so that the
 // persistent grid ends on short tiles (longest first).
 // It also sets each series' scale for the sweep's records (when the job has
-// them: w.scale).
+// them: w.scale); a thread's first series has its samples loaded before the
+// table is built and its scale set after it, so that the loads' latency
+// overlaps the table.
 template <typename Tin>
 __global__ void __launch_bounds__(1024) k_plan(Plan plan, Work w, const Tin *__restrict__ Tb, int W, int R,
                                                int64_t nseg) {
-  __shared__ int64_t part[1024], part2[1024];
-  const int tid = threadIdx.x;
+  __shared__ int64_t wpart[16], wpart2[16];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   if (tid < 4) w.counters[tid] = 0;
+  const bool first = w.scale != nullptr && tid < plan.nseries;
+  Tin smp[32];
+  if (first) {
+    const SeriesDesc S = plan.series(tid);
+    scale_samples(series_samples(plan, Tb, S), S.n, smp);
+  }
   for (int s = tid; s < plan.nseries; s += blockDim.x) {
     w.special[s] = 0;
-    if (w.scale) {
+    if (w.scale && s != tid) {
       const SeriesDesc S = plan.series(s);
-      w.scale[s] = ldexp(1.0, series_scale_exp(series_samples(plan, Tb, S), S.n));
+      Tin v[32];
+      scale_samples(series_samples(plan, Tb, S), S.n, v);
+      w.scale[s] = ldexp(1.0, scale_exp_of(v));
     }
   }
   const bool lpt = w.seg_part != nullptr;
@@ -73,53 +85,84 @@ __global__ void __launch_bounds__(1024) k_plan(Plan plan, Work w, const Tin *__r
     }
     sw0 = lo;
   }
-  int sw = sw0;
-  // (full-height tiles, shorter last tile) of strip g, or (all tiles, 0)
-  auto tiles_of = [&](int64_t g, int &swi, int64_t &t2) -> int64_t {
-    while (swi + 1 < plan.nsweeps && plan.sweep(swi + 1).seg_base <= g) ++swi;
-    const SweepDesc d = plan.sweep(swi);
-    const SeriesDesc rs = plan.series(d.rs), cs = plan.series(d.cs);
-    const int64_t k0 = d.k_lo + (g - d.seg_base) * (int64_t)W;
-    const int64_t L = min(rs.l, cs.l - k0);
+  // The fields of the current sweep that a strip needs, reloaded only when
+  // the strip is in the next sweep (a thread's strips are consecutive, so
+  // mostly in one sweep): no chain of descriptor loads per strip.
+  int sw;
+  int64_t next_base, k_lo, seg_base, rl, cl;
+  auto enter = [&](int s) {
+    sw = s;
+    const SweepDesc d = plan.sweep(s);
+    next_base = s + 1 < plan.nsweeps ? plan.sweep(s + 1).seg_base : INT64_MAX;
+    k_lo = d.k_lo;
+    seg_base = d.seg_base;
+    rl = plan.series(d.rs).l;
+    cl = plan.series(d.cs).l;
+  };
+  // (full-height tiles, shorter last tile) of strip g, or (all tiles, 0);
+  // a 32-bit division when the strip's length allows (64-bit division is a
+  // long software sequence)
+  auto tiles_of = [&](int64_t g, int64_t &t2) -> int64_t {
+    while (next_base <= g) enter(sw + 1);
+    const int64_t k0 = k_lo + (g - seg_base) * (int64_t)W;
+    const int64_t L = min(rl, cl - k0);
+    int64_t q;
+    if (L >= 0 && L <= 0x7fffffff) {
+      q = (int64_t)((uint32_t)L / (uint32_t)R);
+    } else {
+      q = L / R;
+    }
+    const bool part_tile = L - q * R != 0;
     if (!lpt) {
       t2 = 0;
-      return (L + R - 1) / R;
+      return q + (part_tile ? 1 : 0);
     }
-    t2 = (L % R) != 0 ? 1 : 0;
-    return L / R;
+    t2 = part_tile ? 1 : 0;
+    return q;
   };
   int64_t sum = 0, sum2 = 0;
+  if (a < b) enter(sw0);
   for (int64_t g = a; g < b; ++g) {
     int64_t t2;
-    sum += tiles_of(g, sw, t2);
+    sum += tiles_of(g, t2);
     sum2 += t2;
   }
-  // inclusive scan over the threads (log-step, in LDS), then exclusive
-  part[tid] = sum;
-  part2[tid] = sum2;
+  // inclusive scan over the threads: within each wave by shuffles, then
+  // the totals of the waves before it (16 waves of 64), then exclusive
+  int64_t x = sum, x2 = sum2;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int64_t y = __shfl_up(x, d, 64), y2 = __shfl_up(x2, d, 64);
+    if (lane >= d) {
+      x += y;
+      x2 += y2;
+    }
+  }
+  if (lane == 63) {
+    wpart[wv] = x;
+    wpart2[wv] = x2;
+  }
   __syncthreads();
-  for (int d = 1; d < (int)blockDim.x; d <<= 1) {
-    const int64_t a1 = tid >= d ? part[tid - d] : 0, a2 = tid >= d ? part2[tid - d] : 0;
-    __syncthreads();
-    part[tid] += a1;
-    part2[tid] += a2;
-    __syncthreads();
+  for (int k = 0; k < wv; ++k) {
+    x += wpart[k];
+    x2 += wpart2[k];
   }
   if (tid == (int)blockDim.x - 1) {
-    w.seg_prefix[nseg] = part[tid];
-    if (lpt) w.seg_part[nseg] = part2[tid];
+    w.seg_prefix[nseg] = x;
+    if (lpt) w.seg_part[nseg] = x2;
   }
-  int64_t run = part[tid] - sum, run2 = part2[tid] - sum2;
-  sw = sw0;
+  int64_t run = x - sum, run2 = x2 - sum2;
+  if (a < b) enter(sw0);
   for (int64_t g = a; g < b; ++g) {
     int64_t t2;
-    const int64_t t = tiles_of(g, sw, t2);
+    const int64_t t = tiles_of(g, t2);
     w.seg_prefix[g] = run;
     w.seg_sweep[g] = sw;
     if (lpt) w.seg_part[g] = run2;
     run += t;
     run2 += t2;
   }
+  if (first) w.scale[tid] = ldexp(1.0, scale_exp_of(smp));
 }
 
 hipError_t launch_plan(const Plan &plan, const Work &w, const void *T, bool t_f64, int W, int R, int64_t nseg,
