@@ -97,3 +97,25 @@ def test_batch_of_series_at_different_magnitudes():
     for s, (T, m, ez) in enumerate(zip(Ts, ms, ezs)):
         Po, Io = cimpl.selfjoin(T, m, ez)
         compare_profile(T, m, Ps[s], Is[s], Po, Io, 1e-3 * np.sqrt(m), ez=ez, where=f"series {s}")
+
+
+def test_batch_of_more_series_than_plan_threads():
+    """1100 series, more than the plan kernel's 1024 threads, so that some
+    threads set a second series' power of two.  Magnitudes cycle through
+    1e-25 (whose FP32 cross products would underflow unscaled), 1 and 1e19,
+    and every series is checked against the oracle."""
+    import paper_1904_12626_amd as mpx
+    from workloads import random_walk
+    ns = 1100
+    scales = [1e-25, 1.0, 1e19]
+    lens = [150 + (k % 7) * 10 for k in range(ns)]
+    Ts = [random_walk(n, 1000 + k, np.float64) for k, n in enumerate(lens)]
+    m, ez = 16, 4
+    plan = mpx.BatchPlan(lens, [m] * ns, [ez] * ns, dtype=torch.float64, device=DEV)
+    Tcat = np.concatenate([T * scales[k % 3] for k, T in enumerate(Ts)])
+    P, I = plan.run(torch.from_numpy(Tcat).to(DEV))
+    torch.cuda.synchronize()
+    Ps, Is = plan.split(P.cpu().numpy()), plan.split(I.cpu().numpy())
+    for s, T in enumerate(Ts):
+        Po, Io = cimpl.selfjoin(T, m, ez)
+        compare_profile(T, m, Ps[s], Is[s], Po, Io, 1e-3 * np.sqrt(m), ez=ez, where=f"series {s}")
